@@ -1,0 +1,135 @@
+"""Pins of the oracle's Tamm-Dancoff matrix (Eq. 1), dipoles and absorption
+(Eq. 7) against closed forms for Gaussian orbitals, whose pair products are
+Gaussian charges with analytic periodic Coulomb integrals."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.grid import Grid
+from oracle import bse
+
+S = 1.2          # orbital width (bohr)
+N, H = 60, 0.4   # box 24 bohr: orbital tails at the boundary < 1e-9
+
+
+def _orbital(grid, R):
+    xs = grid.coords()
+    box = grid.shape[0] * grid.h
+    out = np.zeros(grid.shape)
+    nrm = (math.pi * S ** 2) ** -0.75
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for c in (-1, 0, 1):
+                dx = xs[0] - R[0] - a * box
+                dy = xs[1] - R[1] - b * box
+                dz = xs[2] - R[2] - c * box
+                out += nrm * np.exp(-(dx[:, None, None] ** 2 + dy[None, :, None] ** 2
+                                      + dz[None, None, :] ** 2) / (2 * S ** 2))
+    return out
+
+
+def _pair(R1, R2):
+    """phi_1 phi_2 = Q g_sigma(r - M): charge, centre, width."""
+    R1, R2 = np.asarray(R1), np.asarray(R2)
+    d2 = np.sum((R1 - R2) ** 2)
+    return math.exp(-d2 / (4 * S ** 2)), 0.5 * (R1 + R2), S / math.sqrt(2)
+
+
+def _coulomb(p1, p2, box):
+    """Periodic Coulomb integral of two Gaussian charges, k = 0 removed:
+    (1/Omega) sum_{G != 0} 4 pi/G^2 Q1 Q2 exp(-G^2 (s1^2 + s2^2)/2) cos(G.(M1 - M2))."""
+    (Q1, M1, s1), (Q2, M2, s2) = p1, p2
+    mmax = 28      # exp(-G^2 (s1^2+s2^2)/2) < 1e-14 beyond
+    m = np.arange(-mmax, mmax + 1)
+    G1 = 2 * math.pi * m / box
+    Gx, Gy, Gz = np.meshgrid(G1, G1, G1, indexing="ij")
+    G2 = Gx ** 2 + Gy ** 2 + Gz ** 2
+    msk = G2 > 0
+    d = M1 - M2
+    ph = Gx[msk] * d[0] + Gy[msk] * d[1] + Gz[msk] * d[2]
+    val = np.sum(4 * math.pi / G2[msk] * np.exp(-G2[msk] * (s1 ** 2 + s2 ** 2) / 2) * np.cos(ph))
+    return Q1 * Q2 * val / box ** 3
+
+
+@pytest.fixture(scope="module")
+def gauss():
+    grid = Grid((N, N, N), H)
+    c = N * H / 2
+    Rv = [(c - 0.7, c + 0.2, c), (c + 0.4, c - 0.5, c + 0.6)]
+    Rc = [(c + 1.1, c + 0.9, c - 0.4), (c - 0.9, c - 1.0, c + 0.3), (c, c + 1.3, c + 1.0)]
+    phv = np.stack([_orbital(grid, R) for R in Rv])
+    phc = np.stack([_orbital(grid, R) for R in Rc])
+    return grid, Rv, Rc, phv, phc
+
+
+def test_exchange_closed_form(gauss):
+    grid, Rv, Rc, phv, phc = gauss
+    X = bse.exchange(grid, phv, phc)
+    box = N * H
+    nc = len(Rc)
+    for i in range(2):
+        for a in range(nc):
+            for j in range(2):
+                for b in range(nc):
+                    ref = _coulomb(_pair(Rv[i], Rc[a]), _pair(Rv[j], Rc[b]), box)
+                    assert abs(X[i * nc + a, j * nc + b] - ref) < 1e-8 * abs(ref) + 1e-12
+
+
+def test_direct_and_assembly_with_bare_coulomb(gauss):
+    """P10: with W^pol = 0 the direct term is the bare (ab|v|ij) and A is
+    diag + 2 (ia|jb) - (ab|v|ij) in the (i, a) row order."""
+    grid, Rv, Rc, phv, phc = gauss
+    box = N * H
+    nc = len(Rc)
+    w_full = np.zeros((2, 2) + grid.shape)
+    for i in range(2):
+        for j in range(2):
+            w_full[i, j] = grid.poisson(phv[i] * phv[j])
+    D = bse.direct(grid, phc, w_full)
+    ev = np.array([-0.5, -0.3])
+    ec = np.array([0.1, 0.25, 0.4])
+    A = bse.build_a(grid, phv, phc, ev, ec, w_full, scissors=0.05)
+    for i in range(2):
+        for a in range(nc):
+            for j in range(2):
+                for b in range(nc):
+                    dref = _coulomb(_pair(Rc[a], Rc[b]), _pair(Rv[i], Rv[j]), box)
+                    xref = _coulomb(_pair(Rv[i], Rc[a]), _pair(Rv[j], Rc[b]), box)
+                    assert abs(D[i * nc + a, j * nc + b] - dref) < 1e-8 * abs(dref) + 1e-12
+                    diag = (ec[a] - ev[i] + 0.05) if (i == j and a == b) else 0.0
+                    aref = diag + 2 * xref - dref
+                    assert abs(A[i * nc + a, j * nc + b] - aref) < 1e-8
+    assert np.abs(A - A.T).max() < 1e-12
+
+
+def test_dipoles_closed_form(gauss):
+    grid, Rv, Rc, phv, phc = gauss
+    f0 = bse.dipoles(grid, phv, phc)
+    c = N * H / 2
+    nc = len(Rc)
+    for i in range(2):
+        for a in range(nc):
+            Q, M, _ = _pair(Rv[i], Rc[a])
+            assert np.allclose(f0[i * nc + a], Q * (M - c), atol=1e-9)
+
+
+def test_excitons_uncoupled_and_absorption_sum():
+    rng = np.random.default_rng(0)
+    d = np.array([0.5, 0.2, 0.9, 0.35])
+    f0 = rng.standard_normal((4, 3))
+    om, dip2 = bse.excitons(np.diag(d), f0, 3)
+    order = np.argsort(d)[:3]
+    assert np.allclose(om, d[order])
+    assert np.allclose(dip2, f0[order] ** 2)
+    # a coupled A: the oscillator strengths of all excitons add up to |f0|^2
+    Q, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    A = Q @ np.diag(d) @ Q.T
+    om, dip2 = bse.excitons(A, f0, 4)
+    assert np.allclose(dip2.sum(axis=0), (f0 ** 2).sum(axis=0))
+    # sigma(omega)/omega integrates to the summed strengths
+    wg = np.linspace(-1, 3, 40001)
+    sig = bse.absorption(om, dip2, wg, 0.02)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        integ = np.trapezoid(np.where(wg != 0, sig / wg, 0.0), wg)
+    assert abs(integ - dip2.sum()) < 1e-6 * dip2.sum()
