@@ -1,0 +1,148 @@
+/* libbse: MI355X (gfx950) hot path of stochastic-W Bethe-Salpeter spectra.
+ *
+ * The method (Method section of the paper, "Stochastic evaluation of the
+ * action of W" and Eqs. 1, 7, 10-15):
+ *   - a closed-shell system with 2 N_occ electrons described by eigenstates
+ *     phi_s, eps_s of a zero-order Hamiltonian H0 = -1/2 Lap + V_ext on a
+ *     periodic real-space grid;
+ *   - the action of the static screened interaction on a pair density,
+ *     W_ij(r) = q_ij(r) + W^pol_ij(r), q_ij = v[phi_i phi_j], obtained by a
+ *     linear-response time-dependent Hartree propagation of L random-sign
+ *     stochastic occupied orbitals (Eq. 14) kicked by q_ij, cleaned of
+ *     occupied-space amplitude every M steps (Eq. 15), with the induced
+ *     Coulomb potential integrated under a Gaussian damping (Eq. 13);
+ *   - the Tamm-Dancoff matrix A(ia;jb) = (eps_a - eps_i + Delta) d_ij d_ab
+ *     + 2 (ia|jb) - (phi_a phi_b|W|phi_i phi_j) (Eq. 1), and its lowest
+ *     excitons with dipole oscillator strengths (Eq. 7).
+ *
+ * Conventions
+ *   - Grid: cubic n x n x n, spacing h (bohr), periodic, row-major with z
+ *     fastest; grid point (i,j,k) sits at (i h, j h, k h).  Integrals are
+ *     sums times h^3.  Supported n: 16, 24, 32, 48, 64 and 112 (FP64 mode:
+ *     up to 64).
+ *   - Orbitals: real, sum_r |phi|^2 h^3 = 1, ascending eps; orbitals
+ *     0..n_occ-1 are occupied.  Units: Hartree atomic units.
+ *   - The Coulomb kernel is periodic, 4 pi/|k|^2 with k = 0 removed.
+ *   - The propagation is the exact linearisation (alpha -> 0) of the
+ *     paper's finite-alpha kick exp(-i alpha q); Strang split-operator steps
+ *     of dt; trapezoid time weights on t_n = n dt up to T = n_steps dt.
+ *
+ * Ownership: the library copies every host input; the caller allocates
+ * every output.  Device variants borrow caller device memory and are
+ * ordered on the stream given to bse_set_stream (default: the null stream).
+ *
+ * Errors: no exception crosses this interface.  Every call returns a
+ * bse_status; on an argument error nothing is written.  bse_last_error()
+ * gives a thread-local message for the last failing call.  A system
+ * handle must not be used by two threads at once.
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bse_system bse_system; /* opaque; owns all device memory */
+
+typedef enum {
+  BSE_OK = 0,
+  BSE_ERR_ARG = -1,     /* invalid argument; nothing written */
+  BSE_ERR_STATE = -2,   /* call out of order (e.g. apply_W before set_orbitals) */
+  BSE_ERR_OOM = -3,     /* device allocation failed */
+  BSE_ERR_DEVICE = -4,  /* HIP runtime error */
+  BSE_ERR_NUMERIC = -5  /* non-finite result for some pair (see pair_status) */
+} bse_status;
+
+enum { BSE_FP64 = 0, BSE_MIXED = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;   /* grid points per axis (must be equal)                    */
+  double h;             /* grid spacing, bohr                                      */
+  int32_t n_occ;        /* occupied orbitals (2 n_occ electrons)                   */
+  int32_t n_stoch;      /* L stochastic orbitals (Eq. 14); 0 = deterministic, all
+                           n_occ occupied orbitals are propagated                  */
+  uint64_t seed;        /* SplitMix64 seed of the signs unless bse_set_signs       */
+  double dt;            /* time step, a.u.                                         */
+  int32_t n_steps;      /* N; T = N dt                                             */
+  double gamma;         /* Gaussian damping width of Eq. 13, Hartree               */
+  int32_t clean_every;  /* M of Eq. 15 (also cleans at t = 0); 0 = never           */
+  double alpha;         /* must be 0 (linearised kick)                             */
+  double scissors;      /* Delta of Eq. 1, Hartree                                 */
+  int32_t precision;    /* BSE_FP64: every step in FP64.  BSE_MIXED: propagation
+                           and cleaning in FP32, source potentials, the time
+                           integral and all outputs in FP64                        */
+  int32_t device;       /* HIP device ordinal                                      */
+  int32_t max_batch;    /* pairs propagated together (memory bound); >= 1          */
+} bse_config;
+
+/* Create a system from V_ext[nx*ny*nz] (host, FP64).  *out receives the
+ * handle.  Allocates the device tables of the grid. */
+bse_status bse_create_system(const bse_config* cfg, const double* v_ext, bse_system** out);
+
+/* Orbitals phi[n_orb][nx*ny*nz] (host, FP64, h^3-normalised) and
+ * eigenvalues eps[n_orb] (host, FP64, ascending).  n_orb >= n_occ; the
+ * A matrix needs n_orb >= n_occ + n_c.  Builds the stochastic orbitals and
+ * propagates the unperturbed set once (its trajectory is shared by every
+ * pair).  Replaces earlier orbitals. */
+bse_status bse_set_orbitals(bse_system* sys, int32_t n_orb, const double* phi, const double* eps);
+
+/* Explicit signs xi[n_stoch][n_occ] (host, +-1) of Eq. 14, replacing the
+ * ones drawn from cfg.seed.  Call before bse_set_orbitals. */
+bse_status bse_set_signs(bse_system* sys, int32_t n_stoch, int32_t n_occ, const int8_t* xi);
+
+/* W-action on n_pairs pair densities phi_p phi_q, pq[n_pairs][2] (host).
+ * w_out[n_pairs][ng] (host, FP64) receives W_pq = q_pq + W^pol_pq;
+ * wpol_out (nullable) receives W^pol_pq; pair_status (nullable,
+ * [n_pairs]) receives 0 or BSE_ERR_NUMERIC per pair (non-finite rows are
+ * NaN-filled and the call returns BSE_ERR_NUMERIC after finishing every
+ * other pair). */
+bse_status bse_apply_W(bse_system* sys, int32_t n_pairs, const int32_t* pq, double* w_out,
+                       double* wpol_out, int32_t* pair_status);
+
+/* Device variant: pq on the host, w_dev[n_pairs][ng] (device, FP64) and
+ * wpol_dev (device, FP64, nullable) borrowed from the caller; stream-
+ * ordered on the bse_set_stream stream; returns after enqueueing. */
+bse_status bse_apply_W_device(bse_system* sys, int32_t n_pairs, const int32_t* pq, void* w_dev,
+                              void* wpol_dev);
+
+/* Tamm-Dancoff matrix (Eq. 1) for the highest n_o occupied and lowest n_c
+ * virtual orbitals: A[(n_o n_c)^2] (host, FP64, row-major), row index
+ * (i - (n_occ - n_o)) * n_c + (a - n_occ).  Propagates the n_o(n_o+1)/2
+ * valence pairs, keeps their W_ij on the device for bse_spectrum. */
+bse_status bse_build_A(bse_system* sys, int32_t n_o, int32_t n_c, double* A);
+
+/* Lowest n_exc excitons of the last A (Lanczos in FP64 on the device):
+ * omega[n_exc] (Hartree), dip2[n_exc][3] = |<X_n|f0_axis>|^2 with
+ * f0_ia = <phi_a| r_axis - box centre |phi_i>, and, if n_w > 0, the
+ * absorption sigma[n_w] = w sum_n sum_axis dip2 g(w - omega_n) on
+ * w_grid[n_w], g a normalised Gaussian of standard deviation sigma_broad
+ * (Eq. 7). */
+bse_status bse_spectrum(bse_system* sys, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
+                        const double* w_grid, double sigma_broad, double* sigma);
+
+/* Stream for all later device work of this system (a hipStream_t). */
+bse_status bse_set_stream(bse_system* sys, void* hip_stream);
+
+/* Signs of Eq. 14 drawn from SplitMix64 (host only, no device needed):
+ * xi[l][s] = +1 if the top bit of draw l*n_occ + s is 0, else -1. */
+bse_status bse_generate_signs(uint64_t seed, int32_t n_stoch, int32_t n_occ, int8_t* xi);
+
+/* Per-kernel timing of the last bse_apply_W / bse_apply_W_device call:
+ * names[k] and avg_ms[k], calls[k] for up to cap entries; returns the
+ * number of kernels timed (0 unless timing was enabled). */
+int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, double* avg_ms,
+                         int32_t* calls);
+/* Enable per-kernel HIP-event timing (adds synchronisation-free events). */
+bse_status bse_set_timing(bse_system* sys, int32_t enable);
+
+const char* bse_last_error(void);
+const char* bse_version(void);
+void bse_destroy_system(bse_system* sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSE_H */

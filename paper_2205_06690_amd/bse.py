@@ -1,0 +1,185 @@
+"""ctypes binding of libbse (include/bse.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module copies
+numpy arrays in and out, or passes device pointers of torch tensors for the
+device variants.  Importing it raises if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbse.so")
+
+BSE_OK, BSE_ERR_ARG, BSE_ERR_STATE, BSE_ERR_OOM, BSE_ERR_DEVICE, BSE_ERR_NUMERIC = 0, -1, -2, -3, -4, -5
+BSE_FP64, BSE_MIXED = 0, 1
+
+# every symbol declared in include/bse.h
+EXPORTS = (
+    "bse_create_system", "bse_set_orbitals", "bse_set_signs", "bse_apply_W",
+    "bse_apply_W_device", "bse_build_A", "bse_spectrum", "bse_set_stream",
+    "bse_generate_signs", "bse_kernel_times", "bse_set_timing", "bse_last_error",
+    "bse_version", "bse_destroy_system",
+)
+
+
+class BseConfig(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+        ("n_occ", C.c_int32), ("n_stoch", C.c_int32), ("seed", C.c_uint64),
+        ("dt", C.c_double), ("n_steps", C.c_int32), ("gamma", C.c_double),
+        ("clean_every", C.c_int32), ("alpha", C.c_double), ("scissors", C.c_double),
+        ("precision", C.c_int32), ("device", C.c_int32), ("max_batch", C.c_int32),
+    ]
+
+
+class BseError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libbse error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libbse is not built ({_LIB_PATH} missing); run "
+                          "python -m paper_2205_06690_amd.build")
+    lib = C.CDLL(_LIB_PATH)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    lib.bse_create_system.argtypes = [C.POINTER(BseConfig), dp, C.POINTER(P)]
+    lib.bse_set_orbitals.argtypes = [P, C.c_int32, dp, dp]
+    lib.bse_set_signs.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
+    lib.bse_apply_W.argtypes = [P, C.c_int32, ip, dp, dp, ip]
+    lib.bse_apply_W_device.argtypes = [P, C.c_int32, ip, P, P]
+    lib.bse_build_A.argtypes = [P, C.c_int32, C.c_int32, dp]
+    lib.bse_spectrum.argtypes = [P, C.c_int32, dp, dp, C.c_int32, dp, C.c_double, dp]
+    lib.bse_set_stream.argtypes = [P, P]
+    lib.bse_generate_signs.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
+    lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
+    lib.bse_kernel_times.restype = C.c_int32
+    lib.bse_set_timing.argtypes = [P, C.c_int32]
+    lib.bse_last_error.restype = C.c_char_p
+    lib.bse_version.restype = C.c_char_p
+    lib.bse_destroy_system.argtypes = [P]
+    lib.bse_destroy_system.restype = None
+    for name in EXPORTS:
+        getattr(lib, name)
+    return lib
+
+
+LIB = _load()
+
+
+def _check(rc: int):
+    if rc != BSE_OK:
+        raise BseError(rc, LIB.bse_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def generate_signs(seed: int, n_stoch: int, n_occ: int) -> np.ndarray:
+    xi = np.empty((n_stoch, n_occ), dtype=np.int8)
+    _check(LIB.bse_generate_signs(seed, n_stoch, n_occ, xi.ctypes.data_as(C.POINTER(C.c_int8))))
+    return xi
+
+
+class System:
+    """One periodic system on one device (a bse_system handle)."""
+
+    def __init__(self, n: int, h: float, v_ext: np.ndarray, *, n_occ: int, n_stoch: int = 10,
+                 seed: int = 0, dt: float = 0.05, n_steps: int = 200, gamma: float = 0.5,
+                 clean_every: int = 10, scissors: float = 0.0, precision: int = BSE_MIXED,
+                 device: int = 0, max_batch: int = 16):
+        cfg = BseConfig(n, n, n, h, n_occ, n_stoch, seed, dt, n_steps, gamma, clean_every,
+                        0.0, scissors, precision, device, max_batch)
+        self.cfg = cfg
+        self.n = n
+        self.ng = n ** 3
+        v = np.ascontiguousarray(v_ext, dtype=np.float64).reshape(-1)
+        if v.size != self.ng:
+            raise ValueError("v_ext size does not match the grid")
+        h_ = C.c_void_p()
+        _check(LIB.bse_create_system(C.byref(cfg), _dptr(v), C.byref(h_)))
+        self._h = h_
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.bse_destroy_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_signs(self, xi: np.ndarray):
+        x = np.ascontiguousarray(xi, dtype=np.int8)
+        _check(LIB.bse_set_signs(self._h, x.shape[0], x.shape[1], x.ctypes.data_as(C.POINTER(C.c_int8))))
+
+    def set_orbitals(self, phi: np.ndarray, eps: np.ndarray):
+        p = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, self.ng)
+        e = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1)
+        if e.size != p.shape[0]:
+            raise ValueError("eps and phi disagree on the orbital count")
+        _check(LIB.bse_set_orbitals(self._h, p.shape[0], _dptr(p), _dptr(e)))
+
+    def set_stream(self, stream_ptr: int):
+        _check(LIB.bse_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def apply_w(self, pairs, want_wpol: bool = False, return_status: bool = False):
+        pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        B = pq.shape[0]
+        w = np.empty((B, self.ng))
+        wp = np.empty((B, self.ng)) if want_wpol else None
+        st = np.zeros(B, dtype=np.int32)
+        rc = LIB.bse_apply_W(self._h, B, _iptr(pq), _dptr(w), _dptr(wp) if wp is not None else None,
+                             _iptr(st))
+        if rc != BSE_OK and not (return_status and rc == BSE_ERR_NUMERIC):
+            _check(rc)
+        out = (w, wp) if want_wpol else (w,)
+        if return_status:
+            out = out + (st,)
+        return out if len(out) > 1 else out[0]
+
+    def apply_w_device(self, pairs, w_dev_ptr: int, wpol_dev_ptr: Optional[int] = None):
+        pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        _check(LIB.bse_apply_W_device(self._h, pq.shape[0], _iptr(pq), C.c_void_p(w_dev_ptr),
+                                      C.c_void_p(wpol_dev_ptr) if wpol_dev_ptr else None))
+
+    def build_a(self, n_o: int, n_c: int) -> np.ndarray:
+        A = np.empty((n_o * n_c, n_o * n_c))
+        _check(LIB.bse_build_A(self._h, n_o, n_c, _dptr(A)))
+        return A
+
+    def spectrum(self, n_exc: int, w_grid=None, sigma: float = 0.08 / 27.211386245988):
+        om = np.empty(n_exc)
+        d2 = np.empty((n_exc, 3))
+        if w_grid is None:
+            _check(LIB.bse_spectrum(self._h, n_exc, _dptr(om), _dptr(d2), 0, None, sigma, None))
+            return om, d2
+        wg = np.ascontiguousarray(w_grid, dtype=np.float64)
+        sg = np.empty(wg.size)
+        _check(LIB.bse_spectrum(self._h, n_exc, _dptr(om), _dptr(d2), wg.size, _dptr(wg), sigma,
+                                _dptr(sg)))
+        return om, d2, sg
+
+    def set_timing(self, on: bool = True):
+        _check(LIB.bse_set_timing(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        cap = 32
+        names = (C.c_char_p * cap)()
+        avg = np.zeros(cap)
+        calls = np.zeros(cap, dtype=np.int32)
+        k = LIB.bse_kernel_times(self._h, cap, names, _dptr(avg), _iptr(calls))
+        if k < 0:
+            raise BseError(BSE_ERR_DEVICE, LIB.bse_last_error().decode())
+        return {names[i].decode(): (float(avg[i]), int(calls[i])) for i in range(k)}

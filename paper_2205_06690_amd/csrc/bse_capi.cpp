@@ -1,0 +1,676 @@
+// C-ABI of libbse: system state, batching of pair propagations, and the
+// orchestration of the kernels in prop_kernels.hip / bse_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bse.h"
+#include "bse_kernels.h"
+#include "prop_kernels.h"
+
+using namespace bse;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  bse_status st;
+};
+
+void fail(bse_status st, const std::string& msg) {
+  g_err = msg;
+  throw Fail{st};
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      fail(BSE_ERR_OOM, std::string(what) + ": " + hipGetErrorString(e));
+    fail(BSE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HIPC(x) hip_check((x), #x)
+
+// device buffer with RAII
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void alloc(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) return;
+    HIPC(hipMalloc(&p, n));
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DBuf() { release(); }
+  template <typename X> X* as() const { return reinterpret_cast<X*>(p); }
+};
+
+uint64_t splitmix64_draw(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+struct Timer {
+  struct Rec {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+  };
+  bool on = false;
+  std::map<std::string, Rec> recs;
+  std::vector<std::string> order;
+  hipStream_t st = nullptr;
+  std::pair<hipEvent_t, hipEvent_t>* begin(const char* name) {
+    if (!on) return nullptr;
+    auto it = recs.find(name);
+    if (it == recs.end()) {
+      order.push_back(name);
+      it = recs.emplace(name, Rec{}).first;
+    }
+    Rec& r = it->second;
+    if (r.used == r.ev.size()) {
+      hipEvent_t a, b;
+      HIPC(hipEventCreate(&a));
+      HIPC(hipEventCreate(&b));
+      r.ev.push_back({a, b});
+    }
+    auto* p = &r.ev[r.used++];
+    HIPC(hipEventRecord(p->first, st));
+    return p;
+  }
+  void end(std::pair<hipEvent_t, hipEvent_t>* p) {
+    if (p) HIPC(hipEventRecord(p->second, st));
+  }
+  void reset() {
+    for (auto& kv : recs) kv.second.used = 0;
+  }
+  ~Timer() {
+    for (auto& kv : recs)
+      for (auto& e : kv.second.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
+};
+
+struct Tables {
+  DBuf tw, kph, pf, ph, k2;
+};
+
+}  // namespace
+
+struct bse_system {
+  bse_config cfg{};
+  int n = 0;
+  size_t ng = 0;
+  double dv = 0;
+  hipStream_t stream = nullptr;
+  int L = 0;
+  bool deterministic = false;
+  std::vector<double> vext;
+  Tables tf;
+  Tables td;
+  // orbitals
+  int n_orb = 0;
+  std::vector<double> eps;
+  DBuf phi64;     // [n_orb][ng] FP64
+  DBuf phi_occ32; // [n_occ][ng] FP32 (mixed)
+  std::vector<int8_t> xi;
+  bool signs_given = false;
+  DBuf xi_d;
+  DBuf eta0;      // [L][ng] FP64
+  DBuf hist;      // [(N+1)][L][ng] complex T
+  DBuf n0;        // [L]
+  bool ready = false;
+  // batch workspace
+  int cap_b = 0;
+  DBuf d, u, dens, wpol, q, rho64, work, work64, part, coef, coefE, E, pq_d, flags;
+  int nchunk = 0;
+  // A / spectrum state
+  int a_no = 0, a_nc = 0;
+  DBuf wij;       // [n_ij][ng] FP64
+  std::vector<double> A;
+  Timer timer;
+  std::vector<double> wts;
+};
+
+namespace {
+
+int wsize(const bse_system* s) { return s->cfg.precision == BSE_FP64 ? 8 : 4; }
+
+template <typename T>
+void upload_tables(bse_system* s, Tables& tb) {
+  using C = cplx<T>;
+  const int n = s->n;
+  const double h = s->cfg.h, dt = s->cfg.dt;
+  std::vector<C> tw(n), kph(n);
+  std::vector<T> k2(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * m / n;
+    tw[m].x = (T)std::cos(a);
+    tw[m].y = (T)std::sin(a);
+    const int mm = (m < (n + 1) / 2) ? m : m - n;  // fftfreq ordering, Nyquist negative
+    const double k = 2.0 * M_PI * mm / (n * h);
+    k2[m] = (T)(k * k);
+    const double ph = -0.5 * k * k * dt;
+    kph[m].x = (T)(std::cos(ph) / n);
+    kph[m].y = (T)(std::sin(ph) / n);
+  }
+  std::vector<C> pf(s->ng), phh(s->ng);
+  for (size_t i = 0; i < s->ng; ++i) {
+    const double v = s->vext[i];
+    pf[i].x = (T)std::cos(-v * dt);
+    pf[i].y = (T)std::sin(-v * dt);
+    phh[i].x = (T)std::cos(-0.5 * v * dt);
+    phh[i].y = (T)std::sin(-0.5 * v * dt);
+  }
+  tb.tw.alloc(sizeof(C) * n);
+  tb.kph.alloc(sizeof(C) * n);
+  tb.k2.alloc(sizeof(T) * n);
+  tb.pf.alloc(sizeof(C) * s->ng);
+  tb.ph.alloc(sizeof(C) * s->ng);
+  HIPC(hipMemcpy(tb.tw.p, tw.data(), sizeof(C) * n, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(tb.kph.p, kph.data(), sizeof(C) * n, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(tb.k2.p, k2.data(), sizeof(T) * n, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(tb.pf.p, pf.data(), sizeof(C) * s->ng, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(tb.ph.p, phh.data(), sizeof(C) * s->ng, hipMemcpyHostToDevice));
+}
+
+template <typename T> Tables& tabs(bse_system* s);
+template <> Tables& tabs<float>(bse_system* s) { return s->tf; }
+template <> Tables& tabs<double>(bse_system* s) { return s->td; }
+
+// Coulomb potential of B real FP64 densities (rho64) into q (FP64)
+void poisson64(bse_system* s, const double* rho, int B, double* out, double* acc, double wn) {
+  const size_t need = sizeof(cplx<double>) * s->ng * (size_t)((B + 1) / 2);
+  s->work64.alloc(need);
+  PoisArgs<double> a{};
+  a.rho = rho;
+  a.B = B;
+  a.work = s->work64.as<cplx<double>>();
+  a.tw = s->td.tw.as<cplx<double>>();
+  a.k2 = s->td.k2.as<double>();
+  a.vscale = 4.0 * M_PI / (double)s->ng;
+  a.out64 = out;
+  a.acc = acc;
+  a.wn = wn;
+  HIPC(launch_poisson<double>(s->n, a, s->stream));
+}
+
+template <typename T>
+void ensure_batch(bse_system* s, int B) {
+  using C = cplx<T>;
+  if (B <= s->cap_b) return;
+  const size_t ng = s->ng;
+  const int L = s->L;
+  const int S = s->cfg.n_occ;
+  s->d.alloc(sizeof(C) * ng * (size_t)B * L);
+  s->u.alloc(sizeof(T) * ng * B);
+  s->dens.alloc(sizeof(T) * ng * B);
+  s->wpol.alloc(sizeof(double) * ng * B);
+  s->q.alloc(sizeof(double) * ng * B);
+  s->rho64.alloc(sizeof(double) * ng * B);
+  s->work.alloc(sizeof(C) * ng * (size_t)((B + 1) / 2));
+  s->E.alloc(sizeof(C) * ng * L);
+  const int chunk = 4096;
+  s->nchunk = (int)((ng + chunk - 1) / chunk);
+  const int F = B * L;
+  s->part.alloc(sizeof(cplx<double>) * (size_t)s->nchunk * std::max(F, L) * (S + 1));
+  s->coef.alloc(sizeof(cplx<double>) * (size_t)F * (S + 1));
+  s->coefE.alloc(sizeof(cplx<double>) * (size_t)L * (S + 1));
+  s->pq_d.alloc(sizeof(int) * 2 * B);
+  s->flags.alloc(sizeof(int) * B);
+  s->cap_b = B;
+}
+
+template <typename T>
+const T* occ_phi(bse_system* s);
+template <> const float* occ_phi<float>(bse_system* s) { return s->phi_occ32.as<float>(); }
+template <> const double* occ_phi<double>(bse_system* s) { return s->phi64.as<double>(); }
+
+template <typename T>
+void clean(bse_system* s, int B, int from_mid, const cplx<T>* H) {
+  Tables& tb = tabs<T>(s);
+  CleanArgs<T> c{};
+  c.d = s->d.as<cplx<T>>();
+  c.F = B * s->L;
+  c.L = s->L;
+  c.S = s->cfg.n_occ;
+  c.u = s->u.as<T>();
+  c.H = H;
+  c.ph = tb.ph.as<cplx<T>>();
+  c.E = s->E.as<cplx<T>>();
+  c.phi = occ_phi<T>(s);
+  c.ng = s->ng;
+  c.dt = (T)s->cfg.dt;
+  c.from_mid = from_mid;
+  c.chunk = 4096;
+  c.part = s->part.as<cplx<double>>();
+  c.coef = s->coef.as<cplx<double>>();
+  c.coefE = s->coefE.as<cplx<double>>();
+  c.n0 = s->n0.as<double>();
+  c.renorm = 1;
+  c.dv = s->dv;
+  c.dens = s->dens.as<T>();
+  c.eta0 = s->eta0.as<double>();
+  auto* t = s->timer.begin("clean");
+  HIPC(launch_clean<T>(c, s->stream));
+  s->timer.end(t);
+}
+
+template <typename T>
+void poissonT(bse_system* s, int B, double* acc, double wn) {
+  Tables& tb = tabs<T>(s);
+  PoisArgs<T> a{};
+  a.rho = s->dens.as<T>();
+  a.B = B;
+  a.work = s->work.as<cplx<T>>();
+  a.tw = tb.tw.as<cplx<T>>();
+  a.k2 = tb.k2.as<T>();
+  a.vscale = (T)(4.0 * M_PI / (double)s->ng);
+  a.out = s->u.as<T>();
+  a.acc = acc;
+  a.wn = wn;
+  auto* t = s->timer.begin("poisson");
+  HIPC(launch_poisson<T>(s->n, a, s->stream));
+  s->timer.end(t);
+}
+
+// one batch of B pairs; results W (FP64) in s->wpol (q added at the end)
+template <typename T>
+void propagate_batch(bse_system* s, const int* pq_host, int B) {
+  using C = cplx<T>;
+  Tables& tb = tabs<T>(s);
+  const size_t ng = s->ng;
+  const int L = s->L;
+  const int F = B * L;
+  const int N = s->cfg.n_steps;
+  const int M = s->cfg.clean_every;
+  hipStream_t st = s->stream;
+  HIPC(hipMemcpyAsync(s->pq_d.p, pq_host, sizeof(int) * 2 * B, hipMemcpyHostToDevice, st));
+  HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, ng, s->rho64.as<double>(), st));
+  poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0);
+  HIPC(hipMemsetAsync(s->wpol.p, 0, sizeof(double) * ng * B, st));
+  HIPC(hipMemsetAsync(s->u.p, 0, sizeof(T) * ng * B, st));
+  HIPC(launch_kick<T>(s->q.as<double>(), s->eta0.as<double>(), L, F, ng, s->d.as<C>(), st));
+  const C* hist = s->hist.as<C>();
+  const size_t hstride = (size_t)L * ng;
+  if (M > 0) clean<T>(s, B, 2, hist);
+  // u_0 = 0: a phase kick does not change the density, so the t = 0 term
+  // of the time integral vanishes.
+  bool half = true;
+  for (int n = 0; n < N; ++n) {
+    PropXArgs<T> px{};
+    px.din = s->d.as<C>();
+    px.dout = s->d.as<C>();
+    px.pf = tb.pf.as<C>();
+    px.ph = tb.ph.as<C>();
+    px.u = s->u.as<T>();
+    px.H = hist + (size_t)n * hstride;
+    px.tw = tb.tw.as<C>();
+    px.kph = tb.kph.as<C>();
+    px.dt = (T)s->cfg.dt;
+    px.L = L;
+    px.mode = half ? PX_HALF : PX_FULL;
+    auto* t1 = s->timer.begin("prop_x");
+    HIPC(launch_prop_x<T>(s->n, px, F, st));
+    s->timer.end(t1);
+    PropYZArgs<T> pz{};
+    pz.d = s->d.as<C>();
+    pz.H = hist + (size_t)(n + 1) * hstride;
+    pz.tw = tb.tw.as<C>();
+    pz.kph = tb.kph.as<C>();
+    pz.dens = s->dens.as<T>();
+    pz.L = L;
+    pz.density = 1;
+    auto* t2 = s->timer.begin("prop_yz");
+    HIPC(launch_prop_yz<T>(s->n, pz, B, st));
+    s->timer.end(t2);
+    const bool do_clean = M > 0 && ((n + 1) % M == 0);
+    const double wn = s->wts[n + 1];
+    if (!do_clean) {
+      poissonT<T>(s, B, s->wpol.as<double>(), wn);
+      half = false;
+    } else {
+      poissonT<T>(s, B, nullptr, 0.0);
+      clean<T>(s, B, 1, hist + (size_t)(n + 1) * hstride);
+      poissonT<T>(s, B, s->wpol.as<double>(), wn);
+      half = true;
+    }
+  }
+}
+
+template <typename T>
+void build_history(bse_system* s) {
+  using C = cplx<T>;
+  Tables& tb = tabs<T>(s);
+  const size_t ng = s->ng;
+  const int L = s->L;
+  const int N = s->cfg.n_steps;
+  const size_t hstride = (size_t)L * ng;
+  s->hist.alloc(sizeof(C) * hstride * (size_t)(N + 1));
+  s->eta0.alloc(sizeof(double) * hstride);
+  s->n0.alloc(sizeof(double) * L);
+  C* hist = s->hist.as<C>();
+  if (!s->deterministic) {
+    s->xi_d.alloc((size_t)L * s->cfg.n_occ);
+    HIPC(hipMemcpy(s->xi_d.p, s->xi.data(), (size_t)L * s->cfg.n_occ, hipMemcpyHostToDevice));
+  }
+  HIPC(launch_stoch_orbitals<T>(s->phi64.as<double>(), s->xi_d.as<signed char>(), L, s->cfg.n_occ,
+                                s->deterministic ? 1 : 0, ng, tb.ph.as<C>(), s->eta0.as<double>(),
+                                hist, s->stream));
+  HIPC(launch_norms(s->eta0.as<double>(), L, ng, s->dv, s->n0.as<double>(), s->stream));
+  for (int n = 0; n < N; ++n) {
+    PropXArgs<T> px{};
+    px.din = hist + (size_t)n * hstride;
+    px.dout = hist + (size_t)(n + 1) * hstride;
+    px.pf = tb.pf.as<C>();
+    px.ph = tb.ph.as<C>();
+    px.tw = tb.tw.as<C>();
+    px.kph = tb.kph.as<C>();
+    px.dt = (T)s->cfg.dt;
+    px.L = L;
+    px.mode = PX_ETA0;
+    HIPC(launch_prop_x<T>(s->n, px, L, s->stream));
+    PropYZArgs<T> pz{};
+    pz.d = hist + (size_t)(n + 1) * hstride;
+    pz.tw = tb.tw.as<C>();
+    pz.kph = tb.kph.as<C>();
+    pz.L = L;
+    pz.density = 0;
+    HIPC(launch_prop_yz<T>(s->n, pz, L, s->stream));
+  }
+}
+
+void compute_weights(bse_system* s) {
+  const int N = s->cfg.n_steps;
+  s->wts.assign(N + 1, 0.0);
+  for (int n = 0; n <= N; ++n) {
+    const double t = n * s->cfg.dt;
+    const double c = (n == 0 || n == N) ? 0.5 : 1.0;
+    s->wts[n] = c * std::exp(-0.5 * s->cfg.gamma * s->cfg.gamma * t * t) * s->cfg.dt;
+  }
+}
+
+void check_ready(bse_system* s) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (!s->ready) fail(BSE_ERR_STATE, "bse_set_orbitals has not been called");
+}
+
+// Run W for n_pairs pairs into device outputs (FP64 [n_pairs][ng]).
+void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev, double* wpol_dev,
+                    int32_t* status_host) {
+  check_ready(s);
+  if (n_pairs < 0 || (n_pairs > 0 && (!pq || !w_dev))) fail(BSE_ERR_ARG, "bad pair arguments");
+  for (int k = 0; k < n_pairs; ++k)
+    if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
+      fail(BSE_ERR_ARG, "pair index out of range");
+  s->timer.st = s->stream;
+  s->timer.reset();
+  const int Bmax = std::max(1, s->cfg.max_batch);
+  bool any_bad = false;
+  for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
+    const int B = std::min(Bmax, n_pairs - k0);
+    if (s->cfg.precision == BSE_FP64) {
+      ensure_batch<double>(s, B);
+      propagate_batch<double>(s, pq + 2 * k0, B);
+    } else {
+      ensure_batch<float>(s, B);
+      propagate_batch<float>(s, pq + 2 * k0, B);
+    }
+    const size_t off = (size_t)k0 * s->ng;
+    const size_t cnt = (size_t)B * s->ng;
+    HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), cnt, w_dev + off, s->stream));
+    if (wpol_dev)
+      HIPC(hipMemcpyAsync(wpol_dev + off, s->wpol.p, sizeof(double) * cnt, hipMemcpyDeviceToDevice,
+                          s->stream));
+    HIPC(launch_finite_check(w_dev + off, B, s->ng, s->flags.as<int>(), s->stream));
+    if (status_host) {
+      std::vector<int> fl(B);
+      HIPC(hipMemcpyAsync(fl.data(), s->flags.p, sizeof(int) * B, hipMemcpyDeviceToHost, s->stream));
+      HIPC(hipStreamSynchronize(s->stream));
+      for (int b = 0; b < B; ++b) {
+        status_host[k0 + b] = fl[b] ? BSE_ERR_NUMERIC : 0;
+        if (fl[b]) {
+          any_bad = true;
+          HIPC(launch_fill_nan(w_dev + off + (size_t)b * s->ng, s->ng, s->stream));
+          if (wpol_dev) HIPC(launch_fill_nan(wpol_dev + off + (size_t)b * s->ng, s->ng, s->stream));
+        }
+      }
+    }
+  }
+  if (any_bad) fail(BSE_ERR_NUMERIC, "non-finite W for some pairs");
+}
+
+#define API_BEGIN try {
+#define API_END                 \
+  }                             \
+  catch (const Fail& f) {       \
+    return f.st;                \
+  }                             \
+  catch (const std::exception& e) { \
+    g_err = e.what();           \
+    return BSE_ERR_DEVICE;      \
+  }                             \
+  return BSE_OK;
+
+}  // namespace
+
+extern "C" {
+
+const char* bse_last_error(void) { return g_err.c_str(); }
+const char* bse_version(void) { return "libbse 0.1 gfx950"; }
+
+bse_status bse_generate_signs(uint64_t seed, int32_t n_stoch, int32_t n_occ, int8_t* xi) {
+  if (n_stoch <= 0 || n_occ <= 0 || !xi) {
+    g_err = "bse_generate_signs: bad arguments";
+    return BSE_ERR_ARG;
+  }
+  for (int l = 0; l < n_stoch; ++l)
+    for (int s = 0; s < n_occ; ++s)
+      xi[(size_t)l * n_occ + s] =
+          (splitmix64_draw(seed, (uint64_t)l * n_occ + s) >> 63) == 0 ? (int8_t)1 : (int8_t)-1;
+  return BSE_OK;
+}
+
+bse_status bse_create_system(const bse_config* cfg, const double* v_ext, bse_system** out) {
+  API_BEGIN
+  if (!cfg || !v_ext || !out) fail(BSE_ERR_ARG, "null argument");
+  *out = nullptr;
+  const bse_config& c = *cfg;
+  if (c.nx != c.ny || c.nx != c.nz) fail(BSE_ERR_ARG, "grid must be cubic (nx == ny == nz)");
+  const bool fp64 = c.precision == BSE_FP64;
+  if (c.precision != BSE_FP64 && c.precision != BSE_MIXED) fail(BSE_ERR_ARG, "bad precision");
+  if (fp64 ? !grid_supported<double>(c.nx) : !grid_supported<float>(c.nx))
+    fail(BSE_ERR_ARG, "unsupported grid size " + std::to_string(c.nx));
+  if (!(c.h > 0) || !(c.dt > 0) || c.n_steps < 0 || c.n_occ <= 0 || c.n_stoch < 0 ||
+      c.clean_every < 0 || !(c.gamma >= 0) || c.max_batch < 1)
+    fail(BSE_ERR_ARG, "bad configuration value");
+  if (c.alpha != 0.0) fail(BSE_ERR_ARG, "only the linearised kick (alpha = 0) is implemented");
+  int ndev = 0;
+  HIPC(hipGetDeviceCount(&ndev));
+  if (c.device < 0 || c.device >= ndev) fail(BSE_ERR_ARG, "bad device ordinal");
+  HIPC(hipSetDevice(c.device));
+  auto* s = new bse_system();
+  try {
+    s->cfg = c;
+    s->n = c.nx;
+    s->ng = (size_t)c.nx * c.ny * c.nz;
+    s->dv = c.h * c.h * c.h;
+    s->deterministic = c.n_stoch == 0;
+    s->L = s->deterministic ? c.n_occ : c.n_stoch;
+    s->vext.assign(v_ext, v_ext + s->ng);
+    for (double v : s->vext)
+      if (!std::isfinite(v)) fail(BSE_ERR_ARG, "non-finite V_ext");
+    upload_tables<double>(s, s->td);
+    if (!fp64) upload_tables<float>(s, s->tf);
+    configure_kernels<double>(s->n);
+    if (!fp64) configure_kernels<float>(s->n);
+    compute_weights(s);
+    if (!s->deterministic) {
+      s->xi.resize((size_t)s->L * c.n_occ);
+      bse_generate_signs(c.seed, s->L, c.n_occ, s->xi.data());
+    }
+  } catch (...) {
+    delete s;
+    throw;
+  }
+  *out = s;
+  API_END
+}
+
+bse_status bse_set_signs(bse_system* s, int32_t n_stoch, int32_t n_occ, const int8_t* xi) {
+  API_BEGIN
+  if (!s || !xi) fail(BSE_ERR_ARG, "null argument");
+  if (s->deterministic || n_stoch != s->L || n_occ != s->cfg.n_occ)
+    fail(BSE_ERR_ARG, "sign shape does not match the configuration");
+  for (size_t i = 0; i < (size_t)n_stoch * n_occ; ++i)
+    if (xi[i] != 1 && xi[i] != -1) fail(BSE_ERR_ARG, "signs must be +1 or -1");
+  s->xi.assign(xi, xi + (size_t)n_stoch * n_occ);
+  s->signs_given = true;
+  API_END
+}
+
+bse_status bse_set_stream(bse_system* s, void* st) {
+  API_BEGIN
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  s->stream = reinterpret_cast<hipStream_t>(st);
+  API_END
+}
+
+bse_status bse_set_orbitals(bse_system* s, int32_t n_orb, const double* phi, const double* eps) {
+  API_BEGIN
+  if (!s || !phi || !eps) fail(BSE_ERR_ARG, "null argument");
+  if (n_orb < s->cfg.n_occ) fail(BSE_ERR_ARG, "n_orb < n_occ");
+  const size_t tot = (size_t)n_orb * s->ng;
+  for (size_t i = 0; i < tot; ++i)
+    if (!std::isfinite(phi[i])) fail(BSE_ERR_ARG, "non-finite orbital value");
+  for (int i = 0; i < n_orb; ++i)
+    if (!std::isfinite(eps[i])) fail(BSE_ERR_ARG, "non-finite eigenvalue");
+  HIPC(hipSetDevice(s->cfg.device));
+  s->ready = false;
+  s->n_orb = n_orb;
+  s->eps.assign(eps, eps + n_orb);
+  s->phi64.alloc(sizeof(double) * tot);
+  HIPC(hipMemcpy(s->phi64.p, phi, sizeof(double) * tot, hipMemcpyHostToDevice));
+  if (s->cfg.precision == BSE_MIXED) {
+    const size_t no = (size_t)s->cfg.n_occ * s->ng;
+    s->phi_occ32.alloc(sizeof(float) * no);
+    HIPC(launch_to_real<float>(s->phi64.as<double>(), no, s->phi_occ32.as<float>(), s->stream));
+    build_history<float>(s);
+  } else {
+    build_history<double>(s);
+  }
+  HIPC(hipStreamSynchronize(s->stream));
+  s->a_no = s->a_nc = 0;
+  s->ready = true;
+  API_END
+}
+
+bse_status bse_apply_W_device(bse_system* s, int32_t n_pairs, const int32_t* pq, void* w_dev,
+                              void* wpol_dev) {
+  API_BEGIN
+  apply_w_device(s, n_pairs, pq, reinterpret_cast<double*>(w_dev),
+                 reinterpret_cast<double*>(wpol_dev), nullptr);
+  API_END
+}
+
+bse_status bse_apply_W(bse_system* s, int32_t n_pairs, const int32_t* pq, double* w_out,
+                       double* wpol_out, int32_t* pair_status) {
+  API_BEGIN
+  check_ready(s);
+  if (n_pairs < 0 || (n_pairs > 0 && (!pq || !w_out))) fail(BSE_ERR_ARG, "bad pair arguments");
+  if (n_pairs == 0) return BSE_OK;
+  DBuf w, wp;
+  const size_t cnt = (size_t)n_pairs * s->ng;
+  w.alloc(sizeof(double) * cnt);
+  if (wpol_out) wp.alloc(sizeof(double) * cnt);
+  std::vector<int32_t> st(n_pairs, 0);
+  bse_status rc = BSE_OK;
+  try {
+    apply_w_device(s, n_pairs, pq, w.as<double>(), wpol_out ? wp.as<double>() : nullptr, st.data());
+  } catch (const Fail& f) {
+    if (f.st != BSE_ERR_NUMERIC) throw;
+    rc = BSE_ERR_NUMERIC;
+  }
+  HIPC(hipMemcpyAsync(w_out, w.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, s->stream));
+  if (wpol_out)
+    HIPC(hipMemcpyAsync(wpol_out, wp.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
+  if (pair_status) std::memcpy(pair_status, st.data(), sizeof(int32_t) * n_pairs);
+  if (rc != BSE_OK) {
+    g_err = "non-finite W for some pairs";
+    return rc;
+  }
+  API_END
+}
+
+bse_status bse_set_timing(bse_system* s, int32_t enable) {
+  API_BEGIN
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  s->timer.on = enable != 0;
+  API_END
+}
+
+int32_t bse_kernel_times(bse_system* s, int32_t cap, const char** names, double* avg_ms,
+                         int32_t* calls) {
+  if (!s || !s->timer.on) return 0;
+  try {
+    HIPC(hipStreamSynchronize(s->stream));
+    int k = 0;
+    for (const auto& nm : s->timer.order) {
+      if (k >= cap) break;
+      const auto& r = s->timer.recs[nm];
+      double tot = 0;
+      for (size_t i = 0; i < r.used; ++i) {
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, r.ev[i].first, r.ev[i].second));
+        tot += ms;
+      }
+      names[k] = s->timer.recs.find(nm)->first.c_str();
+      avg_ms[k] = r.used ? tot / r.used : 0.0;
+      calls[k] = (int32_t)r.used;
+      ++k;
+    }
+    return k;
+  } catch (const Fail&) {
+    return -1;
+  }
+}
+
+bse_status bse_build_A(bse_system* s, int32_t n_o, int32_t n_c, double* A) {
+  API_BEGIN
+  (void)s; (void)n_o; (void)n_c; (void)A;
+  fail(BSE_ERR_STATE, "bse_build_A: not available in this build");
+  API_END
+}
+
+bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
+                        const double* w_grid, double sigma_broad, double* sigma) {
+  API_BEGIN
+  (void)s; (void)n_exc; (void)omega; (void)dip2; (void)n_w; (void)w_grid; (void)sigma_broad; (void)sigma;
+  fail(BSE_ERR_STATE, "bse_spectrum: not available in this build");
+  API_END
+}
+
+void bse_destroy_system(bse_system* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->cfg.device);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Argument blocks and launchers of the propagation kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include "fft_lines.h"
+
+namespace bse {
+
+enum { PX_ETA0 = 0, PX_FULL = 1, PX_HALF = 2 };
+
+template <typename T> struct PropXArgs {
+  const cplx<T>* din;
+  cplx<T>* dout;
+  const cplx<T>* pf;   // exp(-i V dt)
+  const cplx<T>* ph;   // exp(-i V dt/2)
+  const T* u;          // [B][ng]
+  const cplx<T>* H;    // unperturbed mid-step state [L][ng]
+  const cplx<T>* tw;   // twiddles exp(-2 pi i m/N)
+  const cplx<T>* kph;  // exp(-i k^2 dt/2) / N per frequency index
+  T dt;
+  int L;
+  int mode;
+};
+
+template <typename T> struct PropYZArgs {
+  cplx<T>* d;
+  const cplx<T>* H;
+  const cplx<T>* tw;
+  const cplx<T>* kph;
+  T* dens;
+  int L;
+  int density;
+};
+
+template <typename T> struct PoisArgs {
+  const T* rho;        // [B][ng] real densities
+  int B;
+  cplx<T>* work;       // [(B+1)/2][ng]
+  const cplx<T>* tw;
+  const T* k2;         // k^2 per frequency index
+  T vscale;            // 4 pi / ng
+  T* out;              // nullable [B][ng]
+  double* out64;       // nullable [B][ng]
+  double* acc;         // nullable [B][ng]: acc += wn * v[rho]
+  double wn;
+};
+
+template <typename T> struct CleanArgs {
+  cplx<T>* d;          // [F][ng]
+  int F, L, S;
+  const T* u;
+  const cplx<T>* H;
+  const cplx<T>* ph;
+  cplx<T>* E;          // [L][ng] workspace
+  const T* phi;        // occupied orbitals [S][ng]
+  size_t ng;
+  T dt;
+  int from_mid;
+  int chunk;
+  cplx<double>* part;  // [nchunk][F][S+1]
+  cplx<double>* coef;  // [F][S+1]
+  cplx<double>* coefE; // [L][S+1]
+  const double* n0;    // [L]
+  int renorm;
+  double dv;
+  T* dens;             // [F/L][ng]
+  const double* eta0;  // [L][ng] eta_l(0), used at t = 0
+};
+
+template <typename T> bool grid_supported(int n);
+template <typename T> void configure_kernels(int n);
+template <typename T> hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st);
+template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st);
+template <typename T> hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_stoch_orbitals(const double* phi, const signed char* xi, int L, int n_occ,
+                                 int deterministic, size_t ng, const cplx<T>* ph, double* eta0,
+                                 cplx<T>* H0, hipStream_t st);
+template <typename T>
+hipError_t launch_kick(const double* q, const double* eta0, int L, int F, size_t ng, cplx<T>* d,
+                       hipStream_t st);
+template <typename T> hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st);
+template <typename T> hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st);
+hipError_t launch_pair_density(const double* phi, const int* pq, int B, size_t ng, double* rho,
+                               hipStream_t st);
+hipError_t launch_add(const double* a, const double* b, size_t n, double* out, hipStream_t st);
+hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double* out, hipStream_t st);
+
+}  // namespace bse

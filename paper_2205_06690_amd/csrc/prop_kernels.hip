@@ -1,0 +1,727 @@
+// Propagation, Poisson and cleaning kernels of the stochastic TD-Hartree
+// action of W (Method: "Stochastic evaluation of the action of W",
+// Eqs. 10-15), for gfx950.
+//
+// Field layout: complex interleaved (float2/double2), [field][x][y][z] with
+// z fastest, n = N per axis.  The kinetic propagator exp(-i T dt) is
+// separable into exp(-i kx^2 dt/2) exp(-i ky^2 dt/2) exp(-i kz^2 dt/2); the
+// x factor is applied by prop_x on tiles [N x TC] of x-lines, the y and z
+// factors by prop_yz on whole contiguous y-z planes.  The Coulomb solve is a
+// full 3-D transform: forward y-z planes, x-lines with the 4 pi/k^2
+// multiplier between the forward and inverse halves, inverse y-z planes.
+#include "fft_lines.h"
+#include "prop_kernels.h"
+
+namespace bse {
+
+// ---------------------------------------------------------------------------
+// prop_x: pre-kinetic pointwise step fused with the x factor of exp(-iT dt)
+// ---------------------------------------------------------------------------
+// mode PX_ETA0: out = Pf * in                                  (unperturbed set)
+// mode PX_FULL: out = Pf * (d - i dt u_b H_l)                  (mid-step state)
+// mode PX_HALF: out = Ph * (d - i dt/2 u_b (Ph H_l))           (cleaned end state)
+template <int N, int TC, typename T>
+__global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  const int ng = N * N * N;
+  const int tile = blockIdx.x;
+  const int f = blockIdx.y;
+  const int b = f / a.L, l = f % a.L;
+  const int c0 = tile * TC;
+  const C* __restrict__ din = a.din + (size_t)f * ng;
+  C* __restrict__ dout = a.dout + (size_t)f * ng;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int e = tid; e < N * TC; e += nthr) {
+    const int x = e / TC, c = e % TC;
+    const size_t g = (size_t)x * N * N + c0 + c;
+    C v = din[g];
+    if (a.mode == PX_ETA0) {
+      v = cmul(a.pf[g], v);
+    } else {
+      const T uu = a.u[(size_t)b * ng + g];
+      C h = a.H[(size_t)l * ng + g];
+      if (a.mode == PX_FULL) {
+        // d - i dt u h
+        const T cu = a.dt * uu;
+        v = cmk<C>(v.x + cu * h.y, v.y - cu * h.x);
+        v = cmul(a.pf[g], v);
+      } else {
+        const C ph = a.ph[g];
+        h = cmul(ph, h);
+        const T cu = (T)0.5 * a.dt * uu;
+        v = cmk<C>(v.x + cu * h.y, v.y - cu * h.x);
+        v = cmul(ph, v);
+      }
+    }
+    s[x * TC + c] = v;
+  }
+  __syncthreads();
+  stageA_fwd<N>(s, TC, 1, TC, a.tw, tid, nthr, true);
+  __syncthreads();
+  const C* __restrict__ kp = a.kph;
+  stageB<N, 2>(s, TC, 1, TC, a.tw, tid, nthr, true,
+               [kp](int, C v, int k) { return cmul(v, kp[k]); });
+  __syncthreads();
+  stageC_inv<N>(s, TC, 1, TC, tid, nthr, true);
+  __syncthreads();
+  for (int e = tid; e < N * TC; e += nthr) {
+    const int x = e / TC, c = e % TC;
+    dout[(size_t)x * N * N + c0 + c] = s[x * TC + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prop_yz: y and z factors of exp(-iT dt) on a whole y-z plane, plus the
+// induced density dn_b = 4 sum_l Re(conj(H_l) d_{b,l}) of the post-kinetic
+// state (linearised Eq. 11 source).
+// ---------------------------------------------------------------------------
+template <int N, typename T, int NT>
+__device__ __forceinline__ void kinetic_yz_plane(cplx<T>* s, const cplx<T>* __restrict__ tw,
+                                                 const cplx<T>* __restrict__ kp, int tid) {
+  using C = cplx<T>;
+  auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
+  // z lines: line = y (stride N), elements contiguous
+  stageA_fwd<N>(s, N, N, 1, tw, tid, NT, false);
+  __syncthreads();
+  stageB<N, 2>(s, N, N, 1, tw, tid, NT, false, mul);
+  __syncthreads();
+  stageC_inv<N>(s, N, N, 1, tid, NT, false);
+  __syncthreads();
+  // y lines: line = z (stride 1), elements N apart
+  stageA_fwd<N>(s, N, 1, N, tw, tid, NT, true);
+  __syncthreads();
+  stageB<N, 2>(s, N, 1, N, tw, tid, NT, true, mul);
+  __syncthreads();
+  stageC_inv<N>(s, N, 1, N, tid, NT, true);
+  __syncthreads();
+}
+
+template <int N, typename T, int NT>
+__global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int P = N * N;
+  constexpr int PER = (P + NT - 1) / NT;
+  const int ng = N * N * N;
+  const int x = blockIdx.x;
+  const int tid = threadIdx.x;
+  const size_t poff = (size_t)x * P;
+  if (!a.density) {
+    // unperturbed set: field blockIdx.y, kinetic only
+    C* d = a.d + (size_t)blockIdx.y * ng + poff;
+    for (int e = tid; e < P; e += NT) s[e] = d[e];
+    __syncthreads();
+    kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
+    for (int e = tid; e < P; e += NT) d[e] = s[e];
+    return;
+  }
+  const int b = blockIdx.y;
+  T acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) acc[i] = 0;
+  for (int l = 0; l < a.L; ++l) {
+    C* d = a.d + ((size_t)b * a.L + l) * ng + poff;
+    const C* __restrict__ h = a.H + (size_t)l * ng + poff;
+    for (int e = tid; e < P; e += NT) s[e] = d[e];
+    __syncthreads();
+    kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < P) {
+        const C v = s[e];
+        const C hh = h[e];
+        d[e] = v;
+        acc[i] += hh.x * v.x + hh.y * v.y;
+      }
+    }
+    __syncthreads();
+  }
+  T* dn = a.dens + (size_t)b * ng + poff;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < P) dn[e] = (T)4 * acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coulomb potential v[rho] of real densities, two packed per complex field
+// (the 4 pi/k^2 kernel is real and even, so re and im stay independent).
+// ---------------------------------------------------------------------------
+template <int N, typename T, int NT>
+__global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int P = N * N;
+  const int ng = N * N * N;
+  const int x = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
+  const int b0 = 2 * m, b1 = 2 * m + 1;
+  const T* r0 = a.rho + (size_t)b0 * ng + (size_t)x * P;
+  const T* r1 = (b1 < a.B) ? a.rho + (size_t)b1 * ng + (size_t)x * P : nullptr;
+  for (int e = tid; e < P; e += NT) s[e] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
+  __syncthreads();
+  NoMul nm;
+  stageA_fwd<N>(s, N, N, 1, a.tw, tid, NT, false);
+  __syncthreads();
+  stageB<N, 0>(s, N, N, 1, a.tw, tid, NT, false, nm);
+  __syncthreads();
+  stageA_fwd<N>(s, N, 1, N, a.tw, tid, NT, true);
+  __syncthreads();
+  stageB<N, 0>(s, N, 1, N, a.tw, tid, NT, true, nm);
+  __syncthreads();
+  C* w = a.work + (size_t)m * ng + (size_t)x * P;
+  for (int e = tid; e < P; e += NT) w[e] = s[e];
+}
+
+template <int N, int TC, typename T>
+__global__ void __launch_bounds__(256) k_poisson_x(PoisArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  const int ng = N * N * N;
+  const int c0 = blockIdx.x * TC, m = blockIdx.y, tid = threadIdx.x, nthr = blockDim.x;
+  C* w = a.work + (size_t)m * ng;
+  for (int e = tid; e < N * TC; e += nthr) {
+    const int x = e / TC, c = e % TC;
+    s[x * TC + c] = w[(size_t)x * N * N + c0 + c];
+  }
+  __syncthreads();
+  stageA_fwd<N>(s, TC, 1, TC, a.tw, tid, nthr, true);
+  __syncthreads();
+  const T* __restrict__ k2 = a.k2;
+  const T scale = a.vscale;
+  auto mul = [k2, c0, scale](int line, C v, int kx) {
+    const int c = c0 + line;
+    const int ky = scr2k<N>(c / N), kz = scr2k<N>(c % N);
+    const T kk = k2[kx] + k2[ky] + k2[kz];
+    const T f = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / kk;
+    return cscale(v, f);
+  };
+  stageB<N, 2>(s, TC, 1, TC, a.tw, tid, nthr, true, mul);
+  __syncthreads();
+  stageC_inv<N>(s, TC, 1, TC, tid, nthr, true);
+  __syncthreads();
+  for (int e = tid; e < N * TC; e += nthr) {
+    const int x = e / TC, c = e % TC;
+    w[(size_t)x * N * N + c0 + c] = s[x * TC + c];
+  }
+}
+
+template <int N, typename T, int NT>
+__global__ void __launch_bounds__(NT) k_poisson_yz_inv(PoisArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int P = N * N;
+  const int ng = N * N * N;
+  const int x = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
+  const C* w = a.work + (size_t)m * ng + (size_t)x * P;
+  for (int e = tid; e < P; e += NT) s[e] = w[e];
+  __syncthreads();
+  NoMul nm;
+  stageB<N, 1>(s, N, N, 1, a.tw, tid, NT, false, nm);
+  __syncthreads();
+  stageC_inv<N>(s, N, N, 1, tid, NT, false);
+  __syncthreads();
+  stageB<N, 1>(s, N, 1, N, a.tw, tid, NT, true, nm);
+  __syncthreads();
+  stageC_inv<N>(s, N, 1, N, tid, NT, true);
+  __syncthreads();
+  const int b0 = 2 * m, b1 = 2 * m + 1;
+  const size_t o0 = (size_t)b0 * ng + (size_t)x * P;
+  const size_t o1 = (size_t)b1 * ng + (size_t)x * P;
+  const bool has1 = b1 < a.B;
+  for (int e = tid; e < P; e += NT) {
+    const C v = s[e];
+    if (a.out) {
+      a.out[o0 + e] = v.x;
+      if (has1) a.out[o1 + e] = v.y;
+    }
+    if (a.out64) {
+      a.out64[o0 + e] = (double)v.x;
+      if (has1) a.out64[o1 + e] = (double)v.y;
+    }
+    if (a.acc) {
+      a.acc[o0 + e] += a.wn * (double)v.x;
+      if (has1) a.acc[o1 + e] += a.wn * (double)v.y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pointwise helpers
+// ---------------------------------------------------------------------------
+// rho_b = phi_i phi_j (FP64)
+__global__ void k_pair_density(const double* __restrict__ phi, const int* __restrict__ pq,
+                               int B, size_t ng, double* __restrict__ rho) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= ng || b >= B) return;
+  const int p = pq[2 * b], q = pq[2 * b + 1];
+  rho[(size_t)b * ng + i] = phi[(size_t)p * ng + i] * phi[(size_t)q * ng + i];
+}
+
+// eta_l(0) = L^-1/2 sum_s xi[l, s] phi_s  (Eq. 14), FP64, and H_0 = conj(Ph) eta(0)
+template <typename T>
+__global__ void k_stoch_orbitals(const double* __restrict__ phi, const signed char* __restrict__ xi,
+                                 int L, int n_occ, int deterministic, size_t ng, double inv_sqrt_l,
+                                 const cplx<T>* __restrict__ ph, double* __restrict__ eta0,
+                                 cplx<T>* __restrict__ H0) {
+  using C = cplx<T>;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y;
+  if (i >= ng) return;
+  double v = 0.0;
+  if (deterministic) {
+    v = phi[(size_t)l * ng + i];
+  } else {
+    for (int s = 0; s < n_occ; ++s) v += (double)xi[(size_t)l * n_occ + s] * phi[(size_t)s * ng + i];
+    v *= inv_sqrt_l;
+  }
+  eta0[(size_t)l * ng + i] = v;
+  const C p = ph[i];
+  H0[(size_t)l * ng + i] = cmk<C>((T)(v * (double)p.x), (T)(-v * (double)p.y));
+}
+
+// d_{b,l}(0) = -i q_b eta_l(0)
+template <typename T>
+__global__ void k_kick(const double* __restrict__ q, const double* __restrict__ eta0, int L,
+                       size_t ng, cplx<T>* __restrict__ d) {
+  using C = cplx<T>;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (i >= ng) return;
+  const int b = f / L, l = f % L;
+  const double v = q[(size_t)b * ng + i] * eta0[(size_t)l * ng + i];
+  d[(size_t)f * ng + i] = cmk<C>((T)0, (T)(-v));
+}
+
+// end-of-step state from the mid-step one: d <- Ph (d - i dt/2 u_b H_l) and
+// E_l = Ph H_l (from_mid = 1); E_l = Ph H_l only (0); at t = 0 E_l is the
+// real eta_l(0) itself (2).
+template <typename T>
+__global__ void k_clean_finish(cplx<T>* __restrict__ d, const T* __restrict__ u,
+                               const cplx<T>* __restrict__ H, const cplx<T>* __restrict__ ph,
+                               const double* __restrict__ eta0, cplx<T>* __restrict__ E, int L,
+                               size_t ng, T dt, int from_mid) {
+  using C = cplx<T>;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (i >= ng) return;
+  const int b = f / L, l = f % L;
+  if (from_mid == 2) {
+    if (f < L) E[(size_t)l * ng + i] = cmk<C>((T)eta0[(size_t)l * ng + i], (T)0);
+    return;
+  }
+  const C p = ph[i];
+  const C h = H[(size_t)l * ng + i];
+  if (f < L) E[(size_t)l * ng + i] = cmul(p, h);
+  if (from_mid == 1) {
+    C v = d[(size_t)f * ng + i];
+    const T cu = (T)0.5 * dt * u[(size_t)b * ng + i];
+    v = cmk<C>(v.x + cu * h.y, v.y - cu * h.x);
+    d[(size_t)f * ng + i] = cmul(p, v);
+  }
+}
+
+// dn_b = 4 sum_l Re(conj(E_l) d_{b,l})
+template <typename T>
+__global__ void k_density_end(const cplx<T>* __restrict__ d, const cplx<T>* __restrict__ E,
+                              int L, size_t ng, T* __restrict__ dens) {
+  using C = cplx<T>;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= ng) return;
+  T acc = 0;
+  for (int l = 0; l < L; ++l) {
+    const C v = d[((size_t)b * L + l) * ng + i];
+    const C e = E[(size_t)l * ng + i];
+    acc += e.x * v.x + e.y * v.y;
+  }
+  dens[(size_t)b * ng + i] = (T)4 * acc;
+}
+
+// ---------------------------------------------------------------------------
+// cleaning (Eq. 15, linearised): d <- Q d - Re<E_l, Q d>/||eta_l(0)||^2 E_l
+// ---------------------------------------------------------------------------
+// partial coefficients over a chunk of grid points:
+//   part[chunk][f][s] = sum_{r in chunk} phi_s(r) d_f(r)   (s < S)
+//   part[chunk][f][S] = sum_{r in chunk} conj(E_l(f)) d_f(r)
+// tile: 32 fields x 32 states per block, 256 threads, 2x2 per thread.
+constexpr int CT_F = 32, CT_S = 32, CT_R = 32;
+template <typename T>
+__global__ void __launch_bounds__(256) k_clean_coef(const cplx<T>* __restrict__ d, int F,
+                                                    const T* __restrict__ phi, int S,
+                                                    const cplx<T>* __restrict__ E, int L,
+                                                    size_t ng, int chunk,
+                                                    cplx<double>* __restrict__ part) {
+  using C = cplx<T>;
+  __shared__ C sd[CT_F][CT_R + 1];
+  __shared__ T sp[CT_S][CT_R + 1];
+  const int f0 = blockIdx.x * CT_F;
+  const int s0 = blockIdx.y * CT_S;  // s == S row block also carries the E dot
+  const int kc = blockIdx.z;
+  const size_t r0 = (size_t)kc * chunk;
+  const size_t r1 = min(ng, r0 + (size_t)chunk);
+  const int tid = threadIdx.x;
+  const int tf = tid / 16, ts = tid % 16;
+  C acc[2][2];
+  C acce[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    acce[i] = cmk<C>(0, 0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = cmk<C>(0, 0);
+  }
+  const bool do_e = (s0 == 0);
+  for (size_t rb = r0; rb < r1; rb += CT_R) {
+    for (int e = tid; e < CT_F * CT_R; e += 256) {
+      const int ff = e / CT_R, rr = e % CT_R;
+      const int f = f0 + ff;
+      const size_t r = rb + rr;
+      sd[ff][rr] = (f < F && r < r1) ? d[(size_t)f * ng + r] : cmk<C>(0, 0);
+    }
+    for (int e = tid; e < CT_S * CT_R; e += 256) {
+      const int ss = e / CT_R, rr = e % CT_R;
+      const int s = s0 + ss;
+      const size_t r = rb + rr;
+      sp[ss][rr] = (s < S && r < r1) ? phi[(size_t)s * ng + r] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < CT_R; ++rr) {
+      const C d0 = sd[tf * 2][rr], d1 = sd[tf * 2 + 1][rr];
+      const T p0 = sp[ts * 2][rr], p1 = sp[ts * 2 + 1][rr];
+      acc[0][0] = cmk<C>(acc[0][0].x + d0.x * p0, acc[0][0].y + d0.y * p0);
+      acc[0][1] = cmk<C>(acc[0][1].x + d0.x * p1, acc[0][1].y + d0.y * p1);
+      acc[1][0] = cmk<C>(acc[1][0].x + d1.x * p0, acc[1][0].y + d1.y * p0);
+      acc[1][1] = cmk<C>(acc[1][1].x + d1.x * p1, acc[1][1].y + d1.y * p1);
+    }
+    if (do_e && ts == 0) {
+      for (int i = 0; i < 2; ++i) {
+        const int f = f0 + tf * 2 + i;
+        if (f >= F) continue;
+        const int l = f % L;
+        for (int rr = 0; rr < CT_R; ++rr) {
+          const size_t r = rb + rr;
+          if (r >= r1) break;
+          const C ee = E[(size_t)l * ng + r];
+          acce[i] = cadd(acce[i], cmulc(sd[tf * 2 + i][rr], ee));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  cplx<double>* out = part + (size_t)kc * F * (S + 1);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int f = f0 + tf * 2 + i;
+    if (f >= F) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int s = s0 + ts * 2 + j;
+      if (s < S) out[(size_t)f * (S + 1) + s] = cmk<cplx<double>>(acc[i][j].x, acc[i][j].y);
+    }
+    if (do_e && ts == 0) out[(size_t)f * (S + 1) + S] = cmk<cplx<double>>(acce[i].x, acce[i].y);
+  }
+}
+
+// reduce partials over chunks; coef[f][s] = h^3 sum (s < S); coef[f][S] = h^3 <E,d>
+__global__ void k_clean_reduce(const cplx<double>* __restrict__ part, int nchunk, int FS,
+                               double dv, cplx<double>* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= FS) return;
+  double x = 0, y = 0;
+  for (int k = 0; k < nchunk; ++k) {
+    const cplx<double> v = part[(size_t)k * FS + i];
+    x += v.x;
+    y += v.y;
+  }
+  coef[i] = cmk<cplx<double>>(x * dv, y * dv);
+}
+
+// renormalisation factor per field: c_f = Re(<E,d> - sum_s conj(De[l][s]) C[f][s]) / N0_l
+__global__ void k_clean_renorm(cplx<double>* __restrict__ coef, int F, int S,
+                               const cplx<double>* __restrict__ coefE, const double* __restrict__ n0,
+                               int L, int renorm) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int l = f % L;
+  cplx<double>* c = coef + (size_t)f * (S + 1);
+  double r = c[S].x;
+  for (int s = 0; s < S; ++s) {
+    const cplx<double> de = coefE[(size_t)l * (S + 1) + s];
+    const cplx<double> cc = c[s];
+    r -= de.x * cc.x + de.y * cc.y;
+  }
+  c[S] = cmk<cplx<double>>(renorm ? r / n0[l] : 0.0, 0.0);
+}
+
+// d_f(r) -= sum_s C[f][s] phi_s(r) + c_f E_l(r)
+// block: 64 grid points x up to 16 fields of one chunk; coefficients staged in LDS
+template <typename T>
+__global__ void __launch_bounds__(256) k_clean_update(cplx<T>* __restrict__ d, int F,
+                                                      const T* __restrict__ phi, int S,
+                                                      const cplx<T>* __restrict__ E, int L,
+                                                      size_t ng,
+                                                      const cplx<double>* __restrict__ coef) {
+  using C = cplx<T>;
+  constexpr int FB = 16, RB = 64, SB = 128;
+  __shared__ C sc[FB][SB + 1];
+  __shared__ T sphi[32][RB];
+  const size_t r0 = (size_t)blockIdx.x * RB;
+  const int fb0 = blockIdx.y * FB;
+  const int tid = threadIdx.x;
+  const int rr = tid % RB, fq = tid / RB;  // 4 field groups of 4
+  const size_t r = r0 + rr;
+  C acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = cmk<C>(0, 0);
+  for (int sb = 0; sb < S; sb += SB) {
+    const int sn = min(SB, S - sb);
+    __syncthreads();
+    for (int e = tid; e < FB * sn; e += 256) {
+      const int ff = e / sn, ss = e % sn;
+      const int f = fb0 + ff;
+      const cplx<double> v = (f < F) ? coef[(size_t)f * (S + 1) + sb + ss] : cmk<cplx<double>>(0, 0);
+      sc[ff][ss] = cmk<C>((T)v.x, (T)v.y);
+    }
+    for (int s2 = 0; s2 < sn; s2 += 32) {
+      const int sm = min(32, sn - s2);
+      __syncthreads();
+      for (int e = tid; e < 32 * RB; e += 256) {
+        const int ss = e / RB, q = e % RB;
+        sphi[ss][q] = (ss < sm && r0 + q < ng) ? phi[(size_t)(sb + s2 + ss) * ng + r0 + q] : (T)0;
+      }
+      __syncthreads();
+      for (int ss = 0; ss < sm; ++ss) {
+        const T p = sphi[ss][rr];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const C c = sc[fq * 4 + i][s2 + ss];
+          acc[i] = cmk<C>(acc[i].x + c.x * p, acc[i].y + c.y * p);
+        }
+      }
+    }
+  }
+  if (r >= ng) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int f = fb0 + fq * 4 + i;
+    if (f >= F) continue;
+    const int l = f % L;
+    const T cr = (T)coef[(size_t)f * (S + 1) + S].x;
+    const C e = E[(size_t)l * ng + r];
+    C v = d[(size_t)f * ng + r];
+    v = cmk<C>(v.x - acc[i].x - cr * e.x, v.y - acc[i].y - cr * e.y);
+    d[(size_t)f * ng + r] = v;
+  }
+}
+
+// out[b] = q[b] + wpol[b]
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, size_t n,
+                      double* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+// ||eta_l(0)||^2 h^3 partial sums
+__global__ void k_norms(const double* __restrict__ eta0, size_t ng, double dv, double* __restrict__ out) {
+  const int l = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0;
+  for (size_t i = threadIdx.x; i < ng; i += 256) {
+    const double v = eta0[(size_t)l * ng + i];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[l] = red[0] * dv;
+}
+
+template <typename T>
+__global__ void k_to_real(const double* __restrict__ in, size_t n, T* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int N> constexpr int yz_threads() { return N >= 64 ? 512 : 256; }
+template <int N> constexpr int x_tc() { return N >= 64 ? 32 : 16; }
+
+template <int N, typename T>
+struct Launch {
+  static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st) {
+    constexpr int TC = x_tc<N>();
+    dim3 grid(N * N / TC, F);
+    size_t sm = sizeof(cplx<T>) * N * TC;
+    hipLaunchKernelGGL((k_prop_x<N, TC, T>), grid, dim3(256), sm, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st) {
+    constexpr int NT = yz_threads<N>();
+    size_t sm = sizeof(cplx<T>) * N * N;
+    hipLaunchKernelGGL((k_prop_yz<N, T, NT>), dim3(N, nb), dim3(NT), sm, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t poisson(const PoisArgs<T>& a, hipStream_t st) {
+    constexpr int NT = yz_threads<N>();
+    constexpr int TC = x_tc<N>();
+    const int M = (a.B + 1) / 2;
+    size_t smp = sizeof(cplx<T>) * N * N;
+    hipLaunchKernelGGL((k_poisson_yz_fwd<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
+    hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256),
+                       sizeof(cplx<T>) * N * TC, st, a);
+    hipLaunchKernelGGL((k_poisson_yz_inv<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
+    return hipGetLastError();
+  }
+  static void configure() {
+    constexpr int NT = yz_threads<N>();
+    constexpr int TC = x_tc<N>();
+    const int smp = (int)(sizeof(cplx<T>) * N * N);
+    const int smx = (int)(sizeof(cplx<T>) * N * TC);
+    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_poisson_yz_fwd<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+    (void)hipFuncSetAttribute((const void*)k_poisson_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+  }
+};
+
+template <typename T>
+bool grid_supported(int n) {
+  if (sizeof(cplx<T>) * (size_t)n * n > 160 * 1024) return false;
+  switch (n) {
+    case 16: case 24: case 32: case 48: case 64: case 112: return true;
+    default: return false;
+  }
+}
+
+#define BSE_DISPATCH_N(n, T, CALL)                \
+  switch (n) {                                    \
+    case 16: return Launch<16, T>::CALL;          \
+    case 24: return Launch<24, T>::CALL;          \
+    case 32: return Launch<32, T>::CALL;          \
+    case 48: return Launch<48, T>::CALL;          \
+    case 64: return Launch<64, T>::CALL;          \
+    case 112: return Launch<112, T>::CALL;        \
+    default: return hipErrorInvalidValue;         \
+  }
+
+template <typename T>
+hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st) {
+  BSE_DISPATCH_N(n, T, prop_x(a, F, st));
+}
+template <typename T>
+hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st) {
+  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st));
+}
+template <typename T>
+hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st) {
+  BSE_DISPATCH_N(n, T, poisson(a, st));
+}
+template <typename T>
+void configure_kernels(int n) {
+  switch (n) {
+    case 16: Launch<16, T>::configure(); break;
+    case 24: Launch<24, T>::configure(); break;
+    case 32: Launch<32, T>::configure(); break;
+    case 48: Launch<48, T>::configure(); break;
+    case 64: Launch<64, T>::configure(); break;
+    case 112: if (sizeof(T) == 4) Launch<112, float>::configure(); break;
+    default: break;
+  }
+}
+
+static inline dim3 pw_grid(size_t ng, int y) { return dim3((unsigned)((ng + 255) / 256), y); }
+
+hipError_t launch_pair_density(const double* phi, const int* pq, int B, size_t ng, double* rho,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_density, pw_grid(ng, B), dim3(256), 0, st, phi, pq, B, ng, rho);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_stoch_orbitals(const double* phi, const signed char* xi, int L, int n_occ,
+                                 int deterministic, size_t ng, const cplx<T>* ph, double* eta0,
+                                 cplx<T>* H0, hipStream_t st) {
+  hipLaunchKernelGGL((k_stoch_orbitals<T>), pw_grid(ng, L), dim3(256), 0, st, phi, xi, L, n_occ,
+                     deterministic, ng, 1.0 / sqrt((double)L), ph, eta0, H0);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_kick(const double* q, const double* eta0, int L, int F, size_t ng, cplx<T>* d,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_kick<T>), pw_grid(ng, F), dim3(256), 0, st, q, eta0, L, ng, d);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
+  // 1. end-of-step state and E = Ph H
+  hipLaunchKernelGGL((k_clean_finish<T>), pw_grid(a.ng, a.F), dim3(256), 0, st, a.d, a.u, a.H,
+                     a.ph, a.eta0, a.E, a.L, a.ng, a.dt, a.from_mid);
+  // 2. coefficients of d against phi_s and E_l, and of E_l against phi_s
+  const int nchunk = (int)((a.ng + a.chunk - 1) / a.chunk);
+  const int S = a.S;
+  dim3 g1((a.F + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
+  hipLaunchKernelGGL((k_clean_coef<T>), g1, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L, a.ng,
+                     a.chunk, a.part);
+  hipLaunchKernelGGL(k_clean_reduce, dim3((a.F * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
+                     nchunk, a.F * (S + 1), a.dv, a.coef);
+  dim3 g2((a.L + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
+  hipLaunchKernelGGL((k_clean_coef<T>), g2, dim3(256), 0, st, a.E, a.L, a.phi, S, a.E, a.L, a.ng,
+                     a.chunk, a.part);
+  hipLaunchKernelGGL(k_clean_reduce, dim3((a.L * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
+                     nchunk, a.L * (S + 1), a.dv, a.coefE);
+  hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
+                     a.coefE, a.n0, a.L, a.renorm);
+  // 3. update and new density
+  dim3 g3((unsigned)((a.ng + 63) / 64), (a.F + 15) / 16);
+  hipLaunchKernelGGL((k_clean_update<T>), g3, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L,
+                     a.ng, a.coef);
+  hipLaunchKernelGGL((k_density_end<T>), pw_grid(a.ng, a.F / a.L), dim3(256), 0, st, a.d, a.E,
+                     a.L, a.ng, a.dens);
+  return hipGetLastError();
+}
+hipError_t launch_add(const double* a, const double* b, size_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norms, dim3(L), dim3(256), 0, st, eta0, ng, dv, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_to_real<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, n, out);
+  return hipGetLastError();
+}
+
+#define BSE_INST(T)                                                                            \
+  template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t);            \
+  template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t);          \
+  template hipError_t launch_poisson<T>(int, const PoisArgs<T>&, hipStream_t);                 \
+  template void configure_kernels<T>(int);                                                     \
+  template bool grid_supported<T>(int);                                                        \
+  template hipError_t launch_stoch_orbitals<T>(const double*, const signed char*, int, int,    \
+                                               int, size_t, const cplx<T>*, double*, cplx<T>*, \
+                                               hipStream_t);                                   \
+  template hipError_t launch_kick<T>(const double*, const double*, int, int, size_t, cplx<T>*, \
+                                     hipStream_t);                                             \
+  template hipError_t launch_clean<T>(const CleanArgs<T>&, hipStream_t);                       \
+  template hipError_t launch_to_real<T>(const double*, size_t, T*, hipStream_t);
+
+BSE_INST(float)
+BSE_INST(double)
+
+}  // namespace bse
