@@ -1,0 +1,168 @@
+"""Throughput of the stochastic-W hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mid64]
+
+One step is the whole hot path for the mid-size molecule (64^3 grid,
+h = 0.4 bohr, 60 Gaussian wells, N_occ = 120, n_o = 10, n_c = 20, L = 10
+stochastic orbitals, dt = 0.05, 400 steps): the W-action on every valence
+pair density phi_i phi_j (i <= j, 55 pair solves) with FP32 propagation and
+FP64 time integral, inputs resident in HBM.  The value is pair solves per
+second over the timed steps.  It prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def _alg_bytes(kernel: str, B: int, L: int, ng: int, cbytes: int) -> float:
+    """Algorithmic HBM bytes of one launch: every field read and written
+    once, the shared unperturbed set read once, the per-pair scalar field
+    read or written once (phase tables ignored)."""
+    F = B * L
+    rbytes = cbytes // 2
+    if kernel == "prop_x":
+        return 2.0 * F * ng * cbytes + L * ng * cbytes + B * ng * rbytes
+    if kernel == "prop_yz":
+        return 2.0 * F * ng * cbytes + L * ng * cbytes + B * ng * rbytes
+    return float("nan")
+
+
+def cpu_baseline(spec, sysd, pair, steps_sample: int):
+    """The FP64 oracle on one pair for ``steps_sample`` time steps, scaled to
+    pair solves per second of the full ``spec.n_steps`` propagation."""
+    from oracle.grid import Grid
+    from oracle import tdh
+    import dataclasses
+    grid = Grid(spec.shape, spec.h)
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    eta0 = tdh.stochastic_orbitals(phi[:spec.n_occ], sysd["xi"])
+    t0 = time.perf_counter()
+    w, wp = tdh.apply_w(grid, sysd["v_ext"], phi, spec.n_occ, [pair], eta0, dt=spec.dt,
+                        n_steps=steps_sample, gamma=spec.gamma_eff, clean_every=spec.clean_every)
+    t = time.perf_counter() - t0
+    per_solve = t * spec.n_steps / steps_sample
+    return w.reshape(1, -1), wp.reshape(1, -1), per_solve, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="mid64")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs no multi-GPU path "
+              "(pairs would shard across GPUs with one all-gather of A; not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_06690_amd import inputs
+    from paper_2205_06690_amd import bse
+
+    spec = inputs.CONFIGS[args.config]
+    t_in = time.perf_counter()
+    sysd = inputs.make_system(spec)
+    print(f"[bench] inputs {args.config} ready in {time.perf_counter() - t_in:.1f}s",
+          file=sys.stderr, flush=True)
+    prec = bse.BSE_MIXED if args.precision == "mixed" else bse.BSE_FP64
+    pairs = inputs.ij_pairs(spec)
+    B = len(pairs)
+    S = bse.System(spec.n, spec.h, sysd["v_ext"], n_occ=spec.n_occ, n_stoch=spec.n_stoch,
+                   seed=spec.seed, dt=spec.dt, n_steps=spec.n_steps, gamma=spec.gamma_eff,
+                   clean_every=spec.clean_every, precision=prec, max_batch=B)
+    S.set_signs(sysd["xi"])
+    stream = torch.cuda.current_stream()
+    S.set_stream(stream.cuda_stream)
+    S.set_orbitals(sysd["phi"], sysd["eps"])
+    w_dev = torch.empty((B, spec.ng), dtype=torch.float64, device="cuda")
+
+    def step():
+        S.apply_w_device(pairs, w_dev.data_ptr())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = S.kernel_times()
+    S.set_timing(False)
+    dt_step = (t1 - t0) / args.steps
+    value = B / dt_step
+    print(f"[bench] {args.steps} steps, {dt_step * 1e3:.1f} ms/step, kernels {kt}",
+          file=sys.stderr, flush=True)
+
+    cbytes = 8 if prec == bse.BSE_MIXED else 16
+    dom = max(("prop_x", "prop_yz"), key=lambda k: kt.get(k, (0.0, 0))[0] * kt.get(k, (0.0, 0))[1])
+    avg_ms = kt[dom][0]
+    alg = _alg_bytes(dom, B, spec.n_stoch, spec.ng, cbytes)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(avg_ms, 4),
+                "alg_bytes_per_launch": alg}
+
+    out = {
+        "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",
+        "value": round(value, 3), "unit": "pair solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt_step * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == bse.BSE_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {spec.n}^3 grid h={spec.h}, {spec.n_wells} "
+                               f"Gaussian wells seed {spec.seed}, N_occ={spec.n_occ}, "
+                               f"n_o={spec.n_o}, n_c={spec.n_c}, L={spec.n_stoch}, "
+                               f"dt={spec.dt}, {spec.n_steps} steps, M={spec.clean_every}",
+                   "pairs_per_step": B, "precision": args.precision},
+        "roofline": roofline,
+        "kernels_ms": {k: v[0] for k, v in kt.items()},
+    }
+
+    if not args.no_cpu_baseline:
+        pair = tuple(int(x) for x in pairs[-1])
+        w_o, wp_o, per_solve, t_cpu = cpu_baseline(spec, sysd, pair, args.cpu_steps)
+        # the same truncated propagation on the GPU for an accuracy sample
+        import dataclasses
+        S2 = bse.System(spec.n, spec.h, sysd["v_ext"], n_occ=spec.n_occ, n_stoch=spec.n_stoch,
+                        seed=spec.seed, dt=spec.dt, n_steps=args.cpu_steps,
+                        gamma=spec.gamma_eff, clean_every=spec.clean_every, precision=prec,
+                        max_batch=1)
+        S2.set_signs(sysd["xi"])
+        S2.set_orbitals(sysd["phi"], sysd["eps"])
+        w_g, wp_g = S2.apply_w([pair], want_wpol=True)
+        S2.close()
+        rel_w = float(np.linalg.norm(w_g - w_o) / np.linalg.norm(w_o))
+        rel_wp = float(np.linalg.norm(wp_g - wp_o) / np.linalg.norm(wp_o))
+        out["cpu_baseline"] = {
+            "value": round(1.0 / per_solve, 6), "unit": "pair solves/s",
+            "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"1 pair x {args.cpu_steps} of {spec.n_steps} steps "
+                      f"({t_cpu:.1f}s), scaled linearly to the full propagation"}
+        out["parity_sample"] = {"pair": list(pair), "steps": args.cpu_steps,
+                                "rel_err_W": rel_w, "rel_err_Wpol": rel_wp}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

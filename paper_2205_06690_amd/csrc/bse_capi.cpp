@@ -13,6 +13,7 @@
 #include "../../include/bse.h"
 #include "bse_kernels.h"
 #include "prop_kernels.h"
+#include "clean_mfma.h"
 
 using namespace bse;
 
@@ -138,7 +139,7 @@ struct bse_system {
   bool ready = false;
   // batch workspace
   int cap_b = 0;
-  DBuf d, u, dens, wpol, q, rho64, work, work64, part, coef, coefE, E, pq_d, flags;
+  DBuf d, u, dens, wpol, q, rho64, work, work64, part, part32, gpart, coef, coefE, E, pq_d, flags;
   int nchunk = 0;
   // A / spectrum state
   int a_no = 0, a_nc = 0;
@@ -231,6 +232,10 @@ void ensure_batch(bse_system* s, int B) {
   const int F = B * L;
   s->part.alloc(sizeof(cplx<double>) * (size_t)s->nchunk * std::max(F, L) * (S + 1));
   s->coef.alloc(sizeof(cplx<double>) * (size_t)F * (S + 1));
+  if (sizeof(T) == 4) {
+    s->part32.alloc(sizeof(float) * coef_part_floats(std::max(F, L), S, ng, chunk));
+    s->gpart.alloc(sizeof(cplx<double>) * edot_part_entries(F, ng));
+  }
   s->coefE.alloc(sizeof(cplx<double>) * (size_t)L * (S + 1));
   s->pq_d.alloc(sizeof(int) * 2 * B);
   s->flags.alloc(sizeof(int) * B);
@@ -267,6 +272,8 @@ void clean(bse_system* s, int B, int from_mid, const cplx<T>* H) {
   c.dv = s->dv;
   c.dens = s->dens.as<T>();
   c.eta0 = s->eta0.as<double>();
+  c.part32 = s->part32.as<float>();
+  c.gpart = s->gpart.as<cplx<double>>();
   auto* t = s->timer.begin("clean");
   HIPC(launch_clean<T>(c, s->stream));
   s->timer.end(t);
@@ -420,7 +427,6 @@ void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev
     if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
       fail(BSE_ERR_ARG, "pair index out of range");
   s->timer.st = s->stream;
-  s->timer.reset();
   const int Bmax = std::max(1, s->cfg.max_batch);
   bool any_bad = false;
   for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
@@ -622,7 +628,9 @@ bse_status bse_apply_W(bse_system* s, int32_t n_pairs, const int32_t* pq, double
 bse_status bse_set_timing(bse_system* s, int32_t enable) {
   API_BEGIN
   if (!s) fail(BSE_ERR_ARG, "null system");
+  HIPC(hipStreamSynchronize(s->stream));
   s->timer.on = enable != 0;
+  s->timer.reset();
   API_END
 }
 

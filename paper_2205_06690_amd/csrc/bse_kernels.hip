@@ -1,7 +1,19 @@
-// A-matrix contraction, spectrum and utility kernels for gfx950.
+// Tamm-Dancoff matrix (Eq. 1), dipoles and Lanczos helpers for gfx950.
+//
+// The exchange 2(ia|jb) and direct (ab|W|ij) terms are grid contractions
+// C[m][n] = h^3 sum_r A_m(r) B_n(r) with K = n_g in the thousands to
+// millions and small M, N: split-K GEMMs.  Mixed precision runs them on the
+// BF16 matrix cores with a three-term split (a = a_hi + a_lo, b = b_hi + b_lo,
+// a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation per K chunk,
+// FP64 sum over chunks); FP64 mode uses FP64 FMA.
+#include <hip/hip_runtime.h>
+
 #include "bse_kernels.h"
 
 namespace bse {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // flags[b] = 1 if row b of w has a non-finite value
 __global__ void k_finite_check(const double* __restrict__ w, size_t ng, int* __restrict__ flags) {
@@ -22,6 +34,284 @@ __global__ void k_fill_nan(double* __restrict__ w, size_t n) {
   if (i < n) w[i] = __builtin_nan("");
 }
 
+// out[k][r] = phi_p[r] phi_q[r] for (p, q) = pq[k]
+template <typename T>
+__global__ void k_products(const double* __restrict__ phi, const int* __restrict__ pq, int K,
+                           size_t ng, T* __restrict__ out) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= ng || k >= K) return;
+  const int p = pq[2 * k], q = pq[2 * k + 1];
+  out[(size_t)k * ng + r] = (T)(phi[(size_t)p * ng + r] * phi[(size_t)q * ng + r]);
+}
+
+// ---------------------------------------------------------------------------
+// split-K NT GEMM, BF16x3 on the matrix cores:
+//   part[kc][m][n] = sum_{r in chunk kc} A[m][r] B[n][r]   (A, B FP32 row-major)
+// v_mfma_f32_16x16x32_bf16: lane l supplies row (l%16) of A and column (l%16)
+// of B with the 8 k-values 8(l/16)..8(l/16)+7; result D[4(l/16)+v][l%16].
+// ---------------------------------------------------------------------------
+constexpr int G_BM = 64, G_BN = 64, G_BK = 64, G_KP = 8;  // k padding (bf16)
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(const float* __restrict__ A, int M,
+                                                     const float* __restrict__ B, int N,
+                                                     size_t K, size_t chunk,
+                                                     float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[G_BM][G_BK + G_KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[G_BM][G_BK + G_KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[G_BN][G_BK + G_KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[G_BN][G_BK + G_KP];
+  const int m0 = blockIdx.x * G_BM, n0 = blockIdx.y * G_BN, kc = blockIdx.z;
+  const size_t k0 = (size_t)kc * chunk, k1 = min(K, k0 + chunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  constexpr int NL = G_BM * G_BK / 256;  // 16 floats per thread per operand
+  float ra[NL], rb[NL];
+  auto load = [&](size_t kb) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + i * 256;
+      const int row = e / G_BK, kk = e % G_BK;
+      const size_t k = kb + kk;
+      ra[i] = (m0 + row < M && k < k1) ? A[(size_t)(m0 + row) * K + k] : 0.f;
+      rb[i] = (n0 + row < N && k < k1) ? B[(size_t)(n0 + row) * K + k] : 0.f;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + i * 256;
+      const int row = e / G_BK, kk = e % G_BK;
+      __bf16 h, l;
+      split_bf16(ra[i], h, l);
+      Ah[row][kk] = h;
+      Al[row][kk] = l;
+      split_bf16(rb[i], h, l);
+      Bh[row][kk] = h;
+      Bl[row][kk] = l;
+    }
+  };
+  load(k0);
+  for (size_t kb = k0; kb < k1; kb += G_BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kb + G_BK < k1) load(kb + G_BK);
+#pragma unroll
+    for (int ks = 0; ks < G_BK / 32; ++ks) {
+      const int kk = ks * 32 + 8 * (lane >> 4);
+      bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 32 + i * 16 + (lane & 15);
+        ah[i] = *reinterpret_cast<const bf8*>(&Ah[row][kk]);
+        al[i] = *reinterpret_cast<const bf8*>(&Al[row][kk]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wn * 32 + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf8*>(&Bh[col][kk]);
+        bl[j] = *reinterpret_cast<const bf8*>(&Bl[col][kk]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+  float* out = part + (size_t)kc * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m < M && n < N) out[(size_t)m * N + n] = acc[i][j][v];
+      }
+}
+
+// FP64 split-K NT GEMM (vector FMA), 64x64 tile, 4x4 per thread
+__global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int M,
+                                                  const double* __restrict__ B, int N, size_t K,
+                                                  size_t chunk, double* __restrict__ part) {
+  constexpr int BK = 16;
+  __shared__ double As[BK][G_BM + 1];
+  __shared__ double Bs[BK][G_BN + 1];
+  const int m0 = blockIdx.x * G_BM, n0 = blockIdx.y * G_BN, kc = blockIdx.z;
+  const size_t k0 = (size_t)kc * chunk, k1 = min(K, k0 + chunk);
+  const int tid = threadIdx.x, tm = tid / 16, tn = tid % 16;
+  double acc[4][4] = {};
+  for (size_t kb = k0; kb < k1; kb += BK) {
+    for (int e = tid; e < G_BM * BK; e += 256) {
+      const int row = e / BK, kk = e % BK;
+      const size_t k = kb + kk;
+      As[kk][row] = (m0 + row < M && k < k1) ? A[(size_t)(m0 + row) * K + k] : 0.0;
+      Bs[kk][row] = (n0 + row < N && k < k1) ? B[(size_t)(n0 + row) * K + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)kc * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + tm * 4 + i, n = n0 + tn * 4 + j;
+      if (m < M && n < N) out[(size_t)m * N + n] = acc[i][j];
+    }
+}
+
+template <typename P>
+__global__ void k_part_sum(const P* __restrict__ part, int nchunk, int MN, double scale,
+                           double* __restrict__ C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  double s = 0;
+  for (int k = 0; k < nchunk; ++k) s += (double)part[(size_t)k * MN + i];
+  C[i] = s * scale;
+}
+
+// A[(ia),(jb)] = (e_a - e_i + Delta) d_ij d_ab + 2 X[(ia),(jb)] - D[ab][ij]
+// with D packed over a <= b and i <= j (row-major upper triangles).
+__device__ __forceinline__ int upack(int a, int b, int n) {
+  if (a > b) { const int t = a; a = b; b = t; }
+  return a * n - a * (a - 1) / 2 + (b - a);
+}
+__global__ void k_assemble_a(const double* __restrict__ X, const double* __restrict__ D, int no,
+                             int nc, int nij, const double* __restrict__ eps_v,
+                             const double* __restrict__ eps_c, double scissors,
+                             double* __restrict__ A) {
+  const int n = no * nc;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int row = idx / n, col = idx % n;
+  const int i = row / nc, a = row % nc, j = col / nc, b = col % nc;
+  double v = 2.0 * X[idx] - D[(size_t)upack(a, b, nc) * nij + upack(i, j, no)];
+  if (row == col) v += eps_c[a] - eps_v[i] + scissors;
+  A[idx] = v;
+}
+
+// f0[k][ax] = h^3 sum_r phi_p phi_q (r_ax - centre) for (p, q) = pq[k]
+__global__ void __launch_bounds__(256) k_dipoles(const double* __restrict__ phi,
+                                                 const int* __restrict__ pq, int n, double h,
+                                                 double* __restrict__ f0) {
+  const int k = blockIdx.x;
+  const int p = pq[2 * k], q = pq[2 * k + 1];
+  const size_t ng = (size_t)n * n * n;
+  const double c = 0.5 * n * h;
+  double sx = 0, sy = 0, sz = 0;
+  for (size_t r = threadIdx.x; r < ng; r += 256) {
+    const double v = phi[(size_t)p * ng + r] * phi[(size_t)q * ng + r];
+    const int x = (int)(r / ((size_t)n * n)), y = (int)((r / n) % n), z = (int)(r % n);
+    sx += v * (x * h - c);
+    sy += v * (y * h - c);
+    sz += v * (z * h - c);
+  }
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = sy;
+  red[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) f0[(size_t)k * 3 + a] = red[a][0] * h * h * h;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos helpers (FP64): y = A v; c = V^T w; w -= V c; scalars on the host.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gemv(const double* __restrict__ A, int n,
+                                              const double* __restrict__ v, double* __restrict__ y) {
+  const int row = blockIdx.x;
+  double s = 0;
+  for (int j = threadIdx.x; j < n; j += 256) s += A[(size_t)row * n + j] * v[j];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[row] = red[0];
+}
+
+// c[k] = sum_i V[k][i] w[i], k < m
+__global__ void __launch_bounds__(256) k_vt_w(const double* __restrict__ V, int n, int m,
+                                              const double* __restrict__ w, double* __restrict__ c) {
+  const int k = blockIdx.x;
+  if (k >= m) return;
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) s += V[(size_t)k * n + i] * w[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int q = 128; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c[k] = red[0];
+}
+
+// w[i] -= sum_k c[k] V[k][i]
+__global__ void k_w_minus_vc(const double* __restrict__ V, int n, int m,
+                             const double* __restrict__ c, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0;
+  for (int k = 0; k < m; ++k) s += c[k] * V[(size_t)k * n + i];
+  w[i] -= s;
+}
+
+// out[j] = sum_k V[k][j] s[k]  (Ritz vector), k < m
+__global__ void k_vt_s(const double* __restrict__ V, int n, int m, const double* __restrict__ s,
+                       double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0;
+  for (int k = 0; k < m; ++k) acc += V[(size_t)k * n + j] * s[k];
+  out[j] = acc;
+}
+
+__global__ void k_scale_copy(const double* __restrict__ w, int n, double s, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = w[i] * s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st) {
   hipError_t e = hipMemsetAsync(flags, 0, sizeof(int) * B, st);
   if (e != hipSuccess) return e;
@@ -31,6 +321,85 @@ hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hi
 
 hipError_t launch_fill_nan(double* w, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_products(const double* phi, const int* pq, int K, size_t ng, T* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_products<T>), dim3((unsigned)((ng + 255) / 256), K), dim3(256), 0, st, phi,
+                     pq, K, ng, out);
+  return hipGetLastError();
+}
+template hipError_t launch_products<float>(const double*, const int*, int, size_t, float*, hipStream_t);
+template hipError_t launch_products<double>(const double*, const int*, int, size_t, double*, hipStream_t);
+
+size_t gemm_chunk(int M, int N, size_t K) {
+  const size_t tiles = (size_t)((M + G_BM - 1) / G_BM) * ((N + G_BN - 1) / G_BN);
+  size_t chunk = 4096;
+  while (tiles * ((K + chunk - 1) / chunk) > 4096 && chunk < K) chunk *= 2;
+  return chunk;
+}
+size_t gemm_part_elems(int M, int N, size_t K) {
+  const size_t chunk = gemm_chunk(M, N, K);
+  return ((K + chunk - 1) / chunk) * (size_t)M * N;
+}
+
+hipError_t launch_gemm_bf16x3(const float* A, int M, const float* B, int N, size_t K, double scale,
+                              float* part, double* C, hipStream_t st) {
+  const size_t chunk = gemm_chunk(M, N, K);
+  const int nchunk = (int)((K + chunk - 1) / chunk);
+  dim3 g((M + G_BM - 1) / G_BM, (N + G_BN - 1) / G_BN, nchunk);
+  hipLaunchKernelGGL(k_gemm_bf16x3, g, dim3(256), 0, st, A, M, B, N, K, chunk, part);
+  hipLaunchKernelGGL((k_part_sum<float>), dim3((M * N + 255) / 256), dim3(256), 0, st, part, nchunk,
+                     M * N, scale, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const double* A, int M, const double* B, int N, size_t K, double scale,
+                           double* part, double* C, hipStream_t st) {
+  const size_t chunk = gemm_chunk(M, N, K);
+  const int nchunk = (int)((K + chunk - 1) / chunk);
+  dim3 g((M + G_BM - 1) / G_BM, (N + G_BN - 1) / G_BN, nchunk);
+  hipLaunchKernelGGL(k_gemm_f64, g, dim3(256), 0, st, A, M, B, N, K, chunk, part);
+  hipLaunchKernelGGL((k_part_sum<double>), dim3((M * N + 255) / 256), dim3(256), 0, st, part,
+                     nchunk, M * N, scale, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_a(const double* X, const double* D, int no, int nc, int nij,
+                             const double* eps_v, const double* eps_c, double scissors, double* A,
+                             hipStream_t st) {
+  const int n = no * nc;
+  hipLaunchKernelGGL(k_assemble_a, dim3((n * n + 255) / 256), dim3(256), 0, st, X, D, no, nc, nij,
+                     eps_v, eps_c, scissors, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double h, double* f0,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_dipoles, dim3(K), dim3(256), 0, st, phi, pq, n, h, f0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv, dim3(n), dim3(256), 0, st, A, n, v, y);
+  return hipGetLastError();
+}
+hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_vt_w, dim3(m), dim3(256), 0, st, V, n, m, w, c);
+  hipLaunchKernelGGL(k_w_minus_vc, dim3((n + 255) / 256), dim3(256), 0, st, V, n, m, c, w);
+  return hipGetLastError();
+}
+hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_vt_w, dim3(1), dim3(256), 0, st, a, n, 1, b, out);
+  return hipGetLastError();
+}
+hipError_t launch_ritz(const double* V, int n, int m, const double* s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_vt_s, dim3((n + 255) / 256), dim3(256), 0, st, V, n, m, s, out);
+  return hipGetLastError();
+}
+hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, st, w, n, s, out);
   return hipGetLastError();
 }
 

@@ -65,6 +65,8 @@ template <typename T> struct CleanArgs {
   double dv;
   T* dens;             // [F/L][ng]
   const double* eta0;  // [L][ng] eta_l(0), used at t = 0
+  float* part32;       // FP32 matrix-core partials (mixed precision)
+  cplx<double>* gpart; // partial <E_l, d_f> per block of points
 };
 
 template <typename T> bool grid_supported(int n);

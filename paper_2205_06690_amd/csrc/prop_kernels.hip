@@ -11,6 +11,9 @@
 // multiplier between the forward and inverse halves, inverse y-z planes.
 #include "fft_lines.h"
 #include "prop_kernels.h"
+#include "clean_mfma.h"
+
+#include <type_traits>
 
 namespace bse {
 
@@ -670,25 +673,41 @@ hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
   // 1. end-of-step state and E = Ph H
   hipLaunchKernelGGL((k_clean_finish<T>), pw_grid(a.ng, a.F), dim3(256), 0, st, a.d, a.u, a.H,
                      a.ph, a.eta0, a.E, a.L, a.ng, a.dt, a.from_mid);
-  // 2. coefficients of d against phi_s and E_l, and of E_l against phi_s
-  const int nchunk = (int)((a.ng + a.chunk - 1) / a.chunk);
   const int S = a.S;
-  dim3 g1((a.F + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
-  hipLaunchKernelGGL((k_clean_coef<T>), g1, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L, a.ng,
-                     a.chunk, a.part);
-  hipLaunchKernelGGL(k_clean_reduce, dim3((a.F * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
-                     nchunk, a.F * (S + 1), a.dv, a.coef);
-  dim3 g2((a.L + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
-  hipLaunchKernelGGL((k_clean_coef<T>), g2, dim3(256), 0, st, a.E, a.L, a.phi, S, a.E, a.L, a.ng,
-                     a.chunk, a.part);
-  hipLaunchKernelGGL(k_clean_reduce, dim3((a.L * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
-                     nchunk, a.L * (S + 1), a.dv, a.coefE);
-  hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
-                     a.coefE, a.n0, a.L, a.renorm);
-  // 3. update and new density
-  dim3 g3((unsigned)((a.ng + 63) / 64), (a.F + 15) / 16);
-  hipLaunchKernelGGL((k_clean_update<T>), g3, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L,
-                     a.ng, a.coef);
+  if constexpr (std::is_same<T, float>::value) {
+    // 2. coefficients on the matrix cores, <E_l, d_f> by a reduction
+    hipError_t e = launch_coef_mfma(a.d, a.F, a.phi, S, a.ng, a.chunk, a.part32, a.dv, a.coef, st);
+    if (e != hipSuccess) return e;
+    e = launch_edot(a.d, a.E, a.F, a.L, S, a.ng, a.gpart, a.dv, a.coef, st);
+    if (e != hipSuccess) return e;
+    e = launch_coef_mfma(a.E, a.L, a.phi, S, a.ng, a.chunk, a.part32, a.dv, a.coefE, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
+                       a.coefE, a.n0, a.L, a.renorm);
+    // 3. update on the matrix cores
+    e = launch_update_mfma(a.d, a.F, a.phi, S, a.E, a.L, a.ng, a.coef, a.part32, st);
+    if (e != hipSuccess) return e;
+  } else {
+    // 2. coefficients of d against phi_s and E_l, and of E_l against phi_s
+    const int nchunk = (int)((a.ng + a.chunk - 1) / a.chunk);
+    dim3 g1((a.F + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
+    hipLaunchKernelGGL((k_clean_coef<T>), g1, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L, a.ng,
+                       a.chunk, a.part);
+    hipLaunchKernelGGL(k_clean_reduce, dim3((a.F * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
+                       nchunk, a.F * (S + 1), a.dv, a.coef);
+    dim3 g2((a.L + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
+    hipLaunchKernelGGL((k_clean_coef<T>), g2, dim3(256), 0, st, a.E, a.L, a.phi, S, a.E, a.L, a.ng,
+                       a.chunk, a.part);
+    hipLaunchKernelGGL(k_clean_reduce, dim3((a.L * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
+                       nchunk, a.L * (S + 1), a.dv, a.coefE);
+    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
+                       a.coefE, a.n0, a.L, a.renorm);
+    // 3. update
+    dim3 g3((unsigned)((a.ng + 63) / 64), (a.F + 15) / 16);
+    hipLaunchKernelGGL((k_clean_update<T>), g3, dim3(256), 0, st, a.d, a.F, a.phi, S, a.E, a.L,
+                       a.ng, a.coef);
+  }
+  // 4. density of the cleaned state
   hipLaunchKernelGGL((k_density_end<T>), pw_grid(a.ng, a.F / a.L), dim3(256), 0, st, a.d, a.E,
                      a.L, a.ng, a.dens);
   return hipGetLastError();

@@ -296,6 +296,76 @@ def eigensolve(v_ext: np.ndarray, h: float, n_states: int, *, tol: float = 1e-9,
     return np.ascontiguousarray(phi), eps
 
 
+def eigensolve_torch(v_ext: np.ndarray, h: float, n_states: int, *, tol: float = 1e-9,
+                     seed: int = 12345, max_iter: int = 200, deg: int = 16, device: str = "cuda",
+                     verbose: bool = False):
+    """The same Chebyshev-filtered subspace iteration as ``eigensolve``, with
+    the FP64 FFTs and tall-skinny products on a GPU through torch (input
+    preparation only; small dense steps stay on the host in numpy)."""
+    import torch
+    n = v_ext.shape[0]
+    ng = v_ext.size
+    dev = torch.device(device)
+    vt = torch.from_numpy(np.ascontiguousarray(v_ext.reshape(-1))).to(dev)
+    tk = torch.from_numpy(_k2half_rfft(n, h)).to(dev)
+    shape = v_ext.shape
+
+    def H(X):
+        m = X.shape[0]
+        F = torch.fft.rfftn(X.reshape((m,) + shape), dim=(1, 2, 3))
+        F *= tk
+        Y = torch.fft.irfftn(F, s=shape, dim=(1, 2, 3)).reshape(m, ng)
+        return Y + vt * X
+
+    def cholqr(Y):
+        for _ in range(2):
+            S = (Y @ Y.T).cpu().numpy()
+            Li = np.linalg.inv(np.linalg.cholesky(S))
+            Y = torch.from_numpy(Li).to(dev) @ Y
+        return Y
+
+    m = n_states + max(16, n_states // 2)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    X = cholqr(torch.randn((m, ng), dtype=torch.float64, generator=g).to(dev))
+    HX = H(X)
+    w, U = np.linalg.eigh((X @ HX.T).cpu().numpy())
+    X = torch.from_numpy(U.T.copy()).to(dev) @ X
+    b = float(3.0 * (math.pi / h) ** 2 / 2.0) + float(v_ext.max())
+    a, a0 = float(w[-1]), float(w[0])
+    for it in range(max_iter):
+        e = (b - a) / 2.0
+        c = (b + a) / 2.0
+        sigma = e / (a0 - c)
+        tau = 2.0 / sigma
+        Y = (H(X) - c * X) * (sigma / e)
+        Xp = X
+        for _ in range(2, deg + 1):
+            sn = 1.0 / (tau - sigma)
+            Yn = (H(Y) - c * Y) * (2.0 * sn / e) - (sigma * sn) * Xp
+            Xp, Y, sigma = Y, Yn, sn
+        X = cholqr(Y)
+        HX = H(X)
+        S = (X @ HX.T).cpu().numpy()
+        w, U = np.linalg.eigh(0.5 * (S + S.T))
+        Ut = torch.from_numpy(U.T.copy()).to(dev)
+        X = Ut @ X
+        HX = Ut @ HX
+        wt = torch.from_numpy(w[:n_states].copy()).to(dev)
+        res = float(torch.linalg.norm(HX[:n_states] - wt[:, None] * X[:n_states], dim=1).max())
+        if verbose:
+            print(f"chefsi(gpu) it {it} res {res:.3e}", flush=True)
+        a0, a = float(w[0]), float(w[-1])
+        if res < tol:
+            break
+    else:
+        raise RuntimeError(f"eigensolve did not converge (res {res:.3e})")
+    Xh = X[:n_states].cpu().numpy()
+    idx = np.argmax(np.abs(Xh), axis=1)
+    sgn = np.sign(Xh[np.arange(Xh.shape[0]), idx])
+    phi = (Xh * sgn[:, None]) / math.sqrt(h ** 3)
+    return np.ascontiguousarray(phi), w[:n_states].copy()
+
+
 # --------------------------------------------------------------------------
 # random signs of the stochastic orbitals
 # --------------------------------------------------------------------------
@@ -359,10 +429,20 @@ def cache_dir() -> str:
     return d
 
 
+def _gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
 def make_system(spec: SystemSpec, *, n_states: Optional[int] = None, tol: float = 1e-9,
-                use_cache: bool = True, verbose: bool = False):
+                use_cache: bool = True, verbose: bool = False, use_gpu: Optional[bool] = None):
     """Return dict(v_ext, phi, eps, xi) for ``spec`` (FP64; phi has
-    ``n_states`` (default n_occ + n_c) rows)."""
+    ``n_states`` (default n_occ + n_c) rows).  Grids above 10^5 points are
+    solved with torch on a GPU when one is present (input preparation
+    only), else on the CPU."""
     n_states = spec.n_orb if n_states is None else n_states
     v = make_vext(spec)
     key = f"{spec.key()}_{n_states}_{tol:g}"
@@ -375,7 +455,12 @@ def make_system(spec: SystemSpec, *, n_states: Optional[int] = None, tol: float 
         except Exception:
             phi = eps = None
     if phi is None:
-        phi, eps = eigensolve(v, spec.h, n_states, tol=tol, verbose=verbose)
+        if use_gpu is None:
+            use_gpu = spec.ng > 100000 and _gpu_available()
+        if use_gpu:
+            phi, eps = eigensolve_torch(v, spec.h, n_states, tol=tol, verbose=verbose)
+        else:
+            phi, eps = eigensolve(v, spec.h, n_states, tol=tol, verbose=verbose)
         if use_cache:
             tmp = path + f".tmp{os.getpid()}.npz"
             np.savez(tmp, phi=phi, eps=eps)
