@@ -143,8 +143,10 @@ struct bse_system {
   int nchunk = 0;
   // A / spectrum state
   int a_no = 0, a_nc = 0;
-  DBuf wij;       // [n_ij][ng] FP64
-  std::vector<double> A;
+  DBuf wij;       // [n_ij][ng] FP64 W_ij of the valence pairs
+  DBuf A_d;       // [(n_o n_c)^2] FP64
+  DBuf f0_d;      // [n_o n_c][3] dipoles
+  DBuf lz_V, lz_w, lz_c, lz_s;  // Lanczos basis and scratch
   Timer timer;
   std::vector<double> wts;
 };
@@ -462,6 +464,268 @@ void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev
   if (any_bad) fail(BSE_ERR_NUMERIC, "non-finite W for some pairs");
 }
 
+// ---------------------------------------------------------------------------
+// Tamm-Dancoff matrix (Eq. 1)
+// ---------------------------------------------------------------------------
+void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
+  check_ready(s);
+  const int n_occ = s->cfg.n_occ;
+  if (n_o < 1 || n_o > n_occ || n_c < 1 || n_occ + n_c > s->n_orb || !A_host)
+    fail(BSE_ERR_ARG, "bse_build_A: need 1 <= n_o <= n_occ and n_occ + n_c <= n_orb");
+  const size_t ng = s->ng;
+  const int v0 = n_occ - n_o, c0 = n_occ;
+  const int n_ij = n_o * (n_o + 1) / 2, n_ia = n_o * n_c, n_ab = n_c * (n_c + 1) / 2;
+  std::vector<int> pij, pia, pab;
+  for (int i = 0; i < n_o; ++i)
+    for (int j = i; j < n_o; ++j) { pij.push_back(v0 + i); pij.push_back(v0 + j); }
+  for (int i = 0; i < n_o; ++i)
+    for (int a = 0; a < n_c; ++a) { pia.push_back(v0 + i); pia.push_back(c0 + a); }
+  for (int a = 0; a < n_c; ++a)
+    for (int b = a; b < n_c; ++b) { pab.push_back(c0 + a); pab.push_back(c0 + b); }
+  hipStream_t st = s->stream;
+  // 1. W_ij for the valence pairs (kept on the device)
+  s->wij.alloc(sizeof(double) * ng * n_ij);
+  apply_w_device(s, n_ij, pij.data(), s->wij.as<double>(), nullptr, nullptr);
+  DBuf pq;
+  pq.alloc(sizeof(int) * 2 * (size_t)std::max(std::max(n_ia, n_ab), n_ij));
+  const bool fp64 = s->cfg.precision == BSE_FP64;
+  DBuf X, Dm, part, rho64, v64, rho32, v32;
+  X.alloc(sizeof(double) * (size_t)n_ia * n_ia);
+  Dm.alloc(sizeof(double) * (size_t)n_ab * n_ij);
+  const size_t pe = std::max(gemm_part_elems(n_ia, n_ia, ng), gemm_part_elems(n_ab, n_ij, ng));
+  part.alloc(pe * (fp64 ? sizeof(double) : sizeof(float)));
+  // 2. exchange (ia|jb): Coulomb potentials of rho_jb in FP64, then the grid GEMM
+  HIPC(hipMemcpyAsync(pq.p, pia.data(), sizeof(int) * 2 * n_ia, hipMemcpyHostToDevice, st));
+  rho64.alloc(sizeof(double) * ng * n_ia);
+  v64.alloc(sizeof(double) * ng * n_ia);
+  HIPC(launch_products<double>(s->phi64.as<double>(), pq.as<int>(), n_ia, ng, rho64.as<double>(), st));
+  const int PB = 64;
+  for (int k0 = 0; k0 < n_ia; k0 += PB) {
+    const int B = std::min(PB, n_ia - k0);
+    poisson64(s, rho64.as<double>() + (size_t)k0 * ng, B, v64.as<double>() + (size_t)k0 * ng,
+              nullptr, 0.0);
+  }
+  if (fp64) {
+    HIPC(launch_gemm_f64(rho64.as<double>(), n_ia, v64.as<double>(), n_ia, ng, s->dv,
+                         part.as<double>(), X.as<double>(), st));
+  } else {
+    rho32.alloc(sizeof(float) * ng * n_ia);
+    v32.alloc(sizeof(float) * ng * n_ia);
+    HIPC(launch_to_real<float>(rho64.as<double>(), ng * n_ia, rho32.as<float>(), st));
+    HIPC(launch_to_real<float>(v64.as<double>(), ng * n_ia, v32.as<float>(), st));
+    HIPC(launch_gemm_bf16x3(rho32.as<float>(), n_ia, v32.as<float>(), n_ia, ng, s->dv,
+                            part.as<float>(), X.as<double>(), st));
+  }
+  // 3. direct (ab|W|ij) over a <= b and i <= j
+  HIPC(hipStreamSynchronize(st));
+  HIPC(hipMemcpyAsync(pq.p, pab.data(), sizeof(int) * 2 * n_ab, hipMemcpyHostToDevice, st));
+  if (fp64) {
+    DBuf rab;
+    rab.alloc(sizeof(double) * ng * n_ab);
+    HIPC(launch_products<double>(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, rab.as<double>(), st));
+    HIPC(launch_gemm_f64(rab.as<double>(), n_ab, s->wij.as<double>(), n_ij, ng, s->dv,
+                         part.as<double>(), Dm.as<double>(), st));
+    HIPC(hipStreamSynchronize(st));
+  } else {
+    DBuf rab, w32;
+    rab.alloc(sizeof(float) * ng * n_ab);
+    w32.alloc(sizeof(float) * ng * n_ij);
+    HIPC(launch_products<float>(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, rab.as<float>(), st));
+    HIPC(launch_to_real<float>(s->wij.as<double>(), ng * n_ij, w32.as<float>(), st));
+    HIPC(launch_gemm_bf16x3(rab.as<float>(), n_ab, w32.as<float>(), n_ij, ng, s->dv,
+                            part.as<float>(), Dm.as<double>(), st));
+    HIPC(hipStreamSynchronize(st));
+  }
+  // 4. assemble
+  DBuf ev, ec;
+  ev.alloc(sizeof(double) * n_o);
+  ec.alloc(sizeof(double) * n_c);
+  HIPC(hipMemcpyAsync(ev.p, s->eps.data() + v0, sizeof(double) * n_o, hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(ec.p, s->eps.data() + c0, sizeof(double) * n_c, hipMemcpyHostToDevice, st));
+  s->A_d.alloc(sizeof(double) * (size_t)n_ia * n_ia);
+  HIPC(launch_assemble_a(X.as<double>(), Dm.as<double>(), n_o, n_c, n_ij, ev.as<double>(),
+                         ec.as<double>(), s->cfg.scissors, s->A_d.as<double>(), st));
+  // dipoles of the transitions for the spectrum
+  HIPC(hipMemcpyAsync(pq.p, pia.data(), sizeof(int) * 2 * n_ia, hipMemcpyHostToDevice, st));
+  s->f0_d.alloc(sizeof(double) * 3 * n_ia);
+  HIPC(launch_dipoles(s->phi64.as<double>(), pq.as<int>(), n_ia, s->n, s->cfg.h, s->f0_d.as<double>(), st));
+  HIPC(hipMemcpyAsync(A_host, s->A_d.p, sizeof(double) * (size_t)n_ia * n_ia, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  s->a_no = n_o;
+  s->a_nc = n_c;
+}
+
+// ---------------------------------------------------------------------------
+// symmetric tridiagonal eigenpairs (host, FP64): Sturm-count bisection for
+// the k lowest eigenvalues, inverse iteration for their vectors
+// ---------------------------------------------------------------------------
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int m, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    const double qq = (std::fabs(q) < 1e-300) ? 1e-300 : q;
+    q = a[i] - x - b[i - 1] * b[i - 1] / qq;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+void tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, int m, int k,
+                    std::vector<double>& theta, std::vector<std::vector<double>>& vecs) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const double span = std::max(hi - lo, 1e-30);
+  theta.assign(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double l = lo - 1e-12 * span, h = hi + 1e-12 * span;
+    for (int it = 0; it < 200 && h - l > 1e-15 * std::max(1.0, std::fabs(l) + std::fabs(h)); ++it) {
+      const double mid = 0.5 * (l + h);
+      if (sturm_count(a, b, m, mid) > j) h = mid; else l = mid;
+    }
+    theta[j] = 0.5 * (l + h);
+  }
+  vecs.assign(k, std::vector<double>(m, 0.0));
+  uint64_t seed = 977;
+  for (int j = 0; j < k; ++j) {
+    std::vector<double>& y = vecs[j];
+    for (int i = 0; i < m; ++i) {
+      seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+      y[i] = ((seed >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    }
+    const double sh = theta[j] + 1e-13 * span;
+    for (int it = 0; it < 4; ++it) {
+      // solve (T - sh I) z = y by Gaussian elimination with partial pivoting
+      std::vector<double> dl(m), d(m), du(m), du2(m, 0.0), z = y;
+      for (int i = 0; i < m; ++i) { d[i] = a[i] - sh; if (i < m - 1) { du[i] = b[i]; dl[i] = b[i]; } }
+      std::vector<int> piv(m, 0);
+      for (int i = 0; i < m - 1; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+          if (d[i] == 0.0) d[i] = 1e-300;
+          const double f = dl[i] / d[i];
+          dl[i] = f;
+          d[i + 1] -= f * du[i];
+        } else {
+          const double f = d[i] / dl[i];
+          d[i] = dl[i];
+          dl[i] = f;
+          const double t = du[i];
+          du[i] = d[i + 1];
+          d[i + 1] = t - f * d[i + 1];
+          if (i < m - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
+          piv[i] = 1;
+        }
+      }
+      if (d[m - 1] == 0.0) d[m - 1] = 1e-300;
+      for (int i = 0; i < m - 1; ++i) {
+        if (piv[i]) { const double t = z[i]; z[i] = z[i + 1]; z[i + 1] = t - dl[i] * z[i + 1]; }
+        else z[i + 1] -= dl[i] * z[i];
+      }
+      z[m - 1] /= d[m - 1];
+      if (m > 1) z[m - 2] = (z[m - 2] - du[m - 2] * z[m - 1]) / d[m - 2];
+      for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / d[i];
+      // orthogonalise against earlier vectors (degenerate clusters)
+      for (int q = 0; q < j; ++q) {
+        double c = 0;
+        for (int i = 0; i < m; ++i) c += vecs[q][i] * z[i];
+        for (int i = 0; i < m; ++i) z[i] -= c * vecs[q][i];
+      }
+      double nrm = 0;
+      for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
+      nrm = std::sqrt(nrm);
+      for (int i = 0; i < m; ++i) y[i] = z[i] / nrm;
+    }
+  }
+}
+
+// Lanczos with full re-orthogonalisation on the device copy of A
+void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, const double* w_grid,
+              double sig, double* sigma) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_spectrum: call bse_build_A first");
+  const int n = s->a_no * s->a_nc;
+  if (n_exc < 1 || n_exc > n || !omega || !dip2 || n_w < 0 || (n_w > 0 && (!w_grid || !sigma || !(sig > 0))))
+    fail(BSE_ERR_ARG, "bse_spectrum: bad arguments");
+  hipStream_t st = s->stream;
+  s->lz_V.alloc(sizeof(double) * (size_t)(n + 1) * n);
+  s->lz_w.alloc(sizeof(double) * n);
+  s->lz_c.alloc(sizeof(double) * (n + 1));
+  s->lz_s.alloc(sizeof(double) * (n + 1));
+  double* V = s->lz_V.as<double>();
+  double* w = s->lz_w.as<double>();
+  double* c = s->lz_c.as<double>();
+  // deterministic start vector (SplitMix64 draws in [-1, 1))
+  std::vector<double> v0(n);
+  double nr = 0;
+  for (int i = 0; i < n; ++i) {
+    v0[i] = (double)(splitmix64_draw(0x5EED5EEDULL, i) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    nr += v0[i] * v0[i];
+  }
+  for (int i = 0; i < n; ++i) v0[i] /= std::sqrt(nr);
+  HIPC(hipMemcpyAsync(V, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  std::vector<double> alpha, beta;
+  std::vector<double> theta;
+  std::vector<std::vector<double>> svec;
+  double anorm = 0;
+  int m = 0;
+  for (int k = 0; k < n; ++k) {
+    HIPC(launch_gemv(s->A_d.as<double>(), n, V + (size_t)k * n, w, st));
+    // two passes of classical Gram-Schmidt against the whole basis
+    HIPC(launch_reorth(V, n, k + 1, c, w, st));
+    double a_k = 0;
+    HIPC(hipMemcpyAsync(&a_k, c + k, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(launch_reorth(V, n, k + 1, c, w, st));
+    double bb = 0;
+    HIPC(launch_dot(w, w, n, c, st));
+    HIPC(hipMemcpyAsync(&bb, c, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    alpha.push_back(a_k);
+    const double b_k = std::sqrt(std::max(bb, 0.0));
+    anorm = std::max(anorm, std::fabs(a_k) + b_k);
+    m = k + 1;
+    const bool breakdown = b_k < 1e-13 * std::max(anorm, 1e-300);
+    const bool check = m >= n_exc && ((m - n_exc) % 10 == 0 || m == n || breakdown);
+    if (check) {
+      tridiag_lowest(alpha, beta, m, std::min(n_exc, m), theta, svec);
+      bool conv = m >= n_exc;
+      for (int j = 0; j < (int)theta.size() && conv; ++j)
+        if (b_k * std::fabs(svec[j][m - 1]) > 1e-10 * std::max(anorm, 1.0)) conv = false;
+      if (conv || m == n || breakdown) break;
+    }
+    if (breakdown || m == n) break;
+    beta.push_back(b_k);
+    HIPC(launch_scale_copy(w, n, 1.0 / b_k, V + (size_t)(k + 1) * n, st));
+  }
+  if ((int)theta.size() < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
+  // Ritz vectors and dipole strengths
+  std::vector<double> f0(3 * (size_t)n), x(n);
+  HIPC(hipMemcpyAsync(f0.data(), s->f0_d.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st));
+  for (int j = 0; j < n_exc; ++j) {
+    HIPC(hipMemcpyAsync(s->lz_s.p, svec[j].data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    HIPC(launch_ritz(V, n, m, s->lz_s.as<double>(), w, st));
+    HIPC(hipMemcpyAsync(x.data(), w, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    omega[j] = theta[j];
+    for (int ax = 0; ax < 3; ++ax) {
+      double d = 0;
+      for (int i = 0; i < n; ++i) d += x[i] * f0[(size_t)i * 3 + ax];
+      dip2[(size_t)j * 3 + ax] = d * d;
+    }
+  }
+  for (int q = 0; q < n_w; ++q) {
+    double acc = 0;
+    for (int j = 0; j < n_exc; ++j) {
+      const double z = (w_grid[q] - omega[j]) / sig;
+      acc += (dip2[3 * j] + dip2[3 * j + 1] + dip2[3 * j + 2]) * std::exp(-0.5 * z * z);
+    }
+    sigma[q] = w_grid[q] * acc / (sig * std::sqrt(2.0 * M_PI));
+  }
+}
+
 #define API_BEGIN try {
 #define API_END                 \
   }                             \
@@ -662,16 +926,14 @@ int32_t bse_kernel_times(bse_system* s, int32_t cap, const char** names, double*
 
 bse_status bse_build_A(bse_system* s, int32_t n_o, int32_t n_c, double* A) {
   API_BEGIN
-  (void)s; (void)n_o; (void)n_c; (void)A;
-  fail(BSE_ERR_STATE, "bse_build_A: not available in this build");
+  build_a(s, n_o, n_c, A);
   API_END
 }
 
 bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
                         const double* w_grid, double sigma_broad, double* sigma) {
   API_BEGIN
-  (void)s; (void)n_exc; (void)omega; (void)dip2; (void)n_w; (void)w_grid; (void)sigma_broad; (void)sigma;
-  fail(BSE_ERR_STATE, "bse_spectrum: not available in this build");
+  spectrum(s, n_exc, omega, dip2, n_w, w_grid, sigma_broad, sigma);
   API_END
 }
 

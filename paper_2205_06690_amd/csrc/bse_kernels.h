@@ -6,4 +6,23 @@
 namespace bse {
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st);
 hipError_t launch_fill_nan(double* w, size_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_products(const double* phi, const int* pq, int K, size_t ng, T* out, hipStream_t st);
+size_t gemm_chunk(int M, int N, size_t K);
+size_t gemm_part_elems(int M, int N, size_t K);
+// C[m][n] = scale * sum_r A[m][r] B[n][r]
+hipError_t launch_gemm_bf16x3(const float* A, int M, const float* B, int N, size_t K, double scale,
+                              float* part, double* C, hipStream_t st);
+hipError_t launch_gemm_f64(const double* A, int M, const double* B, int N, size_t K, double scale,
+                           double* part, double* C, hipStream_t st);
+hipError_t launch_assemble_a(const double* X, const double* D, int no, int nc, int nij,
+                             const double* eps_v, const double* eps_c, double scissors, double* A,
+                             hipStream_t st);
+hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double h, double* f0,
+                          hipStream_t st);
+hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st);
+hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st);
+hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);
+hipError_t launch_ritz(const double* V, int n, int m, const double* s, double* out, hipStream_t st);
+hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipStream_t st);
 }  // namespace bse

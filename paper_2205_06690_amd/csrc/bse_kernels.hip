@@ -214,7 +214,9 @@ __global__ void k_assemble_a(const double* __restrict__ X, const double* __restr
   if (idx >= n * n) return;
   const int row = idx / n, col = idx % n;
   const int i = row / nc, a = row % nc, j = col / nc, b = col % nc;
-  double v = 2.0 * X[idx] - D[(size_t)upack(a, b, nc) * nij + upack(i, j, no)];
+  // (ia|jb) = (jb|ia): the two computed copies are averaged, so A is
+  // symmetric to the last bit whatever the rounding of the contraction
+  double v = (X[idx] + X[(size_t)col * n + row]) - D[(size_t)upack(a, b, nc) * nij + upack(i, j, no)];
   if (row == col) v += eps_c[a] - eps_v[i] + scissors;
   A[idx] = v;
 }
