@@ -336,7 +336,7 @@ void propagate_batch(bse_system* s, const int* pq_host, int B) {
     px.L = L;
     px.mode = half ? PX_HALF : PX_FULL;
     auto* t1 = s->timer.begin("prop_x");
-    HIPC(launch_prop_x<T>(s->n, px, F, st));
+    HIPC(launch_prop_x<T>(s->n, px, B, st));
     s->timer.end(t1);
     PropYZArgs<T> pz{};
     pz.d = s->d.as<C>();

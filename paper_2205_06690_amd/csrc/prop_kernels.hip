@@ -23,62 +23,105 @@ namespace bse {
 // mode PX_ETA0: out = Pf * in                                  (unperturbed set)
 // mode PX_FULL: out = Pf * (d - i dt u_b H_l)                  (mid-step state)
 // mode PX_HALF: out = Ph * (d - i dt/2 u_b (Ph H_l))           (cleaned end state)
+// The pair variant (ETA = false) runs one block per (tile, pair) over the L
+// orbitals of the pair: u_b and the phase tile stay in registers, and the
+// loads of orbital l+1 are in flight while orbital l is transformed.
 template <int N, int TC, typename T>
-__global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
+__device__ __forceinline__ void kinetic_x_tile(cplx<T>* s, const cplx<T>* __restrict__ tw,
+                                               const cplx<T>* __restrict__ kp, int tid, int nthr) {
   using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* s = reinterpret_cast<C*>(smem_raw);
-  const int ng = N * N * N;
-  const int tile = blockIdx.x;
-  const int f = blockIdx.y;
-  const int b = f / a.L, l = f % a.L;
-  const int c0 = tile * TC;
-  const C* __restrict__ din = a.din + (size_t)f * ng;
-  C* __restrict__ dout = a.dout + (size_t)f * ng;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int e = tid; e < N * TC; e += nthr) {
-    const int x = e / TC, c = e % TC;
-    const size_t g = (size_t)x * N * N + c0 + c;
-    C v = din[g];
-    if (a.mode == PX_ETA0) {
-      v = cmul(a.pf[g], v);
-    } else {
-      const T uu = a.u[(size_t)b * ng + g];
-      C h = a.H[(size_t)l * ng + g];
-      if (a.mode == PX_FULL) {
-        // d - i dt u h
-        const T cu = a.dt * uu;
-        v = cmk<C>(v.x + cu * h.y, v.y - cu * h.x);
-        v = cmul(a.pf[g], v);
-      } else {
-        const C ph = a.ph[g];
-        h = cmul(ph, h);
-        const T cu = (T)0.5 * a.dt * uu;
-        v = cmk<C>(v.x + cu * h.y, v.y - cu * h.x);
-        v = cmul(ph, v);
-      }
-    }
-    s[x * TC + c] = v;
-  }
+  stageA_fwd<N>(s, TC, 1, TC, tw, tid, nthr, true);
   __syncthreads();
-  stageA_fwd<N>(s, TC, 1, TC, a.tw, tid, nthr, true);
-  __syncthreads();
-  const C* __restrict__ kp = a.kph;
-  stageB<N, 2>(s, TC, 1, TC, a.tw, tid, nthr, true,
+  stageB<N, 2>(s, TC, 1, TC, tw, tid, nthr, true,
                [kp](int, C v, int k) { return cmul(v, kp[k]); });
   __syncthreads();
   stageC_inv<N>(s, TC, 1, TC, tid, nthr, true);
   __syncthreads();
-  for (int e = tid; e < N * TC; e += nthr) {
-    const int x = e / TC, c = e % TC;
-    dout[(size_t)x * N * N + c0 + c] = s[x * TC + c];
+}
+
+template <int N, int TC, typename T, bool ETA>
+__global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int NTH = 256;
+  constexpr int PER = N * TC / NTH;
+  static_assert(N * TC % NTH == 0, "tile must divide the block");
+  const int ng = N * N * N;
+  const int c0 = blockIdx.x * TC;
+  const int tid = threadIdx.x;
+  if (ETA) {
+    const int f = blockIdx.y;
+    const C* __restrict__ din = a.din + (size_t)f * ng;
+    C* __restrict__ dout = a.dout + (size_t)f * ng;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTH;
+      const int x = e / TC, c = e % TC;
+      const size_t g = (size_t)x * N * N + c0 + c;
+      s[x * TC + c] = cmul(a.pf[g], din[g]);
+    }
+    __syncthreads();
+    kinetic_x_tile<N, TC, T>(s, a.tw, a.kph, tid, NTH);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTH;
+      const int x = e / TC, c = e % TC;
+      dout[(size_t)x * N * N + c0 + c] = s[x * TC + c];
+    }
+    return;
+  }
+  const int b = blockIdx.y;
+  const bool half = a.mode == PX_HALF;
+  const T cu = half ? (T)0.5 * a.dt : a.dt;
+  const C* __restrict__ ptab = half ? a.ph : a.pf;
+  T uu[PER];
+  C dn[PER], hn[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NTH;
+    const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
+    uu[i] = cu * a.u[(size_t)b * ng + g];
+    dn[i] = a.din[((size_t)b * a.L) * ng + g];
+    hn[i] = a.H[g];
+  }
+  for (int l = 0; l < a.L; ++l) {
+    const size_t fo = ((size_t)b * a.L + l) * ng;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTH;
+      const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
+      const C p = ptab[g];
+      C h = hn[i];
+      if (half) h = cmul(p, h);
+      C v = cmk<C>(dn[i].x + uu[i] * h.y, dn[i].y - uu[i] * h.x);
+      s[e] = cmul(p, v);
+    }
+    __syncthreads();
+    if (l + 1 < a.L) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NTH;
+        const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
+        dn[i] = a.din[fo + ng + g];
+        hn[i] = a.H[(size_t)(l + 1) * ng + g];
+      }
+    }
+    kinetic_x_tile<N, TC, T>(s, a.tw, a.kph, tid, NTH);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTH;
+      a.dout[fo + (size_t)(e / TC) * N * N + c0 + (e % TC)] = s[e];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // prop_yz: y and z factors of exp(-iT dt) on a whole y-z plane, plus the
 // induced density dn_b = 4 sum_l Re(conj(H_l) d_{b,l}) of the post-kinetic
-// state (linearised Eq. 11 source).
+// state (linearised Eq. 11 source).  The pair variant loops over the L
+// orbitals with the next plane's loads in flight during the transform.
 // ---------------------------------------------------------------------------
 template <int N, typename T, int NT>
 __device__ __forceinline__ void kinetic_yz_plane(cplx<T>* s, const cplx<T>* __restrict__ tw,
@@ -101,19 +144,19 @@ __device__ __forceinline__ void kinetic_yz_plane(cplx<T>* s, const cplx<T>* __re
   __syncthreads();
 }
 
-template <int N, typename T, int NT>
+template <int N, typename T, int NT, bool DENS>
 __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int P = N * N;
   constexpr int PER = (P + NT - 1) / NT;
+  constexpr bool PREF_H = PER <= 8;
   const int ng = N * N * N;
   const int x = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t poff = (size_t)x * P;
-  if (!a.density) {
-    // unperturbed set: field blockIdx.y, kinetic only
+  if (!DENS) {
     C* d = a.d + (size_t)blockIdx.y * ng + poff;
     for (int e = tid; e < P; e += NT) s[e] = d[e];
     __syncthreads();
@@ -123,31 +166,57 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
   }
   const int b = blockIdx.y;
   T acc[PER];
+  C dn[PER];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) acc[i] = 0;
+  for (int i = 0; i < PER; ++i) {
+    acc[i] = 0;
+    const int e = tid + i * NT;
+    if (e < P) dn[i] = a.d[((size_t)b * a.L) * ng + poff + e];
+  }
   for (int l = 0; l < a.L; ++l) {
     C* d = a.d + ((size_t)b * a.L + l) * ng + poff;
     const C* __restrict__ h = a.H + (size_t)l * ng + poff;
-    for (int e = tid; e < P; e += NT) s[e] = d[e];
+    C hc[PREF_H ? PER : 1];
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < P) s[e] = dn[i];
+    }
+    __syncthreads();
+    // loads of the next orbital and of this orbital's unperturbed plane are
+    // in flight during the transform
+    if (l + 1 < a.L) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < P) dn[i] = d[ng + e];
+      }
+    }
+    if (PREF_H) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * NT;
+        if (e < P) hc[PREF_H ? i : 0] = h[e];
+      }
+    }
     kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + i * NT;
       if (e < P) {
         const C v = s[e];
-        const C hh = h[e];
+        const C hh = PREF_H ? hc[PREF_H ? i : 0] : h[e];
         d[e] = v;
         acc[i] += hh.x * v.x + hh.y * v.y;
       }
     }
-    __syncthreads();
   }
-  T* dn = a.dens + (size_t)b * ng + poff;
+  T* dn_out = a.dens + (size_t)b * ng + poff;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = tid + i * NT;
-    if (e < P) dn[e] = (T)4 * acc[i];
+    if (e < P) dn_out[e] = (T)4 * acc[i];
   }
 }
 
@@ -561,21 +630,28 @@ __global__ void k_to_real(const double* __restrict__ in, size_t n, T* __restrict
 // host launchers
 // ---------------------------------------------------------------------------
 template <int N> constexpr int yz_threads() { return N >= 64 ? 512 : 256; }
-template <int N> constexpr int x_tc() { return N >= 64 ? 32 : 16; }
+template <int N> constexpr int x_tc() { return N <= 16 ? 16 : 32; }
 
 template <int N, typename T>
 struct Launch {
+  // F: fields (unperturbed set) or pairs (perturbed set)
   static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st) {
     constexpr int TC = x_tc<N>();
     dim3 grid(N * N / TC, F);
     size_t sm = sizeof(cplx<T>) * N * TC;
-    hipLaunchKernelGGL((k_prop_x<N, TC, T>), grid, dim3(256), sm, st, a);
+    if (a.mode == PX_ETA0)
+      hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
+    else
+      hipLaunchKernelGGL((k_prop_x<N, TC, T, false>), grid, dim3(256), sm, st, a);
     return hipGetLastError();
   }
   static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st) {
     constexpr int NT = yz_threads<N>();
     size_t sm = sizeof(cplx<T>) * N * N;
-    hipLaunchKernelGGL((k_prop_yz<N, T, NT>), dim3(N, nb), dim3(NT), sm, st, a);
+    if (a.density)
+      hipLaunchKernelGGL((k_prop_yz<N, T, NT, true>), dim3(N, nb), dim3(NT), sm, st, a);
+    else
+      hipLaunchKernelGGL((k_prop_yz<N, T, NT, false>), dim3(N, nb), dim3(NT), sm, st, a);
     return hipGetLastError();
   }
   static hipError_t poisson(const PoisArgs<T>& a, hipStream_t st) {
@@ -594,10 +670,12 @@ struct Launch {
     constexpr int TC = x_tc<N>();
     const int smp = (int)(sizeof(cplx<T>) * N * N);
     const int smx = (int)(sizeof(cplx<T>) * N * TC);
-    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_poisson_yz_fwd<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
-    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
     (void)hipFuncSetAttribute((const void*)k_poisson_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
   }
 };
