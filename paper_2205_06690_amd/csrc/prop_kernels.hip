@@ -39,35 +39,74 @@ __device__ __forceinline__ void kinetic_x_tile(cplx<T>* s, const cplx<T>* __rest
   __syncthreads();
 }
 
+// Each thread owns work items (column c, j2) of the four-step transform of
+// its x-lines: the N1 values x = j1 N2 + j2 are loaded from HBM straight into
+// registers (coalesced over c), transformed (stage A) and written to LDS;
+// stage B runs through LDS; stage C reads its N1 slots back and the results
+// go straight to HBM.  The pair variant keeps u_b in registers across the L
+// orbitals and has the next orbital's loads in flight during the transform.
 template <int N, int TC, typename T, bool ETA>
 __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int NTH = 256;
-  constexpr int PER = N * TC / NTH;
-  static_assert(N * TC % NTH == 0, "tile must divide the block");
-  const int ng = N * N * N;
+  constexpr int N1 = Fac<N>::N1, N2 = Fac<N>::N2;
+  constexpr int IT = TC * N2 / NTH;
+  static_assert(TC * N2 % NTH == 0, "work items must fill the block");
+  const size_t ng = (size_t)N * N * N;
   const int c0 = blockIdx.x * TC;
   const int tid = threadIdx.x;
-  if (ETA) {
-    const int f = blockIdx.y;
-    const C* __restrict__ din = a.din + (size_t)f * ng;
-    C* __restrict__ dout = a.dout + (size_t)f * ng;
+  const C* __restrict__ tw = a.tw;
+  const C* __restrict__ kp = a.kph;
+  // global offset of element j1 of item it
+  auto gidx = [&](int it, int j1) -> size_t {
+    const int w = tid + it * NTH;
+    const int c = w % TC, j2 = w / TC;
+    return (size_t)(j1 * N2 + j2) * N * N + c0 + c;
+  };
+  // stage A from registers: DFT_N1, twiddle, write slot k1 N2 + j2 of line c
+  auto stage_a = [&](int it, C* v) {
+    const int w = tid + it * NTH;
+    const int c = w % TC, j2 = w / TC;
+    Dft<N1, -1, C>::run(v);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NTH;
-      const int x = e / TC, c = e % TC;
-      const size_t g = (size_t)x * N * N + c0 + c;
-      s[x * TC + c] = cmul(a.pf[g], din[g]);
+    for (int k1 = 0; k1 < N1; ++k1) {
+      C x = v[k1];
+      if (k1 > 0 && j2 > 0) x = cmul(x, tw[(j2 * k1) % N]);
+      s[(k1 * N2 + j2) * TC + c] = x;
+    }
+  };
+  // stage C to registers: read slots, inverse DFT_N1 -> x = j1 N2 + j2
+  auto stage_c = [&](int it, C* v) {
+    const int w = tid + it * NTH;
+    const int c = w % TC, j2 = w / TC;
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = s[(k1 * N2 + j2) * TC + c];
+    Dft<N1, +1, C>::run(v);
+  };
+  auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
+  if (ETA) {
+    const size_t fo = (size_t)blockIdx.y * ng;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      C v[N1];
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const size_t g = gidx(it, j1);
+        v[j1] = cmul(a.pf[g], a.din[fo + g]);
+      }
+      stage_a(it, v);
     }
     __syncthreads();
-    kinetic_x_tile<N, TC, T>(s, a.tw, a.kph, tid, NTH);
+    stageB<N, 2>(s, TC, 1, TC, tw, tid, NTH, true, mul);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NTH;
-      const int x = e / TC, c = e % TC;
-      dout[(size_t)x * N * N + c0 + c] = s[x * TC + c];
+    for (int it = 0; it < IT; ++it) {
+      C v[N1];
+      stage_c(it, v);
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) a.dout[fo + gidx(it, j1)] = v[j1];
     }
     return;
   }
@@ -75,44 +114,51 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   const bool half = a.mode == PX_HALF;
   const T cu = half ? (T)0.5 * a.dt : a.dt;
   const C* __restrict__ ptab = half ? a.ph : a.pf;
-  T uu[PER];
-  C dn[PER], hn[PER];
+  T uu[IT][N1];
+  C dn[IT][N1], hn[IT][N1];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NTH;
-    const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
-    uu[i] = cu * a.u[(size_t)b * ng + g];
-    dn[i] = a.din[((size_t)b * a.L) * ng + g];
-    hn[i] = a.H[g];
-  }
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) {
+      const size_t g = gidx(it, j1);
+      uu[it][j1] = cu * a.u[(size_t)b * ng + g];
+      dn[it][j1] = a.din[(size_t)b * a.L * ng + g];
+      hn[it][j1] = a.H[g];
+    }
   for (int l = 0; l < a.L; ++l) {
     const size_t fo = ((size_t)b * a.L + l) * ng;
-    __syncthreads();
+    C v[IT][N1];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NTH;
-      const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
-      const C p = ptab[g];
-      C h = hn[i];
-      if (half) h = cmul(p, h);
-      C v = cmk<C>(dn[i].x + uu[i] * h.y, dn[i].y - uu[i] * h.x);
-      s[e] = cmul(p, v);
-    }
-    __syncthreads();
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const C p = ptab[gidx(it, j1)];
+        C h = hn[it][j1];
+        if (half) h = cmul(p, h);
+        const C x = cmk<C>(dn[it][j1].x + uu[it][j1] * h.y, dn[it][j1].y - uu[it][j1] * h.x);
+        v[it][j1] = cmul(p, x);
+      }
     if (l + 1 < a.L) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int e = tid + i * NTH;
-        const size_t g = (size_t)(e / TC) * N * N + c0 + (e % TC);
-        dn[i] = a.din[fo + ng + g];
-        hn[i] = a.H[(size_t)(l + 1) * ng + g];
-      }
-    }
-    kinetic_x_tile<N, TC, T>(s, a.tw, a.kph, tid, NTH);
+      for (int it = 0; it < IT; ++it)
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NTH;
-      a.dout[fo + (size_t)(e / TC) * N * N + c0 + (e % TC)] = s[e];
+        for (int j1 = 0; j1 < N1; ++j1) {
+          const size_t g = gidx(it, j1);
+          dn[it][j1] = a.din[fo + ng + g];
+          hn[it][j1] = a.H[(size_t)(l + 1) * ng + g];
+        }
+    }
+    __syncthreads();  // the previous orbital's stage C has read its slots
+#pragma unroll
+    for (int it = 0; it < IT; ++it) stage_a(it, v[it]);
+    __syncthreads();
+    stageB<N, 2>(s, TC, 1, TC, tw, tid, NTH, true, mul);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      stage_c(it, v[it]);
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) a.dout[fo + gidx(it, j1)] = v[it][j1];
     }
   }
 }
@@ -123,24 +169,32 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
 // state (linearised Eq. 11 source).  The pair variant loops over the L
 // orbitals with the next plane's loads in flight during the transform.
 // ---------------------------------------------------------------------------
+// Plane layout in LDS: row y at y * (N + 1), so that lanes walking over y
+// (stride N + 1 complex values) spread over the LDS banks.
+template <int N> constexpr int plane_stride() { return N + 1; }
+template <int N> __device__ __forceinline__ int plane_idx(int e) {
+  return (e / N) * plane_stride<N>() + (e % N);
+}
+
 template <int N, typename T, int NT>
 __device__ __forceinline__ void kinetic_yz_plane(cplx<T>* s, const cplx<T>* __restrict__ tw,
                                                  const cplx<T>* __restrict__ kp, int tid) {
   using C = cplx<T>;
+  constexpr int S = plane_stride<N>();
   auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
-  // z lines: line = y (stride N), elements contiguous
-  stageA_fwd<N>(s, N, N, 1, tw, tid, NT, false);
+  // z lines: line = y (stride S), elements contiguous; lanes walk over y
+  stageA_fwd<N>(s, N, S, 1, tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 2>(s, N, N, 1, tw, tid, NT, false, mul);
+  stageB<N, 2>(s, N, S, 1, tw, tid, NT, true, mul);
   __syncthreads();
-  stageC_inv<N>(s, N, N, 1, tid, NT, false);
+  stageC_inv<N>(s, N, S, 1, tid, NT, true);
   __syncthreads();
-  // y lines: line = z (stride 1), elements N apart
-  stageA_fwd<N>(s, N, 1, N, tw, tid, NT, true);
+  // y lines: line = z (stride 1), elements S apart; lanes walk over z
+  stageA_fwd<N>(s, N, 1, S, tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 2>(s, N, 1, N, tw, tid, NT, true, mul);
+  stageB<N, 2>(s, N, 1, S, tw, tid, NT, true, mul);
   __syncthreads();
-  stageC_inv<N>(s, N, 1, N, tid, NT, true);
+  stageC_inv<N>(s, N, 1, S, tid, NT, true);
   __syncthreads();
 }
 
@@ -158,10 +212,10 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
   const size_t poff = (size_t)x * P;
   if (!DENS) {
     C* d = a.d + (size_t)blockIdx.y * ng + poff;
-    for (int e = tid; e < P; e += NT) s[e] = d[e];
+    for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = d[e];
     __syncthreads();
     kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
-    for (int e = tid; e < P; e += NT) d[e] = s[e];
+    for (int e = tid; e < P; e += NT) d[e] = s[plane_idx<N>(e)];
     return;
   }
   const int b = blockIdx.y;
@@ -181,7 +235,7 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + i * NT;
-      if (e < P) s[e] = dn[i];
+      if (e < P) s[plane_idx<N>(e)] = dn[i];
     }
     __syncthreads();
     // loads of the next orbital and of this orbital's unperturbed plane are
@@ -205,7 +259,7 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
     for (int i = 0; i < PER; ++i) {
       const int e = tid + i * NT;
       if (e < P) {
-        const C v = s[e];
+        const C v = s[plane_idx<N>(e)];
         const C hh = PREF_H ? hc[PREF_H ? i : 0] : h[e];
         d[e] = v;
         acc[i] += hh.x * v.x + hh.y * v.y;
@@ -230,24 +284,25 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int P = N * N;
+  constexpr int S = plane_stride<N>();
   const int ng = N * N * N;
   const int x = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
   const int b0 = 2 * m, b1 = 2 * m + 1;
   const T* r0 = a.rho + (size_t)b0 * ng + (size_t)x * P;
   const T* r1 = (b1 < a.B) ? a.rho + (size_t)b1 * ng + (size_t)x * P : nullptr;
-  for (int e = tid; e < P; e += NT) s[e] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
+  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
   __syncthreads();
   NoMul nm;
-  stageA_fwd<N>(s, N, N, 1, a.tw, tid, NT, false);
+  stageA_fwd<N>(s, N, S, 1, a.tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, N, 1, a.tw, tid, NT, false, nm);
+  stageB<N, 0>(s, N, S, 1, a.tw, tid, NT, true, nm);
   __syncthreads();
-  stageA_fwd<N>(s, N, 1, N, a.tw, tid, NT, true);
+  stageA_fwd<N>(s, N, 1, S, a.tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, 1, N, a.tw, tid, NT, true, nm);
+  stageB<N, 0>(s, N, 1, S, a.tw, tid, NT, true, nm);
   __syncthreads();
   C* w = a.work + (size_t)m * ng + (size_t)x * P;
-  for (int e = tid; e < P; e += NT) w[e] = s[e];
+  for (int e = tid; e < P; e += NT) w[e] = s[plane_idx<N>(e)];
 }
 
 template <int N, int TC, typename T>
@@ -290,26 +345,27 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_inv(PoisArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int P = N * N;
+  constexpr int S = plane_stride<N>();
   const int ng = N * N * N;
   const int x = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
   const C* w = a.work + (size_t)m * ng + (size_t)x * P;
-  for (int e = tid; e < P; e += NT) s[e] = w[e];
+  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = w[e];
   __syncthreads();
   NoMul nm;
-  stageB<N, 1>(s, N, N, 1, a.tw, tid, NT, false, nm);
+  stageB<N, 1>(s, N, S, 1, a.tw, tid, NT, true, nm);
   __syncthreads();
-  stageC_inv<N>(s, N, N, 1, tid, NT, false);
+  stageC_inv<N>(s, N, S, 1, tid, NT, true);
   __syncthreads();
-  stageB<N, 1>(s, N, 1, N, a.tw, tid, NT, true, nm);
+  stageB<N, 1>(s, N, 1, S, a.tw, tid, NT, true, nm);
   __syncthreads();
-  stageC_inv<N>(s, N, 1, N, tid, NT, true);
+  stageC_inv<N>(s, N, 1, S, tid, NT, true);
   __syncthreads();
   const int b0 = 2 * m, b1 = 2 * m + 1;
   const size_t o0 = (size_t)b0 * ng + (size_t)x * P;
   const size_t o1 = (size_t)b1 * ng + (size_t)x * P;
   const bool has1 = b1 < a.B;
   for (int e = tid; e < P; e += NT) {
-    const C v = s[e];
+    const C v = s[plane_idx<N>(e)];
     if (a.out) {
       a.out[o0 + e] = v.x;
       if (has1) a.out[o1 + e] = v.y;
@@ -630,7 +686,7 @@ __global__ void k_to_real(const double* __restrict__ in, size_t n, T* __restrict
 // host launchers
 // ---------------------------------------------------------------------------
 template <int N> constexpr int yz_threads() { return N >= 64 ? 512 : 256; }
-template <int N> constexpr int x_tc() { return N <= 16 ? 16 : 32; }
+template <int N> constexpr int x_tc() { return N <= 16 ? 64 : 32; }
 
 template <int N, typename T>
 struct Launch {
@@ -647,7 +703,7 @@ struct Launch {
   }
   static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st) {
     constexpr int NT = yz_threads<N>();
-    size_t sm = sizeof(cplx<T>) * N * N;
+    size_t sm = sizeof(cplx<T>) * N * plane_stride<N>();
     if (a.density)
       hipLaunchKernelGGL((k_prop_yz<N, T, NT, true>), dim3(N, nb), dim3(NT), sm, st, a);
     else
@@ -658,7 +714,7 @@ struct Launch {
     constexpr int NT = yz_threads<N>();
     constexpr int TC = x_tc<N>();
     const int M = (a.B + 1) / 2;
-    size_t smp = sizeof(cplx<T>) * N * N;
+    size_t smp = sizeof(cplx<T>) * N * plane_stride<N>();
     hipLaunchKernelGGL((k_poisson_yz_fwd<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
     hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256),
                        sizeof(cplx<T>) * N * TC, st, a);
@@ -668,7 +724,7 @@ struct Launch {
   static void configure() {
     constexpr int NT = yz_threads<N>();
     constexpr int TC = x_tc<N>();
-    const int smp = (int)(sizeof(cplx<T>) * N * N);
+    const int smp = (int)(sizeof(cplx<T>) * N * plane_stride<N>());
     const int smx = (int)(sizeof(cplx<T>) * N * TC);
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
@@ -682,7 +738,7 @@ struct Launch {
 
 template <typename T>
 bool grid_supported(int n) {
-  if (sizeof(cplx<T>) * (size_t)n * n > 160 * 1024) return false;
+  if (sizeof(cplx<T>) * (size_t)n * (n + 1) > 160 * 1024) return false;
   switch (n) {
     case 16: case 24: case 32: case 48: case 64: case 112: return true;
     default: return false;
