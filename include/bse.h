@@ -84,9 +84,9 @@ bse_status bse_create_system(const bse_config* cfg, const double* v_ext, bse_sys
 
 /* Orbitals phi[n_orb][nx*ny*nz] (host, FP64, h^3-normalised) and
  * eigenvalues eps[n_orb] (host, FP64, ascending).  n_orb >= n_occ; the
- * A matrix needs n_orb >= n_occ + n_c.  Builds the stochastic orbitals and
- * propagates the unperturbed set once (its trajectory is shared by every
- * pair).  Replaces earlier orbitals. */
+ * A matrix needs n_orb >= n_occ + n_c.  Builds the stochastic orbitals of
+ * Eq. 14 (shared by every pair; the unperturbed set is propagated alongside
+ * each batch of pairs).  Replaces earlier orbitals. */
 bse_status bse_set_orbitals(bse_system* sys, int32_t n_orb, const double* phi, const double* eps);
 
 /* Explicit signs xi[n_stoch][n_occ] (host, +-1) of Eq. 14, replacing the
@@ -122,6 +122,26 @@ bse_status bse_build_A(bse_system* sys, int32_t n_o, int32_t n_c, double* A);
  * (Eq. 7). */
 bse_status bse_spectrum(bse_system* sys, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
                         const double* w_grid, double sigma_broad, double* sigma);
+
+/* Uneven batch: the W-action for several systems at once (different grids,
+ * orbital counts and pair counts, same device).  System k propagates
+ * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and
+ * writes W to w_dev[k] (device, FP64, [n_pairs[k]][ng_k]).  With
+ * use_graph != 0 the whole propagation of every system is captured into one
+ * HIP graph (one branch per system) and launched once; otherwise the systems
+ * run on their own streams.  Returns after the work has finished.  Results
+ * equal those of bse_apply_W_device per system. */
+bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
+                             const int32_t* const* pq, void* const* w_dev, int32_t use_graph);
+
+/* Autotuner: times the tile-shape variants of the two propagation passes
+ * for this system's grid, precision and a batch of n_pairs pairs and keeps
+ * the fastest for later calls.  cache_path (nullable) is a text file of
+ * "key tc nt ms_x ms_yz" lines: a matching key is used without timing, a new
+ * result is appended.  Overwrites the system's pair workspace. */
+bse_status bse_autotune(bse_system* sys, int32_t n_pairs, const char* cache_path);
+/* The tuned x-tile width and plane-pass block size (0 = built-in default). */
+int32_t bse_tuned_shape(bse_system* sys, int32_t* tc, int32_t* nt);
 
 /* Stream for all later device work of this system (a hipStream_t). */
 bse_status bse_set_stream(bse_system* sys, void* hip_stream);

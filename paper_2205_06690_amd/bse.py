@@ -22,7 +22,8 @@ EXPORTS = (
     "bse_create_system", "bse_set_orbitals", "bse_set_signs", "bse_apply_W",
     "bse_apply_W_device", "bse_build_A", "bse_spectrum", "bse_set_stream",
     "bse_generate_signs", "bse_kernel_times", "bse_set_timing", "bse_last_error",
-    "bse_version", "bse_destroy_system",
+    "bse_version", "bse_destroy_system", "bse_apply_W_batch", "bse_autotune",
+    "bse_tuned_shape",
 )
 
 
@@ -62,6 +63,11 @@ def _load():
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
     lib.bse_kernel_times.restype = C.c_int32
     lib.bse_set_timing.argtypes = [P, C.c_int32]
+    lib.bse_apply_W_batch.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
+                                      C.c_int32]
+    lib.bse_autotune.argtypes = [P, C.c_int32, C.c_char_p]
+    lib.bse_tuned_shape.argtypes = [P, ip, ip]
+    lib.bse_tuned_shape.restype = C.c_int32
     lib.bse_last_error.restype = C.c_char_p
     lib.bse_version.restype = C.c_char_p
     lib.bse_destroy_system.argtypes = [P]
@@ -85,6 +91,18 @@ def _dptr(a: np.ndarray):
 
 def _iptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def apply_w_batch(systems, pair_lists, w_dev_ptrs, use_graph: bool = True):
+    """W-action for several systems at once (bse_apply_W_batch); outputs go to
+    the device buffers whose pointers are given."""
+    n = len(systems)
+    hs = (C.c_void_p * n)(*[s._h for s in systems])
+    pqs = [np.ascontiguousarray(np.asarray(p, dtype=np.int32).reshape(-1, 2)) for p in pair_lists]
+    npairs = np.array([p.shape[0] for p in pqs], dtype=np.int32)
+    pq_ptrs = (C.POINTER(C.c_int32) * n)(*[_iptr(p) for p in pqs])
+    w_ptrs = (C.c_void_p * n)(*[C.c_void_p(p) for p in w_dev_ptrs])
+    _check(LIB.bse_apply_W_batch(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, 1 if use_graph else 0))
 
 
 def generate_signs(seed: int, n_stoch: int, n_occ: int) -> np.ndarray:
@@ -170,6 +188,12 @@ class System:
         _check(LIB.bse_spectrum(self._h, n_exc, _dptr(om), _dptr(d2), wg.size, _dptr(wg), sigma,
                                 _dptr(sg)))
         return om, d2, sg
+
+    def autotune(self, n_pairs: int, cache_path: Optional[str] = None):
+        _check(LIB.bse_autotune(self._h, n_pairs, cache_path.encode() if cache_path else None))
+        tc, nt = C.c_int32(), C.c_int32()
+        LIB.bse_tuned_shape(self._h, C.byref(tc), C.byref(nt))
+        return tc.value, nt.value
 
     def set_timing(self, on: bool = True):
         _check(LIB.bse_set_timing(self._h, 1 if on else 0))

@@ -6,6 +6,9 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -134,7 +137,8 @@ struct bse_system {
   bool signs_given = false;
   DBuf xi_d;
   DBuf eta0;      // [L][ng] FP64
-  DBuf hist;      // [(N+1)][L][ng] complex T
+  DBuf h0;        // [L][ng] complex T: unperturbed set at t = 0 (mid-step form)
+  DBuf hbuf;      // [2][L][ng] complex T: unperturbed set, current and next step
   DBuf n0;        // [L]
   bool ready = false;
   // batch workspace
@@ -149,6 +153,8 @@ struct bse_system {
   DBuf lz_V, lz_w, lz_c, lz_s;  // Lanczos basis and scratch
   Timer timer;
   std::vector<double> wts;
+  int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
+  hipStream_t own_stream = nullptr;
 };
 
 namespace {
@@ -241,6 +247,7 @@ void ensure_batch(bse_system* s, int B) {
   s->coefE.alloc(sizeof(cplx<double>) * (size_t)L * (S + 1));
   s->pq_d.alloc(sizeof(int) * 2 * B);
   s->flags.alloc(sizeof(int) * B);
+  s->work64.alloc(sizeof(cplx<double>) * ng * (size_t)((B + 1) / 2));
   s->cap_b = B;
 }
 
@@ -299,9 +306,12 @@ void poissonT(bse_system* s, int B, double* acc, double wn) {
   s->timer.end(t);
 }
 
-// one batch of B pairs; results W (FP64) in s->wpol (q added at the end)
+// one batch of B pairs (pair list already on the device in s->pq_d);
+// results W^pol (FP64) in s->wpol, q in s->q.  Only kernel launches and
+// device-to-device work are issued, so the sequence can be captured into a
+// HIP graph.  The unperturbed set is propagated alongside, double-buffered.
 template <typename T>
-void propagate_batch(bse_system* s, const int* pq_host, int B) {
+void propagate_batch(bse_system* s, int B) {
   using C = cplx<T>;
   Tables& tb = tabs<T>(s);
   const size_t ng = s->ng;
@@ -310,44 +320,65 @@ void propagate_batch(bse_system* s, const int* pq_host, int B) {
   const int N = s->cfg.n_steps;
   const int M = s->cfg.clean_every;
   hipStream_t st = s->stream;
-  HIPC(hipMemcpyAsync(s->pq_d.p, pq_host, sizeof(int) * 2 * B, hipMemcpyHostToDevice, st));
   HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, ng, s->rho64.as<double>(), st));
   poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0);
-  HIPC(hipMemsetAsync(s->wpol.p, 0, sizeof(double) * ng * B, st));
-  HIPC(hipMemsetAsync(s->u.p, 0, sizeof(T) * ng * B, st));
+  HIPC(launch_fill_zero(s->wpol.p, sizeof(double) * ng * B, st));
+  HIPC(launch_fill_zero(s->u.p, sizeof(T) * ng * B, st));
   HIPC(launch_kick<T>(s->q.as<double>(), s->eta0.as<double>(), L, F, ng, s->d.as<C>(), st));
-  const C* hist = s->hist.as<C>();
   const size_t hstride = (size_t)L * ng;
-  if (M > 0) clean<T>(s, B, 2, hist);
+  const C* hcur = s->h0.as<C>();
+  C* hbuf = s->hbuf.as<C>();
+  if (M > 0) clean<T>(s, B, 2, hcur);
   // u_0 = 0: a phase kick does not change the density, so the t = 0 term
   // of the time integral vanishes.
   bool half = true;
   for (int n = 0; n < N; ++n) {
+    C* hnext = hbuf + (size_t)((n + 1) & 1) * hstride;
+    // unperturbed set: one step, H_n -> H_{n+1}
+    PropXArgs<T> pe{};
+    pe.din = hcur;
+    pe.dout = hnext;
+    pe.pf = tb.pf.as<C>();
+    pe.ph = tb.ph.as<C>();
+    pe.tw = tb.tw.as<C>();
+    pe.kph = tb.kph.as<C>();
+    pe.dt = (T)s->cfg.dt;
+    pe.L = L;
+    pe.mode = PX_ETA0;
+    HIPC(launch_prop_x<T>(s->n, pe, L, st, s->tune_tc));
+    PropYZArgs<T> pze{};
+    pze.d = hnext;
+    pze.tw = tb.tw.as<C>();
+    pze.kph = tb.kph.as<C>();
+    pze.L = L;
+    pze.density = 0;
+    HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
+    // perturbed set
     PropXArgs<T> px{};
     px.din = s->d.as<C>();
     px.dout = s->d.as<C>();
     px.pf = tb.pf.as<C>();
     px.ph = tb.ph.as<C>();
     px.u = s->u.as<T>();
-    px.H = hist + (size_t)n * hstride;
+    px.H = hcur;
     px.tw = tb.tw.as<C>();
     px.kph = tb.kph.as<C>();
     px.dt = (T)s->cfg.dt;
     px.L = L;
     px.mode = half ? PX_HALF : PX_FULL;
     auto* t1 = s->timer.begin("prop_x");
-    HIPC(launch_prop_x<T>(s->n, px, B, st));
+    HIPC(launch_prop_x<T>(s->n, px, B, st, s->tune_tc));
     s->timer.end(t1);
     PropYZArgs<T> pz{};
     pz.d = s->d.as<C>();
-    pz.H = hist + (size_t)(n + 1) * hstride;
+    pz.H = hnext;
     pz.tw = tb.tw.as<C>();
     pz.kph = tb.kph.as<C>();
     pz.dens = s->dens.as<T>();
     pz.L = L;
     pz.density = 1;
     auto* t2 = s->timer.begin("prop_yz");
-    HIPC(launch_prop_yz<T>(s->n, pz, B, st));
+    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt));
     s->timer.end(t2);
     const bool do_clean = M > 0 && ((n + 1) % M == 0);
     const double wn = s->wts[n + 1];
@@ -356,53 +387,34 @@ void propagate_batch(bse_system* s, const int* pq_host, int B) {
       half = false;
     } else {
       poissonT<T>(s, B, nullptr, 0.0);
-      clean<T>(s, B, 1, hist + (size_t)(n + 1) * hstride);
+      clean<T>(s, B, 1, hnext);
       poissonT<T>(s, B, s->wpol.as<double>(), wn);
       half = true;
     }
+    hcur = hnext;
   }
 }
 
+// stochastic orbitals eta(0), their norms, and the t = 0 unperturbed state
 template <typename T>
-void build_history(bse_system* s) {
+void prepare_unperturbed(bse_system* s) {
   using C = cplx<T>;
   Tables& tb = tabs<T>(s);
   const size_t ng = s->ng;
   const int L = s->L;
-  const int N = s->cfg.n_steps;
   const size_t hstride = (size_t)L * ng;
-  s->hist.alloc(sizeof(C) * hstride * (size_t)(N + 1));
+  s->h0.alloc(sizeof(C) * hstride);
+  s->hbuf.alloc(sizeof(C) * hstride * 2);
   s->eta0.alloc(sizeof(double) * hstride);
   s->n0.alloc(sizeof(double) * L);
-  C* hist = s->hist.as<C>();
   if (!s->deterministic) {
     s->xi_d.alloc((size_t)L * s->cfg.n_occ);
     HIPC(hipMemcpy(s->xi_d.p, s->xi.data(), (size_t)L * s->cfg.n_occ, hipMemcpyHostToDevice));
   }
   HIPC(launch_stoch_orbitals<T>(s->phi64.as<double>(), s->xi_d.as<signed char>(), L, s->cfg.n_occ,
                                 s->deterministic ? 1 : 0, ng, tb.ph.as<C>(), s->eta0.as<double>(),
-                                hist, s->stream));
+                                s->h0.as<C>(), s->stream));
   HIPC(launch_norms(s->eta0.as<double>(), L, ng, s->dv, s->n0.as<double>(), s->stream));
-  for (int n = 0; n < N; ++n) {
-    PropXArgs<T> px{};
-    px.din = hist + (size_t)n * hstride;
-    px.dout = hist + (size_t)(n + 1) * hstride;
-    px.pf = tb.pf.as<C>();
-    px.ph = tb.ph.as<C>();
-    px.tw = tb.tw.as<C>();
-    px.kph = tb.kph.as<C>();
-    px.dt = (T)s->cfg.dt;
-    px.L = L;
-    px.mode = PX_ETA0;
-    HIPC(launch_prop_x<T>(s->n, px, L, s->stream));
-    PropYZArgs<T> pz{};
-    pz.d = hist + (size_t)(n + 1) * hstride;
-    pz.tw = tb.tw.as<C>();
-    pz.kph = tb.kph.as<C>();
-    pz.L = L;
-    pz.density = 0;
-    HIPC(launch_prop_yz<T>(s->n, pz, L, s->stream));
-  }
 }
 
 void compute_weights(bse_system* s) {
@@ -433,13 +445,11 @@ void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev
   bool any_bad = false;
   for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
     const int B = std::min(Bmax, n_pairs - k0);
-    if (s->cfg.precision == BSE_FP64) {
-      ensure_batch<double>(s, B);
-      propagate_batch<double>(s, pq + 2 * k0, B);
-    } else {
-      ensure_batch<float>(s, B);
-      propagate_batch<float>(s, pq + 2 * k0, B);
-    }
+    if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, B);
+    else ensure_batch<float>(s, B);
+    HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
+    if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
+    else propagate_batch<float>(s, B);
     const size_t off = (size_t)k0 * s->ng;
     const size_t cnt = (size_t)B * s->ng;
     HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), cnt, w_dev + off, s->stream));
@@ -726,6 +736,175 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// autotuner: x-tile width and plane-pass block size for this system's grid,
+// batch size and precision, timed on the system's own buffers; results are
+// appended to a text cache (one "key tc nt ms_x ms_yz" line per shape)
+// ---------------------------------------------------------------------------
+template <typename T>
+float time_launches(bse_system* s, int reps, const std::function<hipError_t()>& fn) {
+  hipEvent_t a, b;
+  HIPC(hipEventCreate(&a));
+  HIPC(hipEventCreate(&b));
+  hipError_t e = fn();  // warm-up, also validates the variant
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return -1.f;
+  }
+  HIPC(hipEventRecord(a, s->stream));
+  for (int r = 0; r < reps; ++r) HIPC(fn());
+  HIPC(hipEventRecord(b, s->stream));
+  HIPC(hipEventSynchronize(b));
+  float ms = 0;
+  HIPC(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+template <typename T>
+void autotune_t(bse_system* s, int B, const char* cache_path) {
+  using C = cplx<T>;
+  char key[128];
+  std::snprintf(key, sizeof(key), "n%d_%s_B%d_L%d", s->n, sizeof(T) == 4 ? "f32" : "f64", B, s->L);
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream is(line);
+      std::string k;
+      int tc = 0, nt = 0;
+      if (is >> k >> tc >> nt && k == key) {
+        s->tune_tc = tc;
+        s->tune_nt = nt;
+        return;
+      }
+    }
+  }
+  ensure_batch<T>(s, B);
+  Tables& tb = tabs<T>(s);
+  HIPC(launch_fill_zero(s->d.p, sizeof(C) * s->ng * (size_t)B * s->L, s->stream));
+  HIPC(launch_fill_zero(s->u.p, sizeof(T) * s->ng * (size_t)B, s->stream));
+  PropXArgs<T> px{};
+  px.din = s->d.as<C>();
+  px.dout = s->d.as<C>();
+  px.pf = tb.pf.as<C>();
+  px.ph = tb.ph.as<C>();
+  px.u = s->u.as<T>();
+  px.H = s->h0.as<C>();
+  px.tw = tb.tw.as<C>();
+  px.kph = tb.kph.as<C>();
+  px.dt = (T)s->cfg.dt;
+  px.L = s->L;
+  px.mode = PX_FULL;
+  PropYZArgs<T> pz{};
+  pz.d = s->d.as<C>();
+  pz.H = s->h0.as<C>();
+  pz.tw = tb.tw.as<C>();
+  pz.kph = tb.kph.as<C>();
+  pz.dens = s->dens.as<T>();
+  pz.L = s->L;
+  pz.density = 1;
+  float best_x = 1e30f, best_yz = 1e30f;
+  int tc_best = 0, nt_best = 0;
+  for (int tc : {16, 32, 64}) {
+    const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_x<T>(s->n, px, B, s->stream, tc); });
+    if (ms > 0 && ms < best_x) { best_x = ms; tc_best = tc; }
+  }
+  for (int nt : {256, 512}) {
+    const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_yz<T>(s->n, pz, B, s->stream, nt); });
+    if (ms > 0 && ms < best_yz) { best_yz = ms; nt_best = nt; }
+  }
+  if (tc_best == 0 || nt_best == 0) fail(BSE_ERR_DEVICE, "autotune: no valid variant");
+  s->tune_tc = tc_best;
+  s->tune_nt = nt_best;
+  if (cache_path && *cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key << " " << tc_best << " " << nt_best << " " << best_x << " " << best_yz << "\n";
+  }
+}
+
+// ---------------------------------------------------------------------------
+// uneven batch: several systems (grids, pair counts) propagated together; the
+// whole propagation of every system is captured into one HIP graph with one
+// branch per system and launched once
+// ---------------------------------------------------------------------------
+void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
+                   const int32_t* const* pq, void* const* w_dev, int use_graph) {
+  if (n_sys < 1 || !sys || !n_pairs || !pq || !w_dev) fail(BSE_ERR_ARG, "bse_apply_W_batch: null argument");
+  int dev = -1;
+  for (int i = 0; i < n_sys; ++i) {
+    bse_system* s = sys[i];
+    check_ready(s);
+    if (dev < 0) dev = s->cfg.device;
+    if (s->cfg.device != dev) fail(BSE_ERR_ARG, "bse_apply_W_batch: systems on different devices");
+    if (n_pairs[i] < 1 || n_pairs[i] > s->cfg.max_batch || !pq[i] || !w_dev[i])
+      fail(BSE_ERR_ARG, "bse_apply_W_batch: need 1 <= n_pairs <= max_batch and non-null buffers");
+    for (int j = i + 1; j < n_sys; ++j)
+      if (sys[j] == s) fail(BSE_ERR_ARG, "bse_apply_W_batch: a system appears twice");
+    for (int k = 0; k < n_pairs[i]; ++k)
+      if (pq[i][2 * k] < 0 || pq[i][2 * k] >= s->n_orb || pq[i][2 * k + 1] < 0 || pq[i][2 * k + 1] >= s->n_orb)
+        fail(BSE_ERR_ARG, "pair index out of range");
+  }
+  HIPC(hipSetDevice(dev));
+  std::vector<hipStream_t> saved(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    bse_system* s = sys[i];
+    if (!s->own_stream) HIPC(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+    if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, n_pairs[i]);
+    else ensure_batch<float>(s, n_pairs[i]);
+    HIPC(hipMemcpy(s->pq_d.p, pq[i], sizeof(int) * 2 * n_pairs[i], hipMemcpyHostToDevice));
+    saved[i] = s->stream;
+    s->stream = s->own_stream;
+    s->timer.on = false;
+  }
+  hipStream_t origin = nullptr;
+  std::vector<hipEvent_t> ev(n_sys + 1, nullptr);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto restore = [&]() {
+    for (int i = 0; i < n_sys; ++i) sys[i]->stream = saved[i];
+    for (auto e : ev) if (e) (void)hipEventDestroy(e);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (origin) (void)hipStreamDestroy(origin);
+  };
+  try {
+    HIPC(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+    for (auto& e : ev) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (use_graph) HIPC(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    HIPC(hipEventRecord(ev[n_sys], origin));
+    for (int i = 0; i < n_sys; ++i) {
+      bse_system* s = sys[i];
+      HIPC(hipStreamWaitEvent(s->stream, ev[n_sys], 0));
+      const int B = n_pairs[i];
+      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
+      else propagate_batch<float>(s, B);
+      HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)B * s->ng,
+                      reinterpret_cast<double*>(w_dev[i]), s->stream));
+      HIPC(hipEventRecord(ev[i], s->stream));
+      HIPC(hipStreamWaitEvent(origin, ev[i], 0));
+    }
+    if (use_graph) {
+      HIPC(hipStreamEndCapture(origin, &graph));
+      HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      HIPC(hipGraphLaunch(exec, origin));
+    }
+    HIPC(hipStreamSynchronize(origin));
+  } catch (...) {
+    if (use_graph) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(origin, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    restore();
+    throw;
+  }
+  restore();
+}
+
 #define API_BEGIN try {
 #define API_END                 \
   }                             \
@@ -841,9 +1020,9 @@ bse_status bse_set_orbitals(bse_system* s, int32_t n_orb, const double* phi, con
     const size_t no = (size_t)s->cfg.n_occ * s->ng;
     s->phi_occ32.alloc(sizeof(float) * no);
     HIPC(launch_to_real<float>(s->phi64.as<double>(), no, s->phi_occ32.as<float>(), s->stream));
-    build_history<float>(s);
+    prepare_unperturbed<float>(s);
   } else {
-    build_history<double>(s);
+    prepare_unperturbed<double>(s);
   }
   HIPC(hipStreamSynchronize(s->stream));
   s->a_no = s->a_nc = 0;
@@ -937,9 +1116,33 @@ bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip
   API_END
 }
 
+bse_status bse_autotune(bse_system* s, int32_t n_pairs, const char* cache_path) {
+  API_BEGIN
+  check_ready(s);
+  if (n_pairs < 1 || n_pairs > s->cfg.max_batch) fail(BSE_ERR_ARG, "bse_autotune: 1 <= n_pairs <= max_batch");
+  if (s->cfg.precision == BSE_FP64) autotune_t<double>(s, n_pairs, cache_path);
+  else autotune_t<float>(s, n_pairs, cache_path);
+  API_END
+}
+
+int32_t bse_tuned_shape(bse_system* s, int32_t* tc, int32_t* nt) {
+  if (!s || !tc || !nt) return BSE_ERR_ARG;
+  *tc = s->tune_tc;
+  *nt = s->tune_nt;
+  return BSE_OK;
+}
+
+bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
+                             const int32_t* const* pq, void* const* w_dev, int32_t use_graph) {
+  API_BEGIN
+  apply_w_batch(n_sys, systems, n_pairs, pq, w_dev, use_graph);
+  API_END
+}
+
 void bse_destroy_system(bse_system* s) {
   if (!s) return;
   (void)hipSetDevice(s->cfg.device);
+  if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
   delete s;
 }
 

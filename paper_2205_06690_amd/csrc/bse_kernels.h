@@ -6,6 +6,7 @@
 namespace bse {
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st);
 hipError_t launch_fill_nan(double* w, size_t n, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 template <typename T>
 hipError_t launch_products(const double* phi, const int* pq, int K, size_t ng, T* out, hipStream_t st);
 size_t gemm_chunk(int M, int N, size_t K);

@@ -10,6 +10,8 @@
 
 #include "bse_kernels.h"
 
+#include <algorithm>
+
 namespace bse {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -314,8 +316,23 @@ __global__ void k_scale_copy(const double* __restrict__ w, int n, double s, doub
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+__global__ void k_fill_zero_words(unsigned int* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// zero a device buffer with a kernel (graph-capture safe, unlike a memset node)
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_zero_words, dim3(blocks), dim3(256), 0, st,
+                     reinterpret_cast<unsigned int*>(p), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(flags, 0, sizeof(int) * B, st);
+  hipError_t e = launch_fill_zero(flags, sizeof(int) * B, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finite_check, dim3(64, B), dim3(256), 0, st, w, ng, flags);
   return hipGetLastError();

@@ -688,27 +688,54 @@ __global__ void k_to_real(const double* __restrict__ in, size_t n, T* __restrict
 template <int N> constexpr int yz_threads() { return N >= 64 ? 512 : 256; }
 template <int N> constexpr int x_tc() { return N <= 16 ? 64 : 32; }
 
+// tile width of the x pass and block size of the plane passes are tunable;
+// a variant is valid when the work items fill the block
+template <int N, int TC> constexpr bool x_valid() {
+  return (N * N) % TC == 0 && (TC * Fac<N>::N2) % 256 == 0;
+}
+
 template <int N, typename T>
 struct Launch {
-  // F: fields (unperturbed set) or pairs (perturbed set)
-  static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st) {
-    constexpr int TC = x_tc<N>();
-    dim3 grid(N * N / TC, F);
-    size_t sm = sizeof(cplx<T>) * N * TC;
-    if (a.mode == PX_ETA0)
-      hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
-    else
-      hipLaunchKernelGGL((k_prop_x<N, TC, T, false>), grid, dim3(256), sm, st, a);
-    return hipGetLastError();
+  template <int TC>
+  static hipError_t prop_x_tc(const PropXArgs<T>& a, int F, hipStream_t st) {
+    if constexpr (!x_valid<N, TC>()) {
+      return hipErrorInvalidValue;
+    } else {
+      dim3 grid(N * N / TC, F);
+      size_t sm = sizeof(cplx<T>) * N * TC;
+      if (a.mode == PX_ETA0)
+        hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
+      else
+        hipLaunchKernelGGL((k_prop_x<N, TC, T, false>), grid, dim3(256), sm, st, a);
+      return hipGetLastError();
+    }
   }
-  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st) {
-    constexpr int NT = yz_threads<N>();
+  // F: fields (unperturbed set) or pairs (perturbed set); tc 0 = default
+  static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st, int tc) {
+    if (tc == 0) tc = x_tc<N>();
+    switch (tc) {
+      case 16: return prop_x_tc<16>(a, F, st);
+      case 32: return prop_x_tc<32>(a, F, st);
+      case 64: return prop_x_tc<64>(a, F, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  template <int NT>
+  static hipError_t prop_yz_nt(const PropYZArgs<T>& a, int nb, hipStream_t st) {
     size_t sm = sizeof(cplx<T>) * N * plane_stride<N>();
     if (a.density)
       hipLaunchKernelGGL((k_prop_yz<N, T, NT, true>), dim3(N, nb), dim3(NT), sm, st, a);
     else
       hipLaunchKernelGGL((k_prop_yz<N, T, NT, false>), dim3(N, nb), dim3(NT), sm, st, a);
     return hipGetLastError();
+  }
+  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt) {
+    if (nt == 0) nt = yz_threads<N>();
+    switch (nt) {
+      case 256: return prop_yz_nt<256>(a, nb, st);
+      case 512: return prop_yz_nt<512>(a, nb, st);
+      default: return hipErrorInvalidValue;
+    }
   }
   static hipError_t poisson(const PoisArgs<T>& a, hipStream_t st) {
     constexpr int NT = yz_threads<N>();
@@ -721,17 +748,30 @@ struct Launch {
     hipLaunchKernelGGL((k_poisson_yz_inv<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
     return hipGetLastError();
   }
+  template <int TC> static void conf_x() {
+    if constexpr (x_valid<N, TC>()) {
+      const int smx = (int)(sizeof(cplx<T>) * N * TC);
+      (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+      (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+    }
+  }
+  template <int NT> static void conf_yz() {
+    const int smp = (int)(sizeof(cplx<T>) * N * plane_stride<N>());
+    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+  }
   static void configure() {
     constexpr int NT = yz_threads<N>();
     constexpr int TC = x_tc<N>();
     const int smp = (int)(sizeof(cplx<T>) * N * plane_stride<N>());
     const int smx = (int)(sizeof(cplx<T>) * N * TC);
-    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
-    (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    conf_x<16>();
+    conf_x<32>();
+    conf_x<64>();
+    conf_yz<256>();
+    conf_yz<512>();
     (void)hipFuncSetAttribute((const void*)k_poisson_yz_fwd<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
-    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
-    (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
     (void)hipFuncSetAttribute((const void*)k_poisson_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
   }
 };
@@ -757,12 +797,12 @@ bool grid_supported(int n) {
   }
 
 template <typename T>
-hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st) {
-  BSE_DISPATCH_N(n, T, prop_x(a, F, st));
+hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc) {
+  BSE_DISPATCH_N(n, T, prop_x(a, F, st, tc));
 }
 template <typename T>
-hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st) {
-  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st));
+hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt) {
+  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st, nt));
 }
 template <typename T>
 hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st) {
@@ -861,8 +901,8 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
 }
 
 #define BSE_INST(T)                                                                            \
-  template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t);            \
-  template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t);          \
+  template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t, int);       \
+  template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t, int);     \
   template hipError_t launch_poisson<T>(int, const PoisArgs<T>&, hipStream_t);                 \
   template void configure_kernels<T>(int);                                                     \
   template bool grid_supported<T>(int);                                                        \
