@@ -60,6 +60,73 @@ def cpu_baseline(spec, sysd, pair, steps_sample: int):
     return w.reshape(1, -1), wp.reshape(1, -1), per_solve, t
 
 
+def bench_uneven(args):
+    """The uneven batch: 32 synthetic molecules on {32,48,64}^3 grids with
+    10-80 wells, N_occ 10-100 and 16-200 pair densities each, L = 10,
+    400 steps, FP32 propagation.  Timed three ways: one system after the
+    other, all systems on their own streams, and all systems captured into
+    one HIP graph launched once.  Prints one JSON line."""
+    import torch
+    from paper_2205_06690_amd import inputs
+    from paper_2205_06690_amd import bse
+    specs = inputs.uneven_batch_specs(args.n_systems)
+    systems, pairs, outs = [], [], []
+    t_in = time.perf_counter()
+    for k, (sp, npair) in enumerate(specs):
+        sd = inputs.make_system(sp)
+        p = inputs.ia_pairs(sp)[:npair]
+        S = bse.System(sp.n, sp.h, sd["v_ext"], n_occ=sp.n_occ, n_stoch=sp.n_stoch, seed=sp.seed,
+                       dt=sp.dt, n_steps=sp.n_steps, gamma=sp.gamma_eff,
+                       clean_every=sp.clean_every, precision=bse.BSE_MIXED, max_batch=len(p))
+        S.set_signs(sd["xi"])
+        S.set_orbitals(sd["phi"], sd["eps"])
+        if args.autotune:
+            S.autotune(len(p), os.path.join(os.environ.get("TMPDIR", "/tmp"), "bse_tune.txt"))
+        systems.append(S)
+        pairs.append(p)
+        outs.append(torch.empty((len(p), sp.ng), dtype=torch.float64, device="cuda"))
+        print(f"[bench] system {k}: {sp.n}^3, N_occ {sp.n_occ}, {len(p)} pairs", file=sys.stderr,
+              flush=True)
+    print(f"[bench] inputs ready in {time.perf_counter() - t_in:.1f}s", file=sys.stderr, flush=True)
+    total = sum(len(p) for p in pairs)
+    res = {}
+
+    def run(mode):
+        if mode == "sequential":
+            for S, p, o in zip(systems, pairs, outs):
+                S.apply_w_device(p, o.data_ptr())
+        else:
+            bse.apply_w_batch(systems, pairs, [o.data_ptr() for o in outs],
+                              use_graph=(mode == "graph"))
+        torch.cuda.synchronize()
+
+    for mode in ("sequential", "streams", "graph"):
+        for _ in range(args.warmup):
+            run(mode)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run(mode)
+        res[mode] = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] {mode}: {res[mode] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    hist = {}
+    for sp, _ in specs:
+        hist[f"{sp.n}^3"] = hist.get(f"{sp.n}^3", 0) + 1
+    out = {
+        "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",
+        "value": round(total / res["graph"], 3), "unit": "pair solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["graph"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uneven batch: {len(specs)} Gaussian-well molecules, grids {hist}, "
+                               "h=0.4, N_occ 10-100, 16-200 pair densities each, L=10, dt=0.05, "
+                               "400 steps, M=10, one HIP-graph launch",
+                   "pairs_per_step": total, "autotuned": bool(args.autotune)},
+        "sequential_solves_per_s": round(total / res["sequential"], 3),
+        "streams_solves_per_s": round(total / res["streams"], 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +136,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--n-systems", type=int, default=32)
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -77,6 +146,10 @@ def main():
               "(pairs would shard across GPUs with one all-gather of A; not built)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "uneven32":
+        bench_uneven(args)
+        return
 
     import torch
     from paper_2205_06690_amd import inputs

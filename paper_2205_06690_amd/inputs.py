@@ -440,7 +440,7 @@ def _gpu_available() -> bool:
 def make_system(spec: SystemSpec, *, n_states: Optional[int] = None, tol: float = 1e-9,
                 use_cache: bool = True, verbose: bool = False, use_gpu: Optional[bool] = None):
     """Return dict(v_ext, phi, eps, xi) for ``spec`` (FP64; phi has
-    ``n_states`` (default n_occ + n_c) rows).  Grids above 10^5 points are
+    ``n_states`` (default n_occ + n_c) rows).  Grids above 2 10^4 points are
     solved with torch on a GPU when one is present (input preparation
     only), else on the CPU."""
     n_states = spec.n_orb if n_states is None else n_states
@@ -456,7 +456,7 @@ def make_system(spec: SystemSpec, *, n_states: Optional[int] = None, tol: float 
             phi = eps = None
     if phi is None:
         if use_gpu is None:
-            use_gpu = spec.ng > 100000 and _gpu_available()
+            use_gpu = spec.ng > 20000 and _gpu_available()
         if use_gpu:
             phi, eps = eigensolve_torch(v, spec.h, n_states, tol=tol, verbose=verbose)
         else:
