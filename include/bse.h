@@ -162,6 +162,61 @@ const char* bse_last_error(void);
 const char* bse_version(void);
 void bse_destroy_system(bse_system* sys);
 
+/* ---------------------------------------------------------------------------
+ * Screening surrogate: a Fourier neural operator that maps the scaled
+ * source potential q_ij / s_ij (s_ij its RMS) plus molecule descriptor
+ * channels to W^pol_ij / s_ij on the same grid.  It is trained on pairs that
+ * bse_apply_W generates and is judged by them; it does not replace the
+ * propagation unless its prediction passes the caller's checks.
+ *
+ * Network: h0 = P x + p; for l < layers: z = W_l h + b_l + S_l h,
+ * h = gelu(z) (no gelu after the last layer); y = Q h + q0.  S_l keeps the
+ * modes kx, ky in [-modes, modes), kz in [0, modes) (FFT index units), mixes
+ * channels per mode with complex weights R_l[k][i][o], and returns
+ * (1/ng) Re sum_k c_k U(k) e^{ik.r} with c_k = 1 on kz = 0, 2 elsewhere.
+ * Loss: mean over the batch of ||y - t||^2 / ||t||^2; Adam (0.9, 0.999,
+ * 1e-8) on FP32 master weights; the weights used by the forward and
+ * backward kernels are the master weights rounded to BF16 when
+ * bf16_weights != 0; activations and accumulation are FP32.
+ *
+ * Flat parameter vector (floats): P[width][cin], p[width], Q[width], q0[1],
+ * then per layer R_l[K][width][width][2] (re, im; K = 4 modes^3, mode order
+ * kx-major, then ky, then kz, signed frequencies ascending), W_l[width][width]
+ * (out, in), b_l[width].
+ * Buffers: x[B][cin][n^3], y and t [B][n^3], FP32, device, caller-owned.
+ * ------------------------------------------------------------------------- */
+typedef struct bse_fno bse_fno;
+typedef struct {
+  int32_t n;            /* grid points per axis: 16, 32 or 64 */
+  int32_t cin;          /* input channels (<= 64)             */
+  int32_t width;        /* hidden channels (<= 64)            */
+  int32_t modes;        /* m, 2m <= n                         */
+  int32_t layers;       /* Fourier layers                     */
+  int32_t max_batch;    /* largest batch                      */
+  int32_t device;
+  int32_t bf16_weights; /* 1: compute with BF16-rounded weights */
+  uint64_t seed;        /* initial weights                    */
+} bse_fno_config;
+
+bse_status bse_fno_create(const bse_fno_config* cfg, bse_fno** out);
+int64_t bse_fno_num_params(const bse_fno* fno);
+/* Set (host, FP32, flat layout above) the master weights; resets Adam. */
+bse_status bse_fno_set_params(bse_fno* fno, const float* host);
+/* Copy the master (which = 0) or compute (which = 1) weights to the host. */
+bse_status bse_fno_get_params(bse_fno* fno, float* host, int32_t which);
+bse_status bse_fno_set_stream(bse_fno* fno, void* hip_stream);
+/* y = network(x) for a batch of B samples; returns when done. */
+bse_status bse_fno_forward(bse_fno* fno, int32_t B, const void* x_dev, void* y_dev);
+/* Loss of the batch against targets t and, if grad_host is non-null, its
+ * gradient (flat layout; complex weights as d/dRe, d/dIm). */
+bse_status bse_fno_loss_grad(bse_fno* fno, int32_t B, const void* x_dev, const void* t_dev,
+                             double* loss, float* grad_host);
+/* One training step: loss, gradient, Adam update with learning rate lr. */
+bse_status bse_fno_train_step(bse_fno* fno, int32_t B, const void* x_dev, const void* t_dev,
+                              double lr, double* loss);
+const char* bse_fno_last_error(void);
+void bse_fno_destroy(bse_fno* fno);
+
 #ifdef __cplusplus
 }
 #endif

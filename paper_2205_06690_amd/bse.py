@@ -23,7 +23,9 @@ EXPORTS = (
     "bse_apply_W_device", "bse_build_A", "bse_spectrum", "bse_set_stream",
     "bse_generate_signs", "bse_kernel_times", "bse_set_timing", "bse_last_error",
     "bse_version", "bse_destroy_system", "bse_apply_W_batch", "bse_autotune",
-    "bse_tuned_shape",
+    "bse_tuned_shape", "bse_fno_create", "bse_fno_num_params", "bse_fno_set_params",
+    "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
+    "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy",
 )
 
 
@@ -34,6 +36,14 @@ class BseConfig(C.Structure):
         ("dt", C.c_double), ("n_steps", C.c_int32), ("gamma", C.c_double),
         ("clean_every", C.c_int32), ("alpha", C.c_double), ("scissors", C.c_double),
         ("precision", C.c_int32), ("device", C.c_int32), ("max_batch", C.c_int32),
+    ]
+
+
+class FnoConfig(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("cin", C.c_int32), ("width", C.c_int32), ("modes", C.c_int32),
+        ("layers", C.c_int32), ("max_batch", C.c_int32), ("device", C.c_int32),
+        ("bf16_weights", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -68,6 +78,19 @@ def _load():
     lib.bse_autotune.argtypes = [P, C.c_int32, C.c_char_p]
     lib.bse_tuned_shape.argtypes = [P, ip, ip]
     lib.bse_tuned_shape.restype = C.c_int32
+    fp = C.POINTER(C.c_float)
+    lib.bse_fno_create.argtypes = [C.POINTER(FnoConfig), C.POINTER(P)]
+    lib.bse_fno_num_params.argtypes = [P]
+    lib.bse_fno_num_params.restype = C.c_int64
+    lib.bse_fno_set_params.argtypes = [P, fp]
+    lib.bse_fno_get_params.argtypes = [P, fp, C.c_int32]
+    lib.bse_fno_set_stream.argtypes = [P, P]
+    lib.bse_fno_forward.argtypes = [P, C.c_int32, P, P]
+    lib.bse_fno_loss_grad.argtypes = [P, C.c_int32, P, P, dp, fp]
+    lib.bse_fno_train_step.argtypes = [P, C.c_int32, P, P, C.c_double, dp]
+    lib.bse_fno_last_error.restype = C.c_char_p
+    lib.bse_fno_destroy.argtypes = [P]
+    lib.bse_fno_destroy.restype = None
     lib.bse_last_error.restype = C.c_char_p
     lib.bse_version.restype = C.c_char_p
     lib.bse_destroy_system.argtypes = [P]
@@ -207,3 +230,58 @@ class System:
         if k < 0:
             raise BseError(BSE_ERR_DEVICE, LIB.bse_last_error().decode())
         return {names[i].decode(): (float(avg[i]), int(calls[i])) for i in range(k)}
+
+
+def _fcheck(rc: int):
+    if rc != BSE_OK:
+        raise BseError(rc, LIB.bse_fno_last_error().decode())
+
+
+class Fno:
+    """The screening surrogate (bse_fno handle); buffers are device pointers."""
+
+    def __init__(self, n: int, cin: int = 3, width: int = 32, modes: int = 8, layers: int = 4,
+                 max_batch: int = 8, device: int = 0, bf16_weights: bool = True, seed: int = 0):
+        cfg = FnoConfig(n, cin, width, modes, layers, max_batch, device, 1 if bf16_weights else 0, seed)
+        h = C.c_void_p()
+        _fcheck(LIB.bse_fno_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self.cfg = cfg
+        self.n_params = int(LIB.bse_fno_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.bse_fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, flat: np.ndarray):
+        f = np.ascontiguousarray(flat, dtype=np.float32)
+        if f.size != self.n_params:
+            raise ValueError("parameter vector size")
+        _fcheck(LIB.bse_fno_set_params(self._h, f.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self, compute: bool = False) -> np.ndarray:
+        f = np.empty(self.n_params, dtype=np.float32)
+        _fcheck(LIB.bse_fno_get_params(self._h, f.ctypes.data_as(C.POINTER(C.c_float)), 1 if compute else 0))
+        return f
+
+    def set_stream(self, stream_ptr: int):
+        _fcheck(LIB.bse_fno_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def forward(self, B: int, x_ptr: int, y_ptr: int):
+        _fcheck(LIB.bse_fno_forward(self._h, B, C.c_void_p(x_ptr), C.c_void_p(y_ptr)))
+
+    def loss_grad(self, B: int, x_ptr: int, t_ptr: int, want_grad: bool = True):
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        _fcheck(LIB.bse_fno_loss_grad(self._h, B, C.c_void_p(x_ptr), C.c_void_p(t_ptr), C.byref(loss),
+                                      g.ctypes.data_as(C.POINTER(C.c_float)) if g is not None else None))
+        return loss.value, g
+
+    def train_step(self, B: int, x_ptr: int, t_ptr: int, lr: float) -> float:
+        loss = C.c_double()
+        _fcheck(LIB.bse_fno_train_step(self._h, B, C.c_void_p(x_ptr), C.c_void_p(t_ptr), lr, C.byref(loss)))
+        return loss.value

@@ -1,0 +1,93 @@
+"""GPU surrogate kernels against the FP64 oracle network: forward outputs,
+loss and every gradient on the same (BF16-rounded) weights, and a short
+training run that lowers the loss."""
+import numpy as np
+import pytest
+
+from oracle import fno as ofno
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def flat_to_dict(flat, cin, W, m, L):
+    K = (2 * m) * (2 * m) * m
+    d, o = {}, 0
+
+    def take(n):
+        nonlocal o
+        v = flat[o:o + n].astype(np.float64)
+        o += n
+        return v
+    d["P"] = take(W * cin).reshape(W, cin)
+    d["p"] = take(W)
+    d["Q"] = take(W)
+    d["q0"] = take(1)
+    for l in range(L):
+        r = take(K * W * W * 2).reshape(K, W, W, 2)
+        d[f"R{l}"] = r[..., 0] + 1j * r[..., 1]
+        d[f"W{l}"] = take(W * W).reshape(W, W)
+        d[f"b{l}"] = take(W)
+    assert o == flat.size
+    return d
+
+
+def dict_to_flat(d, L):
+    parts = [d["P"].ravel(), d["p"], d["Q"], d["q0"]]
+    for l in range(L):
+        R = d[f"R{l}"]
+        parts += [np.stack([R.real, R.imag], axis=-1).ravel(), d[f"W{l}"].ravel(), d[f"b{l}"]]
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("n,cin,W,m,L,B,bf16", [(16, 3, 4, 2, 2, 2, False), (16, 3, 32, 8, 4, 2, True),
+                                                (32, 3, 8, 4, 3, 1, True)])
+def test_forward_and_gradients_match_oracle(n, cin, W, m, L, B, bf16):
+    import torch
+    from paper_2205_06690_amd import bse
+    rng = np.random.default_rng(3)
+    net = bse.Fno(n, cin=cin, width=W, modes=m, layers=L, max_batch=B, bf16_weights=bf16, seed=5)
+    p = net.get_params()
+    p = p + 0.05 * rng.standard_normal(p.size).astype(np.float32)   # biases non-zero too
+    net.set_params(p)
+    pc = net.get_params(compute=True)                                 # the weights the kernels use
+    x = rng.standard_normal((B, cin, n, n, n)).astype(np.float32)
+    t = rng.standard_normal((B, n, n, n)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    td = torch.from_numpy(t).cuda()
+    yd = torch.empty((B, n, n, n), dtype=torch.float32, device="cuda")
+    net.forward(B, xd.data_ptr(), yd.data_ptr())
+    d = flat_to_dict(pc, cin, W, m, L)
+    y_o, _ = ofno.forward(d, x.astype(np.float64), n, m, L)
+    ey = np.abs(yd.cpu().numpy() - y_o).max() / np.abs(y_o).max()
+    loss, g = net.loss_grad(B, xd.data_ptr(), td.data_ptr())
+    loss_o, g_o = ofno.loss_and_grad(d, x.astype(np.float64), t.astype(np.float64), n, m, L)
+    gf = dict_to_flat(g_o, L)
+    eg = np.linalg.norm(g - gf) / np.linalg.norm(gf)
+    say(f"fno n={n} W={W} m={m} L={L}: rel|dy| {ey:.2e}  loss {loss:.6f} vs {loss_o:.6f}  rel|dgrad| {eg:.2e}")
+    assert ey < 1e-4
+    assert abs(loss - loss_o) < 1e-5 * abs(loss_o)
+    assert eg < 1e-4
+    # every parameter family separately
+    gd = flat_to_dict(g, cin, W, m, L)
+    for k in g_o:
+        nrm = np.linalg.norm(g_o[k])
+        if nrm > 0:
+            assert np.linalg.norm(gd[k] - g_o[k]) / nrm < 1e-3, k
+
+
+def test_training_lowers_loss():
+    import torch
+    from paper_2205_06690_amd import bse
+    n, B = 16, 4
+    rng = np.random.default_rng(0)
+    net = bse.Fno(n, cin=3, width=16, modes=4, layers=4, max_batch=B, seed=1)
+    x = torch.from_numpy(rng.standard_normal((B, 3, n, n, n)).astype(np.float32)).cuda()
+    # a smooth target: a fixed linear map of the first channel
+    k = np.fft.fftfreq(n) * n
+    filt = 1.0 / (1.0 + k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
+    t = np.real(np.fft.ifftn(np.fft.fftn(x[:, 0].cpu().numpy(), axes=(1, 2, 3)) * filt, axes=(1, 2, 3)))
+    t = torch.from_numpy((-0.5 * t).astype(np.float32)).cuda()
+    losses = [net.train_step(B, x.data_ptr(), t.data_ptr(), 3e-3) for _ in range(60)]
+    say("training losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
