@@ -215,7 +215,25 @@ bse_status bse_fno_loss_grad(bse_fno* fno, int32_t B, const void* x_dev, const v
 bse_status bse_fno_train_step(bse_fno* fno, int32_t B, const void* x_dev, const void* t_dev,
                               double lr, double* loss);
 const char* bse_fno_last_error(void);
+int32_t bse_fno_max_batch(const bse_fno* fno);
 void bse_fno_destroy(bse_fno* fno);
+
+/* Training samples for the surrogate from a system's pairs pq[n_pairs][2]
+ * (host): x_dev[n][3][ng] (FP32) receives q/s, the ground-state density
+ * 2 sum_occ phi^2 divided by its maximum, and V_ext divided by max|V_ext|,
+ * with s the RMS of q; t_dev (nullable, FP32 [n][ng]) receives W^pol/s from
+ * the propagation (bse_apply_W); scale_dev (nullable, FP64 [n]) receives s.
+ * The grid of the system must be that of the network. */
+bse_status bse_fno_make_samples(bse_system* sys, int32_t n_pairs, const int32_t* pq, void* x_dev,
+                                void* t_dev, void* scale_dev);
+
+/* Surrogate W-action: W = q + s * net(x) for the pairs pq (host) into
+ * w_dev[n_pairs][ng] (device, FP64).  A prediction is accepted when
+ * 0 < <rho|W rho> and <rho|W^pol rho> < 0 (rho = phi_p phi_q); accepted[k]
+ * (host, nullable) reports it.  With fallback != 0 every rejected pair is
+ * recomputed by the propagation. */
+bse_status bse_apply_W_surrogate(bse_system* sys, bse_fno* net, int32_t n_pairs, const int32_t* pq,
+                                 void* w_dev, int32_t fallback, int32_t* accepted);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,8 @@ EXPORTS = (
     "bse_version", "bse_destroy_system", "bse_apply_W_batch", "bse_autotune",
     "bse_tuned_shape", "bse_fno_create", "bse_fno_num_params", "bse_fno_set_params",
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
-    "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy",
+    "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
+    "bse_fno_make_samples", "bse_apply_W_surrogate",
 )
 
 
@@ -89,6 +90,10 @@ def _load():
     lib.bse_fno_loss_grad.argtypes = [P, C.c_int32, P, P, dp, fp]
     lib.bse_fno_train_step.argtypes = [P, C.c_int32, P, P, C.c_double, dp]
     lib.bse_fno_last_error.restype = C.c_char_p
+    lib.bse_fno_max_batch.argtypes = [P]
+    lib.bse_fno_max_batch.restype = C.c_int32
+    lib.bse_fno_make_samples.argtypes = [P, C.c_int32, ip, P, P, P]
+    lib.bse_apply_W_surrogate.argtypes = [P, P, C.c_int32, ip, P, C.c_int32, ip]
     lib.bse_fno_destroy.argtypes = [P]
     lib.bse_fno_destroy.restype = None
     lib.bse_last_error.restype = C.c_char_p
@@ -285,3 +290,23 @@ class Fno:
         loss = C.c_double()
         _fcheck(LIB.bse_fno_train_step(self._h, B, C.c_void_p(x_ptr), C.c_void_p(t_ptr), lr, C.byref(loss)))
         return loss.value
+
+
+def make_samples(system: "System", pairs, x_ptr: int, t_ptr: Optional[int] = None,
+                 scale_ptr: Optional[int] = None):
+    """Surrogate inputs (and propagated targets) for a system's pairs
+    (bse_fno_make_samples)."""
+    pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    _check(LIB.bse_fno_make_samples(system._h, pq.shape[0], _iptr(pq), C.c_void_p(x_ptr),
+                                    C.c_void_p(t_ptr) if t_ptr else None,
+                                    C.c_void_p(scale_ptr) if scale_ptr else None))
+
+
+def apply_w_surrogate(system: "System", net: "Fno", pairs, w_ptr: int, fallback: bool = True):
+    """Surrogate W-action with acceptance checks (bse_apply_W_surrogate);
+    returns the per-pair acceptance flags."""
+    pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    acc = np.zeros(pq.shape[0], dtype=np.int32)
+    _check(LIB.bse_apply_W_surrogate(system._h, net._h, pq.shape[0], _iptr(pq), C.c_void_p(w_ptr),
+                                     1 if fallback else 0, _iptr(acc)))
+    return acc

@@ -155,6 +155,9 @@ struct bse_system {
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
   hipStream_t own_stream = nullptr;
+  // surrogate descriptors and buffers
+  DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
+  double n0_scale = 0, v_scale = 0;
 };
 
 namespace {
@@ -905,6 +908,135 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
   restore();
 }
 
+// ---------------------------------------------------------------------------
+// surrogate samples and surrogate W-action
+// ---------------------------------------------------------------------------
+void surrogate_descriptors(bse_system* s) {
+  if (s->n0_scale > 0) return;
+  s->n0dens.alloc(sizeof(double) * s->ng);
+  HIPC(launch_ground_density(s->phi64.as<double>(), s->cfg.n_occ, s->ng, s->n0dens.as<double>(), s->stream));
+  std::vector<double> h(s->ng);
+  HIPC(hipMemcpyAsync(h.data(), s->n0dens.p, sizeof(double) * s->ng, hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
+  double m0 = 0, mv = 0;
+  for (size_t i = 0; i < s->ng; ++i) {
+    m0 = std::max(m0, std::fabs(h[i]));
+    mv = std::max(mv, std::fabs(s->vext[i]));
+  }
+  s->vdev.alloc(sizeof(double) * s->ng);
+  HIPC(hipMemcpy(s->vdev.p, s->vext.data(), sizeof(double) * s->ng, hipMemcpyHostToDevice));
+  s->n0_scale = m0 > 0 ? 1.0 / m0 : 1.0;
+  s->v_scale = mv > 0 ? 1.0 / mv : 1.0;
+}
+
+// q for the B pairs in s->pq_d (into s->q, rho into s->rho64) and their RMS
+// scales (device s->fscale, host copy returned)
+std::vector<double> source_and_scale(bse_system* s, int B) {
+  HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, s->ng, s->rho64.as<double>(), s->stream));
+  poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0);
+  s->fdots.alloc(sizeof(double) * 3 * B);
+  HIPC(launch_row_dots(s->q.as<double>(), nullptr, nullptr, B, s->ng, s->fdots.as<double>(), s->stream));
+  std::vector<double> dots(3 * (size_t)B), sc(B);
+  HIPC(hipMemcpyAsync(dots.data(), s->fdots.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
+  for (int b = 0; b < B; ++b) {
+    sc[b] = std::sqrt(dots[3 * (size_t)b] / (double)s->ng);
+    if (!(sc[b] > 0)) fail(BSE_ERR_NUMERIC, "pair density with zero source potential");
+  }
+  s->fscale.alloc(sizeof(double) * B);
+  HIPC(hipMemcpyAsync(s->fscale.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, s->stream));
+  return sc;
+}
+
+void make_samples(bse_system* s, int n_pairs, const int32_t* pq, float* x, float* t, double* scale_out) {
+  check_ready(s);
+  if (n_pairs < 1 || !pq || !x) fail(BSE_ERR_ARG, "bse_fno_make_samples: bad arguments");
+  for (int k = 0; k < n_pairs; ++k)
+    if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
+      fail(BSE_ERR_ARG, "pair index out of range");
+  surrogate_descriptors(s);
+  const int Bmax = std::max(1, s->cfg.max_batch);
+  for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
+    const int B = std::min(Bmax, n_pairs - k0);
+    if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, B);
+    else ensure_batch<float>(s, B);
+    HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
+    if (t) {
+      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
+      else propagate_batch<float>(s, B);
+    }
+    source_and_scale(s, B);
+    HIPC(launch_features(s->q.as<double>(), s->fscale.as<double>(), s->n0dens.as<double>(), s->n0_scale,
+                         s->vdev.as<double>(), s->v_scale, B, s->ng, x + (size_t)k0 * 3 * s->ng, s->stream));
+    if (t)
+      HIPC(launch_targets(s->wpol.as<double>(), s->fscale.as<double>(), B, s->ng, t + (size_t)k0 * s->ng,
+                          s->stream));
+    if (scale_out)
+      HIPC(hipMemcpyAsync(scale_out + k0, s->fscale.p, sizeof(double) * B, hipMemcpyDeviceToDevice, s->stream));
+  }
+  HIPC(hipStreamSynchronize(s->stream));
+}
+
+void apply_w_surrogate(bse_system* s, bse_fno* net, int n_pairs, const int32_t* pq, double* w_dev,
+                       int fallback, int32_t* accepted) {
+  check_ready(s);
+  if (!net || n_pairs < 1 || !pq || !w_dev) fail(BSE_ERR_ARG, "bse_apply_W_surrogate: bad arguments");
+  for (int k = 0; k < n_pairs; ++k)
+    if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
+      fail(BSE_ERR_ARG, "pair index out of range");
+  surrogate_descriptors(s);
+  const int Bmax = std::max(1, std::min(s->cfg.max_batch, bse_fno_max_batch(net)));
+  std::vector<int32_t> acc(n_pairs, 0);
+  HIPC(bse_fno_set_stream(net, s->stream) == BSE_OK ? hipSuccess : hipErrorInvalidValue);
+  for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
+    const int B = std::min(Bmax, n_pairs - k0);
+    if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, B);
+    else ensure_batch<float>(s, B);
+    s->fx.alloc(sizeof(float) * 3 * s->ng * B);
+    s->fy.alloc(sizeof(float) * s->ng * B);
+    s->fwpol.alloc(sizeof(double) * s->ng * B);
+    HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
+    source_and_scale(s, B);
+    HIPC(launch_features(s->q.as<double>(), s->fscale.as<double>(), s->n0dens.as<double>(), s->n0_scale,
+                         s->vdev.as<double>(), s->v_scale, B, s->ng, s->fx.as<float>(), s->stream));
+    if (bse_fno_forward(net, B, s->fx.p, s->fy.p) != BSE_OK)
+      fail(BSE_ERR_DEVICE, std::string("surrogate forward: ") + bse_fno_last_error());
+    HIPC(launch_assemble_w(s->q.as<double>(), s->fscale.as<double>(), s->fy.as<float>(), B, s->ng,
+                           s->fwpol.as<double>(), w_dev + (size_t)k0 * s->ng, s->stream));
+    // acceptance: 0 < <rho|W rho> and <rho|W^pol rho> < 0 (screening lowers
+    // the Coulomb energy of the pair density without reversing its sign)
+    HIPC(launch_row_dots(s->rho64.as<double>(), s->q.as<double>(), s->fwpol.as<double>(), B, s->ng,
+                         s->fdots.as<double>(), s->stream));
+    std::vector<double> dots(3 * (size_t)B);
+    HIPC(hipMemcpyAsync(dots.data(), s->fdots.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    for (int b = 0; b < B; ++b) {
+      const double e0 = dots[3 * (size_t)b + 1], e = dots[3 * (size_t)b + 2];
+      acc[k0 + b] = (std::isfinite(e) && e < 0.0 && e > -e0) ? 1 : 0;
+    }
+  }
+  if (fallback) {
+    std::vector<int32_t> rej;
+    std::vector<int> idx;
+    for (int k = 0; k < n_pairs; ++k)
+      if (!acc[k]) {
+        rej.push_back(pq[2 * k]);
+        rej.push_back(pq[2 * k + 1]);
+        idx.push_back(k);
+      }
+    if (!idx.empty()) {
+      DBuf tmp;
+      tmp.alloc(sizeof(double) * s->ng * idx.size());
+      apply_w_device(s, (int)idx.size(), rej.data(), tmp.as<double>(), nullptr, nullptr);
+      for (size_t j = 0; j < idx.size(); ++j)
+        HIPC(hipMemcpyAsync(w_dev + (size_t)idx[j] * s->ng, tmp.as<double>() + j * s->ng,
+                            sizeof(double) * s->ng, hipMemcpyDeviceToDevice, s->stream));
+      HIPC(hipStreamSynchronize(s->stream));
+    }
+  }
+  if (accepted) std::memcpy(accepted, acc.data(), sizeof(int32_t) * n_pairs);
+}
+
 #define API_BEGIN try {
 #define API_END                 \
   }                             \
@@ -1136,6 +1268,21 @@ bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const in
                              const int32_t* const* pq, void* const* w_dev, int32_t use_graph) {
   API_BEGIN
   apply_w_batch(n_sys, systems, n_pairs, pq, w_dev, use_graph);
+  API_END
+}
+
+bse_status bse_fno_make_samples(bse_system* s, int32_t n_pairs, const int32_t* pq, void* x_dev,
+                                void* t_dev, void* scale_dev) {
+  API_BEGIN
+  make_samples(s, n_pairs, pq, reinterpret_cast<float*>(x_dev), reinterpret_cast<float*>(t_dev),
+               reinterpret_cast<double*>(scale_dev));
+  API_END
+}
+
+bse_status bse_apply_W_surrogate(bse_system* s, bse_fno* net, int32_t n_pairs, const int32_t* pq,
+                                 void* w_dev, int32_t fallback, int32_t* accepted) {
+  API_BEGIN
+  apply_w_surrogate(s, net, n_pairs, pq, reinterpret_cast<double*>(w_dev), fallback, accepted);
   API_END
 }
 

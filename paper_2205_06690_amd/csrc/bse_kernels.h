@@ -27,3 +27,15 @@ hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipS
 hipError_t launch_ritz(const double* V, int n, int m, const double* s, double* out, hipStream_t st);
 hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipStream_t st);
 }  // namespace bse
+
+namespace bse {
+hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double* n0, hipStream_t st);
+hipError_t launch_row_dots(const double* a, const double* c, const double* d, int B, size_t ng,
+                           double* out, hipStream_t st);
+hipError_t launch_features(const double* q, const double* scale, const double* n0, double n0s,
+                           const double* v, double vs, int B, size_t ng, float* x, hipStream_t st);
+hipError_t launch_targets(const double* wpol, const double* scale, int B, size_t ng, float* t,
+                          hipStream_t st);
+hipError_t launch_assemble_w(const double* q, const double* scale, const float* y, int B, size_t ng,
+                             double* wpol, double* w, hipStream_t st);
+}  // namespace bse

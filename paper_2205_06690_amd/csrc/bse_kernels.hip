@@ -423,3 +423,114 @@ hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipS
 }
 
 }  // namespace bse
+
+namespace bse {
+
+// ---------------------------------------------------------------------------
+// surrogate features and acceptance checks
+// ---------------------------------------------------------------------------
+// n0(r) = 2 sum_{s < n_occ} phi_s(r)^2 (ground-state density)
+__global__ void k_ground_density(const double* __restrict__ phi, int n_occ, size_t ng,
+                                 double* __restrict__ n0) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  double acc = 0;
+  for (int s = 0; s < n_occ; ++s) {
+    const double v = phi[(size_t)s * ng + r];
+    acc += v * v;
+  }
+  n0[r] = 2.0 * acc;
+}
+
+// per-row sums: out[b][0] = sum a*a, out[b][1] = sum a*c (c nullable), out[b][2] = sum a*d
+__global__ void __launch_bounds__(256) k_row_dots(const double* __restrict__ a,
+                                                  const double* __restrict__ c,
+                                                  const double* __restrict__ d, size_t ng,
+                                                  double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (size_t r = threadIdx.x; r < ng; r += 256) {
+    const double v = a[(size_t)b * ng + r];
+    s0 += v * v;
+    if (c) s1 += v * c[(size_t)b * ng + r];
+    if (d) s2 += v * d[(size_t)b * ng + r];
+  }
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k)
+      for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) out[(size_t)b * 3 + j] = red[j][0];
+}
+
+// x[b][0] = q_b / s_b, x[b][1] = n0 * n0_scale, x[b][2] = V * v_scale
+__global__ void k_features(const double* __restrict__ q, const double* __restrict__ scale,
+                           const double* __restrict__ n0, double n0s, const double* __restrict__ v,
+                           double vs, size_t ng, float* __restrict__ x) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (r >= ng) return;
+  float* xb = x + (size_t)b * 3 * ng;
+  xb[r] = (float)(q[(size_t)b * ng + r] / scale[b]);
+  xb[ng + r] = (float)(n0[r] * n0s);
+  xb[2 * ng + r] = (float)(v[r] * vs);
+}
+
+// t[b] = wpol_b / s_b (FP32)
+__global__ void k_targets(const double* __restrict__ wpol, const double* __restrict__ scale, size_t ng,
+                          float* __restrict__ t) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (r >= ng) return;
+  t[(size_t)b * ng + r] = (float)(wpol[(size_t)b * ng + r] / scale[b]);
+}
+
+// wpol_b = s_b y_b (FP64), w_b = q_b + wpol_b
+__global__ void k_assemble_w(const double* __restrict__ q, const double* __restrict__ scale,
+                             const float* __restrict__ y, size_t ng, double* __restrict__ wpol,
+                             double* __restrict__ w) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (r >= ng) return;
+  const size_t i = (size_t)b * ng + r;
+  const double p = scale[b] * (double)y[i];
+  wpol[i] = p;
+  w[i] = q[i] + p;
+}
+
+hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double* n0, hipStream_t st) {
+  hipLaunchKernelGGL(k_ground_density, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, phi, n_occ,
+                     ng, n0);
+  return hipGetLastError();
+}
+hipError_t launch_row_dots(const double* a, const double* c, const double* d, int B, size_t ng,
+                           double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_dots, dim3(B), dim3(256), 0, st, a, c, d, ng, out);
+  return hipGetLastError();
+}
+hipError_t launch_features(const double* q, const double* scale, const double* n0, double n0s,
+                           const double* v, double vs, int B, size_t ng, float* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((ng + 255) / 256), B), dim3(256), 0, st, q, scale, n0,
+                     n0s, v, vs, ng, x);
+  return hipGetLastError();
+}
+hipError_t launch_targets(const double* wpol, const double* scale, int B, size_t ng, float* t,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_targets, dim3((unsigned)((ng + 255) / 256), B), dim3(256), 0, st, wpol, scale,
+                     ng, t);
+  return hipGetLastError();
+}
+hipError_t launch_assemble_w(const double* q, const double* scale, const float* y, int B, size_t ng,
+                             double* wpol, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble_w, dim3((unsigned)((ng + 255) / 256), B), dim3(256), 0, st, q, scale,
+                     y, ng, wpol, w);
+  return hipGetLastError();
+}
+
+}  // namespace bse

@@ -258,6 +258,7 @@ bse_status bse_fno_create(const bse_fno_config* cfg, bse_fno** out) {
 }
 
 int64_t bse_fno_num_params(const bse_fno* f) { return f ? (int64_t)f->n_params : -1; }
+int32_t bse_fno_max_batch(const bse_fno* f) { return f ? f->cfg.max_batch : 0; }
 
 bse_status bse_fno_set_params(bse_fno* f, const float* host) {
   FAPI_BEGIN

@@ -247,13 +247,17 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 }
 
 // out[b][o][r] = sum_i Wm[o][i] in[b][i][r] + bias[o] (+ add[b][o][r]);
-// act: 0 none, 1 gelu (pre-activation kept in zout when non-null)
+// act: 0 none, 1 gelu (pre-activation kept in zout when non-null).
+// CIN/COUT > 0: compile-time channel counts (inputs stay in registers).
 constexpr int PW_MAXC = 64;
-__global__ void __launch_bounds__(256) k_pointwise(const float* __restrict__ in, int Cin,
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_pointwise(const float* __restrict__ in, int Cin_,
                                                    const float* __restrict__ Wm,
-                                                   const float* __restrict__ bias, int Cout,
+                                                   const float* __restrict__ bias, int Cout_,
                                                    const float* __restrict__ add, size_t ng, int act,
                                                    float* __restrict__ zout, float* __restrict__ out) {
+  const int Cin = CIN > 0 ? CIN : Cin_;
+  const int Cout = COUT > 0 ? COUT : Cout_;
   __shared__ float sw[PW_MAXC * PW_MAXC];
   __shared__ float sb[PW_MAXC];
   for (int e = threadIdx.x; e < Cin * Cout; e += 256) sw[e] = Wm[e];
@@ -262,11 +266,16 @@ __global__ void __launch_bounds__(256) k_pointwise(const float* __restrict__ in,
   const size_t r = (size_t)blockIdx.x * 256 + threadIdx.x;
   const int b = blockIdx.y;
   if (r >= ng) return;
-  float xin[PW_MAXC];
-  for (int i = 0; i < Cin; ++i) xin[i] = in[((size_t)b * Cin + i) * ng + r];
+  float xin[CIN > 0 ? CIN : PW_MAXC];
+#pragma unroll
+  for (int i = 0; i < (CIN > 0 ? CIN : PW_MAXC); ++i)
+    if (i < Cin) xin[i] = in[((size_t)b * Cin + i) * ng + r];
+#pragma unroll 4
   for (int o = 0; o < Cout; ++o) {
     float acc = sb[o];
-    for (int i = 0; i < Cin; ++i) acc += sw[o * Cin + i] * xin[i];
+#pragma unroll
+    for (int i = 0; i < (CIN > 0 ? CIN : PW_MAXC); ++i)
+      if (i < Cin) acc += sw[o * Cin + i] * xin[i];
     const size_t oi = ((size_t)b * Cout + o) * ng + r;
     if (add) acc += add[oi];
     if (zout) zout[oi] = acc;
@@ -274,21 +283,28 @@ __global__ void __launch_bounds__(256) k_pointwise(const float* __restrict__ in,
   }
 }
 
-// gin[b][i][r] = sum_o Wm[o][i] gz[b][o][r] (+ add)
-__global__ void __launch_bounds__(256) k_pointwise_bwd(const float* __restrict__ gz, int Cout,
+// gin[b][i][r] += sum_o Wm[o][i] gz[b][o][r]
+template <int COUT>
+__global__ void __launch_bounds__(256) k_pointwise_bwd(const float* __restrict__ gz, int Cout_,
                                                        const float* __restrict__ Wm, int Cin,
                                                        size_t ng, float* __restrict__ gin) {
+  const int Cout = COUT > 0 ? COUT : Cout_;
   __shared__ float sw[PW_MAXC * PW_MAXC];
   for (int e = threadIdx.x; e < Cin * Cout; e += 256) sw[e] = Wm[e];
   __syncthreads();
   const size_t r = (size_t)blockIdx.x * 256 + threadIdx.x;
   const int b = blockIdx.y;
   if (r >= ng) return;
-  float g[PW_MAXC];
-  for (int o = 0; o < Cout; ++o) g[o] = gz[((size_t)b * Cout + o) * ng + r];
+  float g[COUT > 0 ? COUT : PW_MAXC];
+#pragma unroll
+  for (int o = 0; o < (COUT > 0 ? COUT : PW_MAXC); ++o)
+    if (o < Cout) g[o] = gz[((size_t)b * Cout + o) * ng + r];
+#pragma unroll 4
   for (int i = 0; i < Cin; ++i) {
     float acc = 0.f;
-    for (int o = 0; o < Cout; ++o) acc += sw[o * Cin + i] * g[o];
+#pragma unroll
+    for (int o = 0; o < (COUT > 0 ? COUT : PW_MAXC); ++o)
+      if (o < Cout) acc += sw[o * Cin + i] * g[o];
     gin[((size_t)b * Cin + i) * ng + r] += acc;
   }
 }
@@ -507,14 +523,24 @@ hipError_t fno_pointwise(const float* in, int Cin, const float* Wm, const float*
                          const float* add, int B, size_t ng, int act, float* zout, float* out,
                          hipStream_t st) {
   if (Cin > PW_MAXC || Cout > PW_MAXC) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pointwise, dim3(nb(ng), B), dim3(256), 0, st, in, Cin, Wm, bias, Cout, add, ng,
-                     act, zout, out);
+  const dim3 g(nb(ng), B);
+  if (Cin == 3 && Cout == 32)
+    hipLaunchKernelGGL((k_pointwise<3, 32>), g, dim3(256), 0, st, in, Cin, Wm, bias, Cout, add, ng, act, zout, out);
+  else if (Cin == 32 && Cout == 32)
+    hipLaunchKernelGGL((k_pointwise<32, 32>), g, dim3(256), 0, st, in, Cin, Wm, bias, Cout, add, ng, act, zout, out);
+  else if (Cin == 32 && Cout == 1)
+    hipLaunchKernelGGL((k_pointwise<32, 1>), g, dim3(256), 0, st, in, Cin, Wm, bias, Cout, add, ng, act, zout, out);
+  else
+    hipLaunchKernelGGL((k_pointwise<0, 0>), g, dim3(256), 0, st, in, Cin, Wm, bias, Cout, add, ng, act, zout, out);
   return hipGetLastError();
 }
 hipError_t fno_pointwise_bwd(const float* gz, int Cout, const float* Wm, int Cin, int B, size_t ng,
                              float* gin, hipStream_t st) {
   if (Cin > PW_MAXC || Cout > PW_MAXC) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pointwise_bwd, dim3(nb(ng), B), dim3(256), 0, st, gz, Cout, Wm, Cin, ng, gin);
+  if (Cout == 32)
+    hipLaunchKernelGGL((k_pointwise_bwd<32>), dim3(nb(ng), B), dim3(256), 0, st, gz, Cout, Wm, Cin, ng, gin);
+  else
+    hipLaunchKernelGGL((k_pointwise_bwd<0>), dim3(nb(ng), B), dim3(256), 0, st, gz, Cout, Wm, Cin, ng, gin);
   return hipGetLastError();
 }
 hipError_t fno_gelu_bwd(float* gh, const float* z, size_t n, hipStream_t st) {
