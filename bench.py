@@ -127,6 +127,77 @@ def bench_uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """The learned screening surrogate: trained on 4096 pair densities of 20
+    mid-size molecules (seeds 100-119), judged on 512 held-out pairs of 3
+    others (seeds 200-202) against the propagation that generated them."""
+    import torch
+    from paper_2205_06690_amd import bse, surrogate
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    tr_specs = surrogate.surrogate_specs(range(100, 120), n_steps=args.sur_steps)
+    te_specs = surrogate.surrogate_specs(range(200, 203), n_steps=args.sur_steps)
+    x_tr, t_tr, s_tr = surrogate.generate(tr_specs, limit=args.n_train, log=log)
+    x_te, t_te, s_te = surrogate.generate(te_specs, limit=args.n_test, log=log)
+    t_gen = time.perf_counter() - t0
+    net = bse.Fno(64, cin=3, width=32, modes=args.modes, layers=4, max_batch=args.sur_batch,
+                  bf16_weights=True, seed=0)
+    t1 = time.perf_counter()
+    hist = surrogate.train(net, x_tr, t_tr, epochs=args.epochs, batch=args.sur_batch, lr=args.lr,
+                           lr_end=args.lr * 0.01, log=log, time_limit=args.train_seconds)
+    t_train = time.perf_counter() - t1
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    y = surrogate.predict(net, x_te, args.sur_batch)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t2) / x_te.shape[0]
+    x0 = x_te[:, 0].double()
+    tt, yy = t_te.double(), y.double()
+    rel_wpol = (torch.linalg.norm(yy - tt, dim=1) / torch.linalg.norm(tt, dim=1)).cpu().numpy()
+    rel_w = (torch.linalg.norm(yy - tt, dim=1) / torch.linalg.norm(x0 + tt, dim=1)).cpu().numpy()
+    rel_w_q = (torch.linalg.norm(tt, dim=1) / torch.linalg.norm(x0 + tt, dim=1)).cpu().numpy()
+    # acceptance and cost on the first held-out molecule: surrogate vs propagation
+    from paper_2205_06690_amd import inputs
+    spec = te_specs[0]
+    S = surrogate.open_system(spec, inputs.make_system(spec))
+    pairs = surrogate.system_pairs(spec)
+    w = torch.empty((len(pairs), spec.ng), dtype=torch.float64, device="cuda")
+    bse.apply_w_surrogate(S, net, pairs[:8], w.data_ptr(), fallback=False)      # warm-up
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    acc = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), fallback=False)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t3) / len(pairs)
+    t4 = time.perf_counter()
+    S.apply_w_device(pairs, w.data_ptr())
+    torch.cuda.synchronize()
+    t_prop = (time.perf_counter() - t4) / len(pairs)
+    out = {
+        "metric": "surrogate W-action: held-out relative error on W and W^pol, time per pair",
+        "config": {"workload": f"64^3 Gaussian-well molecules (60 wells, N_occ=120), train seeds 100-119 "
+                               f"({x_tr.shape[0]} pairs), held out seeds 200-202 ({x_te.shape[0]} pairs), "
+                               f"targets from {args.sur_steps}-step propagation (L=10, dt=0.05); network: "
+                               f"4 Fourier layers, width 32, modes kx,ky in [-{args.modes},{args.modes}), "
+                               f"kz in [0,{args.modes}), BF16 weights, FP32 accumulation",
+                   "params": net.n_params, "epochs_run": len(hist), "batch": args.sur_batch},
+        "train_loss": [round(v, 6) for v in hist],
+        "heldout_rel_err_Wpol": {"median": float(np.median(rel_wpol)), "p90": float(np.quantile(rel_wpol, 0.9))},
+        "heldout_rel_err_W": {"median": float(np.median(rel_w)), "p90": float(np.quantile(rel_w, 0.9)),
+                              "frac_below_1e-3": float(np.mean(rel_w < 1e-3)),
+                              "frac_below_1e-2": float(np.mean(rel_w < 1e-2))},
+        "no_network_rel_err_W": {"median": float(np.median(rel_w_q)), "note": "W approximated by q"},
+        "accepted_fraction": float(np.mean(acc)),
+        "ms_per_pair_surrogate": round(t_sur * 1e3, 3),
+        "ms_per_pair_propagation": round(t_prop * 1e3, 3),
+        "ms_per_pair_inference_only": round(t_inf * 1e3, 3),
+        "seconds": {"data": round(t_gen, 1), "train": round(t_train, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +208,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--n-systems", type=int, default=32)
+    ap.add_argument("--n-train", type=int, default=4096)
+    ap.add_argument("--n-test", type=int, default=512)
+    ap.add_argument("--sur-steps", type=int, default=200)
+    ap.add_argument("--sur-batch", type=int, default=8)
+    ap.add_argument("--modes", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--train-seconds", type=float, default=420.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -149,6 +228,9 @@ def main():
 
     if args.config == "uneven32":
         bench_uneven(args)
+        return
+    if args.config == "surrogate":
+        bench_surrogate(args)
         return
 
     import torch
