@@ -133,6 +133,7 @@ struct bse_system {
   std::vector<double> eps;
   DBuf phi64;     // [n_orb][ng] FP64
   DBuf phi_occ32; // [n_occ][ng] FP32 (mixed)
+  DBuf phih, phil, phith, phitl;  // bf16 hi/lo splits of phi_occ32, [n_occ][ng] and [ng][Sp]
   std::vector<int8_t> xi;
   bool signs_given = false;
   DBuf xi_d;
@@ -244,7 +245,7 @@ void ensure_batch(bse_system* s, int B) {
   s->part.alloc(sizeof(cplx<double>) * (size_t)s->nchunk * std::max(F, L) * (S + 1));
   s->coef.alloc(sizeof(cplx<double>) * (size_t)F * (S + 1));
   if (sizeof(T) == 4) {
-    s->part32.alloc(sizeof(float) * coef_part_floats(std::max(F, L), S, ng, chunk));
+    s->part32.alloc(sizeof(float) * clean_scratch_floats(F, L, S, ng));
     s->gpart.alloc(sizeof(cplx<double>) * edot_part_entries(F, ng));
   }
   s->coefE.alloc(sizeof(cplx<double>) * (size_t)L * (S + 1));
@@ -286,6 +287,10 @@ void clean(bse_system* s, int B, int from_mid, const cplx<T>* H) {
   c.eta0 = s->eta0.as<double>();
   c.part32 = s->part32.as<float>();
   c.gpart = s->gpart.as<cplx<double>>();
+  c.phih = s->phih.as<unsigned short>();
+  c.phil = s->phil.as<unsigned short>();
+  c.phith = s->phith.as<unsigned short>();
+  c.phitl = s->phitl.as<unsigned short>();
   auto* t = s->timer.begin("clean");
   HIPC(launch_clean<T>(c, s->stream));
   s->timer.end(t);
@@ -1152,6 +1157,15 @@ bse_status bse_set_orbitals(bse_system* s, int32_t n_orb, const double* phi, con
     const size_t no = (size_t)s->cfg.n_occ * s->ng;
     s->phi_occ32.alloc(sizeof(float) * no);
     HIPC(launch_to_real<float>(s->phi64.as<double>(), no, s->phi_occ32.as<float>(), s->stream));
+    const size_t nt = (size_t)clean_sp(s->cfg.n_occ) * s->ng;
+    s->phih.alloc(sizeof(unsigned short) * no);
+    s->phil.alloc(sizeof(unsigned short) * no);
+    s->phith.alloc(sizeof(unsigned short) * nt);
+    s->phitl.alloc(sizeof(unsigned short) * nt);
+    HIPC(launch_phi_split(s->phi_occ32.as<float>(), s->cfg.n_occ, s->ng,
+                          PhiSplitBufs{s->phih.as<unsigned short>(), s->phil.as<unsigned short>(),
+                                       s->phith.as<unsigned short>(), s->phitl.as<unsigned short>()},
+                          s->stream));
     prepare_unperturbed<float>(s);
   } else {
     prepare_unperturbed<double>(s);

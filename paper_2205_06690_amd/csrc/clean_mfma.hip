@@ -1,105 +1,238 @@
 // Cleaning projection of the perturbed stochastic orbitals (Eq. 15,
-// linearised) on the FP32 matrix cores of gfx950.
+// linearised) on the gfx950 matrix cores, in three-term BF16 arithmetic.
 //
 //   coefficients  C[f][s] = h^3 sum_r phi_s(r) d_f(r)       (split-K GEMM)
 //   update        d_f(r) -= sum_s C[f][s] phi_s(r) + c_f E_l(r)
 //
 // Complex fields are viewed as two real rows (2f: real part, 2f+1:
-// imaginary part), the occupied orbitals are real, so both products are real
+// imaginary part); the occupied orbitals are real, so both products are real
 // GEMMs: rows x states over K = grid points, and rows x points over
-// K = states.  v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; the 16x16 result sits in lane l as D[4(l/16)+v][l%16],
-// v = 0..3.
+// K = states.  Each FP32 operand x is split as x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi), and a.b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (the
+// dropped lo.lo term is ~2^-16 of the product); products accumulate in FP32
+// per tile, tiles over K chunks in FP64.  The occupied orbitals are split
+// once per orbital set, in both layouts the two GEMMs read.
+//
+// v_mfma_f32_16x16x32_bf16: lane l supplies row (l%16) of A and column (l%16)
+// of B, each as 8 consecutive K values starting at 8(l/16); the 16x16 result
+// sits in lane l as D[4(l/16)+v][l%16], v = 0..3.
+//
+// The end of the time step (d <- Ph (d - i dt/2 u_b H_l), Strang splitting)
+// is applied on the fly by the coefficient GEMM's loader and again by the
+// update's epilogue, so the perturbed set is read once by each GEMM and
+// written once.
 #include <hip/hip_runtime.h>
 
 #include "clean_mfma.h"
 
+#include <algorithm>
+
 namespace bse {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int CM_BM = 128, CM_BN = 128, CM_BK = 32, CM_PAD = 4;
+constexpr int XT = 128;       // tile rows and columns
+constexpr int XK = 32;        // K per stage: one 16x16x32 step
+constexpr int XKP = XK + 8;   // padded LDS row in bf16 (80 bytes, 16-byte aligned)
 
-// part[kc][row][s] (row < 2F, s < S) = sum over chunk kc of A[row][r] phi_s(r).
-// Global loads of stage k+1 are issued into registers before the matrix-core
-// work of stage k.
-__global__ void __launch_bounds__(256) k_coef_mfma(const float2* __restrict__ d, int F,
-                                                   const float* __restrict__ phi, int S,
-                                                   size_t ng, int chunk,
-                                                   float* __restrict__ part) {
-  __shared__ float As[CM_BK][CM_BM + CM_PAD];
-  __shared__ float Bs[CM_BK][CM_BN + CM_PAD];
-  constexpr int NA = (CM_BM / 2) * CM_BK / 256;  // float2 per thread
-  constexpr int NB = CM_BN * CM_BK / 256;        // float per thread
-  const int R = 2 * F;
-  const int r0 = blockIdx.x * CM_BM;
-  const int s0 = blockIdx.y * CM_BN;
-  const int kc = blockIdx.z;
+int clean_sp(int S) { return (S + XK - 1) / XK * XK; }
+
+__device__ __forceinline__ void split_hl(float x, unsigned short& h, unsigned short& l) {
+  const __bf16 bh = (__bf16)x;
+  const __bf16 bl = (__bf16)(x - (float)bh);
+  h = __builtin_bit_cast(unsigned short, bh);
+  l = __builtin_bit_cast(unsigned short, bl);
+}
+
+// Workgroup ids are dealt round-robin to the 8 XCDs; renumber them so that
+// each XCD works through a contiguous range of tiles (nb is a multiple of 8)
+// and tiles that share an operand tile share that XCD's L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned id, unsigned nb) {
+  return (id & 7u) * (nb >> 3) + (id >> 3);
+}
+
+__device__ __forceinline__ float2 cm(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// end of the step for one value: ph (v - i hdt u h)
+__device__ __forceinline__ float2 finish1(float2 v, float2 h, float u, float2 p, float hdt) {
+  const float cu = hdt * u;
+  return cm(p, make_float2(v.x + cu * h.y, v.y - cu * h.x));
+}
+
+__device__ __forceinline__ float2 finish_mid(const MidArgs& m, int f, size_t r, float2 v) {
+  const int b = f / m.L, l = f % m.L;
+  return finish1(v, m.H[(size_t)l * m.ng + r], m.u[(size_t)b * m.ng + r], m.ph[r], m.half_dt);
+}
+
+// One stage of MFMA work on the staged 128 x 32 tiles: wave (wm, wn) owns a
+// 64 x 64 block of 4 x 4 result tiles.
+__device__ __forceinline__ void mma_stage(const __bf16 (*Ah)[XKP], const __bf16 (*Al)[XKP],
+                                          const __bf16 (*Bh)[XKP], const __bf16 (*Bl)[XKP],
+                                          int lane, int wm, int wn, f4 (&acc)[4][4]) {
+  const int kk = 8 * (lane >> 4);
+  bf8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = wm * 64 + i * 16 + (lane & 15);
+    ah[i] = *reinterpret_cast<const bf8*>(&Ah[row][kk]);
+    al[i] = *reinterpret_cast<const bf8*>(&Al[row][kk]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = wn * 64 + j * 16 + (lane & 15);
+    bh[j] = *reinterpret_cast<const bf8*>(&Bh[col][kk]);
+    bl[j] = *reinterpret_cast<const bf8*>(&Bl[col][kk]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// phi [S][ng] FP32 -> hi/lo in [S][ng] and, zero-padded to Sp states, [ng][Sp]
+__global__ void k_phi_split(const float* __restrict__ phi, int S, int Sp, size_t ng,
+                            unsigned short* __restrict__ h, unsigned short* __restrict__ l,
+                            unsigned short* __restrict__ th, unsigned short* __restrict__ tl) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng * (size_t)Sp) return;
+  const size_t r = i / Sp;
+  const int s = (int)(i % Sp);
+  const float x = s < S ? phi[(size_t)s * ng + r] : 0.f;
+  unsigned short a, b;
+  split_hl(x, a, b);
+  th[i] = a;
+  tl[i] = b;
+  if (s < S) {
+    h[(size_t)s * ng + r] = a;
+    l[(size_t)s * ng + r] = b;
+  }
+}
+
+// part[kc][row][s] (row < 2F, s < S) = sum over chunk kc of D[row][r] phi_s(r),
+// D = d, finished on the fly when MID.  With EDOT the column-tile-0 blocks
+// also accumulate <E_l, d_f> over their chunk into gpart[f][kc] (E = Ph H_l
+// computed in registers when MID, read from E otherwise).  Global loads of
+// stage k+1 are in flight during the matrix-core work of stage k.
+template <bool MID, bool EDOT>
+__global__ void __launch_bounds__(256) k_coef_x3(const float2* __restrict__ d, int F, PhiSplit ps,
+                                                 size_t ng, int chunk, int nrt, int nct, int nchunk,
+                                                 unsigned ntile, MidArgs mid,
+                                                 const float2* __restrict__ E, int L,
+                                                 float* __restrict__ part,
+                                                 double2* __restrict__ gpart) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[XT][XKP];
+  const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntile) return;
+  const int rt = (int)(t % nrt), ct = (int)((t / nrt) % nct), kc = (int)(t / ((unsigned)nrt * nct));
+  const int R = 2 * F, S = ps.S;
+  const int r0 = rt * XT, s0 = ct * XT, f0 = r0 / 2;
   const size_t k0 = (size_t)kc * chunk;
   const size_t k1 = min(ng, k0 + (size_t)chunk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int f0 = r0 / 2;
+  const bool do_e = EDOT && ct == 0;
+  // loader: fields f0 + qa + 16i at points pa, pa+1; state s0 + sb at points hb..hb+15
+  const int qa = tid >> 4, pa = (tid & 15) * 2;
+  const int sb = tid >> 1, hb = (tid & 1) * 16;
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float2 ra[NA];
-  float rb[NB];
+  float4 ra[4], rh[4];
+  float2 ru[4];
+  float4 rp = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint4 rbh[2], rbl[2];
+  double ex[4], ey[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ex[i] = ey[i] = 0.0;
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
   auto load = [&](size_t kb) {
+    const size_t r = kb + pa;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * 256;
-      const int ff = e / CM_BK, p = e % CM_BK;
-      const int f = f0 + ff;
-      const size_t r = kb + p;
-      ra[i] = (f < F && r < k1) ? d[(size_t)f * ng + r] : make_float2(0.f, 0.f);
+    for (int i = 0; i < 4; ++i) {
+      const int f = f0 + qa + 16 * i;
+      if (f < F) {
+        ra[i] = *reinterpret_cast<const float4*>(d + (size_t)f * ng + r);
+        if (MID) {
+          rh[i] = *reinterpret_cast<const float4*>(mid.H + (size_t)(f % L) * ng + r);
+          ru[i] = *reinterpret_cast<const float2*>(mid.u + (size_t)(f / L) * ng + r);
+        } else if (do_e) {
+          rh[i] = *reinterpret_cast<const float4*>(E + (size_t)(f % L) * ng + r);
+        }
+      } else {
+        ra[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = tid + i * 256;
-      const int ss = e / CM_BK, p = e % CM_BK;
-      const int s = s0 + ss;
-      const size_t r = kb + p;
-      rb[i] = (s < S && r < k1) ? phi[(size_t)s * ng + r] : 0.f;
+    if (MID) rp = *reinterpret_cast<const float4*>(mid.ph + r);
+    const int s = s0 + sb;
+    if (s < S) {
+      const uint4* qh = reinterpret_cast<const uint4*>(ps.h + (size_t)s * ng + kb + hb);
+      const uint4* ql = reinterpret_cast<const uint4*>(ps.l + (size_t)s * ng + kb + hb);
+      rbh[0] = qh[0];
+      rbh[1] = qh[1];
+      rbl[0] = ql[0];
+      rbl[1] = ql[1];
+    } else {
+      rbh[0] = rbh[1] = rbl[0] = rbl[1] = z4;
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * 256;
-      const int ff = e / CM_BK, p = e % CM_BK;
-      As[p][2 * ff] = ra[i].x;
-      As[p][2 * ff + 1] = ra[i].y;
+    for (int i = 0; i < 4; ++i) {
+      const int ff = qa + 16 * i;
+      const int f = f0 + ff;
+      float2 v0 = make_float2(ra[i].x, ra[i].y), v1 = make_float2(ra[i].z, ra[i].w);
+      if (f < F) {
+        float2 e0, e1;
+        if (MID) {
+          const float2 h0 = make_float2(rh[i].x, rh[i].y), h1 = make_float2(rh[i].z, rh[i].w);
+          const float2 p0 = make_float2(rp.x, rp.y), p1 = make_float2(rp.z, rp.w);
+          v0 = finish1(v0, h0, ru[i].x, p0, mid.half_dt);
+          v1 = finish1(v1, h1, ru[i].y, p1, mid.half_dt);
+          e0 = cm(p0, h0);
+          e1 = cm(p1, h1);
+        } else {
+          e0 = make_float2(rh[i].x, rh[i].y);
+          e1 = make_float2(rh[i].z, rh[i].w);
+        }
+        if (do_e) {
+          ex[i] += (double)e0.x * v0.x + (double)e0.y * v0.y + (double)e1.x * v1.x + (double)e1.y * v1.y;
+          ey[i] += (double)e0.x * v0.y - (double)e0.y * v0.x + (double)e1.x * v1.y - (double)e1.y * v1.x;
+        }
+      }
+      unsigned short h0r, l0r, h1r, l1r, h0i, l0i, h1i, l1i;
+      split_hl(v0.x, h0r, l0r);
+      split_hl(v1.x, h1r, l1r);
+      split_hl(v0.y, h0i, l0i);
+      split_hl(v1.y, h1i, l1i);
+      *reinterpret_cast<unsigned*>(&Ah[2 * ff][pa]) = (unsigned)h0r | ((unsigned)h1r << 16);
+      *reinterpret_cast<unsigned*>(&Al[2 * ff][pa]) = (unsigned)l0r | ((unsigned)l1r << 16);
+      *reinterpret_cast<unsigned*>(&Ah[2 * ff + 1][pa]) = (unsigned)h0i | ((unsigned)h1i << 16);
+      *reinterpret_cast<unsigned*>(&Al[2 * ff + 1][pa]) = (unsigned)l0i | ((unsigned)l1i << 16);
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = tid + i * 256;
-      const int ss = e / CM_BK, p = e % CM_BK;
-      Bs[p][ss] = rb[i];
-    }
+    *reinterpret_cast<uint4*>(&Bh[sb][hb]) = rbh[0];
+    *reinterpret_cast<uint4*>(&Bh[sb][hb + 8]) = rbh[1];
+    *reinterpret_cast<uint4*>(&Bl[sb][hb]) = rbl[0];
+    *reinterpret_cast<uint4*>(&Bl[sb][hb + 8]) = rbl[1];
   };
   load(k0);
-  for (size_t kb = k0; kb < k1; kb += CM_BK) {
+  for (size_t kb = k0; kb < k1; kb += XK) {
     __syncthreads();
     store();
     __syncthreads();
-    if (kb + CM_BK < k1) load(kb + CM_BK);
-#pragma unroll
-    for (int k4 = 0; k4 < CM_BK / 4; ++k4) {
-      const int kk = k4 * 4 + (lane >> 4);
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][wm * 64 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][wn * 64 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+    if (kb + XK < k1) load(kb + XK);
+    mma_stage(Ah, Al, Bh, Bl, lane, wm, wn, acc);
   }
   float* out = part + (size_t)kc * R * S;
 #pragma unroll
@@ -112,17 +245,19 @@ __global__ void __launch_bounds__(256) k_coef_mfma(const float2* __restrict__ d,
         const int col = s0 + wn * 64 + j * 16 + (lane & 15);
         if (row < R && col < S) out[(size_t)row * S + col] = acc[i][j][v];
       }
-}
-
-// coefT[s][row] = (float) re/im of coef[f][s], row = 2f + c
-__global__ void k_coef_transpose(const double2* __restrict__ coef, int F, int S,
-                                 float* __restrict__ coefT) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F * S) return;
-  const int f = i % F, s = i / F;
-  const double2 c = coef[(size_t)f * (S + 1) + s];
-  coefT[(size_t)s * 2 * F + 2 * f] = (float)c.x;
-  coefT[(size_t)s * 2 * F + 2 * f + 1] = (float)c.y;
+  if (do_e) {
+    // the 16 lanes sharing qa hold the same 4 fields at different points
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double x = ex[i], y = ey[i];
+      for (int off = 8; off > 0; off >>= 1) {
+        x += __shfl_down(x, off, 16);
+        y += __shfl_down(y, off, 16);
+      }
+      const int f = f0 + qa + 16 * i;
+      if ((tid & 15) == 0 && f < F) gpart[(size_t)f * nchunk + kc] = make_double2(x, y);
+    }
+  }
 }
 
 // coef[f][s] = dv * (sum_kc part[kc][2f][s] + i sum_kc part[kc][2f+1][s]),
@@ -141,35 +276,6 @@ __global__ void k_coef_reduce(const float* __restrict__ part, int nchunk, int F,
   coef[(size_t)f * (S + 1) + s] = make_double2(x * dv, y * dv);
 }
 
-// partial <E_l, d_f> over blocks of 1024 points: gpart[f][blk]
-__global__ void __launch_bounds__(256) k_edot(const float2* __restrict__ d, const float2* __restrict__ E,
-                                              int L, size_t ng, double2* __restrict__ gpart) {
-  const int f = blockIdx.y, l = f % L;
-  const size_t base = (size_t)blockIdx.x * 1024;
-  double x = 0, y = 0;
-  for (int q = 0; q < 4; ++q) {
-    const size_t r = base + threadIdx.x + q * 256;
-    if (r < ng) {
-      const float2 a = d[(size_t)f * ng + r];
-      const float2 e = E[(size_t)l * ng + r];
-      x += (double)e.x * a.x + (double)e.y * a.y;
-      y += (double)e.x * a.y - (double)e.y * a.x;
-    }
-  }
-  __shared__ double rx[256], ry[256];
-  rx[threadIdx.x] = x;
-  ry[threadIdx.x] = y;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      rx[threadIdx.x] += rx[threadIdx.x + s];
-      ry[threadIdx.x] += ry[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) gpart[(size_t)f * gridDim.x + blockIdx.x] = make_double2(rx[0], ry[0]);
-}
-
 __global__ void k_edot_reduce(const double2* __restrict__ gpart, int nblk, int F, int S, double dv,
                               double2* __restrict__ coef) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,78 +288,93 @@ __global__ void k_edot_reduce(const double2* __restrict__ gpart, int nblk, int F
   coef[(size_t)f * (S + 1) + S] = make_double2(x * dv, y * dv);
 }
 
-// d_f(r) -= sum_s C[f][s] phi_s(r) + c_f E_l(r); rows 2f/2f+1 = re/im of C
-// (coefT[s][row], FP32).  Block: 128 rows (64 fields) x 128 points, K =
-// states in stages of 32 with register prefetch.
-__global__ void __launch_bounds__(256) k_update_mfma(float2* __restrict__ d, int F,
-                                                     const float* __restrict__ phi, int S,
-                                                     const float2* __restrict__ E, int L,
-                                                     size_t ng, const float* __restrict__ coefT,
-                                                     const double2* __restrict__ coef) {
-  __shared__ float As[CM_BK][CM_BM + CM_PAD];
-  __shared__ float Bs[CM_BK][CM_BN + CM_PAD];
-  constexpr int NA = CM_BM * CM_BK / 256;
-  constexpr int NB = CM_BN * CM_BK / 256;
-  const int R = 2 * F;
-  const size_t p0 = (size_t)blockIdx.x * CM_BN;
-  const int r0 = blockIdx.y * CM_BM;
+// coefficient rows for the update: ct[row][s], row 2f = Re C[f][s], 2f+1 =
+// Im C[f][s], split hi/lo, zero for s >= S
+__global__ void k_coef_split(const double2* __restrict__ coef, int F, int S, int Sp,
+                             unsigned short* __restrict__ cth, unsigned short* __restrict__ ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * F * Sp) return;
+  const int row = i / Sp, s = i % Sp, f = row / 2;
+  float x = 0.f;
+  if (s < S) {
+    const double2 c = coef[(size_t)f * (S + 1) + s];
+    x = (float)((row & 1) ? c.y : c.x);
+  }
+  split_hl(x, cth[i], ctl[i]);
+}
+
+// d_f(r) = fin(d_f(r)) - sum_s C[f][s] phi_s(r) - c_f E_l(r), fin the end of
+// the step when MID.  Block: 128 rows (64 fields) x 128 points, K = states
+// in stages of 32; row tile fastest so that the row tiles of one point tile
+// (sharing its phi^T tile) run together on one XCD.
+template <bool MID>
+__global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F, PhiSplit ps,
+                                                   const float2* __restrict__ E, int L, size_t ng,
+                                                   const unsigned short* __restrict__ cth,
+                                                   const unsigned short* __restrict__ ctl,
+                                                   const double2* __restrict__ coef, int nrt,
+                                                   unsigned ntile, MidArgs mid) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[XT][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[XT][XKP];
+  const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntile) return;
+  const int rt = (int)(t % nrt);
+  const size_t p0 = (size_t)(t / nrt) * XT;
+  const int r0 = rt * XT;
+  const int R = 2 * F, S = ps.S, Sp = ps.Sp;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
+  const int sb = tid >> 1, hb = (tid & 1) * 16;   // row / point sb, states hb..hb+15
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float ra[NA], rb[NB];
-  auto load = [&](int sb) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * 256;
-      const int ss = e / CM_BM, rr = e % CM_BM;
-      const int s = sb + ss, row = r0 + rr;
-      ra[i] = (s < S && row < R) ? coefT[(size_t)s * R + row] : 0.f;
+  uint4 rah[2], ral[2], rbh[2], rbl[2];
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  auto load = [&](int kb) {
+    const int row = r0 + sb;
+    if (row < R) {
+      const uint4* qh = reinterpret_cast<const uint4*>(cth + (size_t)row * Sp + kb + hb);
+      const uint4* ql = reinterpret_cast<const uint4*>(ctl + (size_t)row * Sp + kb + hb);
+      rah[0] = qh[0];
+      rah[1] = qh[1];
+      ral[0] = ql[0];
+      ral[1] = ql[1];
+    } else {
+      rah[0] = rah[1] = ral[0] = ral[1] = z4;
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = tid + i * 256;
-      const int ss = e / CM_BN, p = e % CM_BN;
-      const int s = sb + ss;
-      const size_t r = p0 + p;
-      rb[i] = (s < S && r < ng) ? phi[(size_t)s * ng + r] : 0.f;
+    const size_t pt = p0 + sb;
+    if (pt < ng) {
+      const uint4* qh = reinterpret_cast<const uint4*>(ps.th + pt * Sp + kb + hb);
+      const uint4* ql = reinterpret_cast<const uint4*>(ps.tl + pt * Sp + kb + hb);
+      rbh[0] = qh[0];
+      rbh[1] = qh[1];
+      rbl[0] = ql[0];
+      rbl[1] = ql[1];
+    } else {
+      rbh[0] = rbh[1] = rbl[0] = rbl[1] = z4;
     }
   };
   auto store = [&]() {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * 256;
-      As[e / CM_BM][e % CM_BM] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = tid + i * 256;
-      Bs[e / CM_BN][e % CM_BN] = rb[i];
-    }
+    *reinterpret_cast<uint4*>(&Ah[sb][hb]) = rah[0];
+    *reinterpret_cast<uint4*>(&Ah[sb][hb + 8]) = rah[1];
+    *reinterpret_cast<uint4*>(&Al[sb][hb]) = ral[0];
+    *reinterpret_cast<uint4*>(&Al[sb][hb + 8]) = ral[1];
+    *reinterpret_cast<uint4*>(&Bh[sb][hb]) = rbh[0];
+    *reinterpret_cast<uint4*>(&Bh[sb][hb + 8]) = rbh[1];
+    *reinterpret_cast<uint4*>(&Bl[sb][hb]) = rbl[0];
+    *reinterpret_cast<uint4*>(&Bl[sb][hb + 8]) = rbl[1];
   };
   load(0);
-  for (int sb = 0; sb < S; sb += CM_BK) {
+  for (int kb = 0; kb < Sp; kb += XK) {
     __syncthreads();
     store();
     __syncthreads();
-    if (sb + CM_BK < S) load(sb + CM_BK);
-#pragma unroll
-    for (int k4 = 0; k4 < CM_BK / 4; ++k4) {
-      const int kk = k4 * 4 + (lane >> 4);
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][wm * 64 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][wn * 64 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+    if (kb + XK < Sp) load(kb + XK);
+    mma_stage(Ah, Al, Bh, Bl, lane, wm, wn, acc);
   }
   // epilogue: lane holds rows 4q..4q+3 = fields 2q, 2q+1 (re, im) at one point
 #pragma unroll
@@ -271,6 +392,7 @@ __global__ void __launch_bounds__(256) k_update_mfma(float2* __restrict__ d, int
         const float cr = (float)coef[(size_t)f * (S + 1) + S].x;
         const float2 e = E[(size_t)l * ng + r];
         float2 v = d[(size_t)f * ng + r];
+        if (MID) v = finish_mid(mid, f, r, v);
         v.x -= acc[i][j][2 * h] + cr * e.x;
         v.y -= acc[i][j][2 * h + 1] + cr * e.y;
         d[(size_t)f * ng + r] = v;
@@ -278,36 +400,72 @@ __global__ void __launch_bounds__(256) k_update_mfma(float2* __restrict__ d, int
     }
 }
 
-hipError_t launch_coef_mfma(const float2* d, int F, const float* phi, int S, size_t ng, int chunk,
-                            float* part, double dv, double2* coef, hipStream_t st) {
+static unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
+
+hipError_t launch_phi_split(const float* phi, int S, size_t ng, PhiSplitBufs b, hipStream_t st) {
+  const int Sp = clean_sp(S);
+  const size_t n = ng * (size_t)Sp;
+  hipLaunchKernelGGL(k_phi_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, phi, S, Sp, ng,
+                     b.h, b.l, b.th, b.tl);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_x3(const float2* d, int F, const PhiSplit& ps, size_t ng, int chunk,
+                          float* part, double dv, double2* coef, hipStream_t st, const MidArgs& mid,
+                          const float2* E, int L, double2* gpart) {
+  if (F <= 0 || ps.S <= 0 || ng % XK || chunk % XK || chunk <= 0) return hipErrorInvalidValue;
+  if (mid.on && !gpart) return hipErrorInvalidValue;
+  const int nrt = (2 * F + XT - 1) / XT, nct = (ps.S + XT - 1) / XT;
   const int nchunk = (int)((ng + chunk - 1) / chunk);
-  dim3 g((2 * F + CM_BM - 1) / CM_BM, (S + CM_BN - 1) / CM_BN, nchunk);
-  hipLaunchKernelGGL(k_coef_mfma, g, dim3(256), 0, st, d, F, phi, S, ng, chunk, part);
-  hipLaunchKernelGGL(k_coef_reduce, dim3((F * S + 255) / 256), dim3(256), 0, st, part, nchunk, F, S,
-                     dv, coef);
+  const unsigned ntile = (unsigned)nrt * nct * nchunk;
+  const dim3 g(round8(ntile)), b(256);
+  if (mid.on)
+    hipLaunchKernelGGL((k_coef_x3<true, true>), g, b, 0, st, d, F, ps, ng, chunk, nrt, nct, nchunk,
+                       ntile, mid, E, L, part, gpart);
+  else if (gpart)
+    hipLaunchKernelGGL((k_coef_x3<false, true>), g, b, 0, st, d, F, ps, ng, chunk, nrt, nct, nchunk,
+                       ntile, mid, E, L, part, gpart);
+  else
+    hipLaunchKernelGGL((k_coef_x3<false, false>), g, b, 0, st, d, F, ps, ng, chunk, nrt, nct, nchunk,
+                       ntile, mid, E, L, part, gpart);
+  if (gpart)
+    hipLaunchKernelGGL(k_edot_reduce, dim3((F + 255) / 256), dim3(256), 0, st, gpart, nchunk, F, ps.S,
+                       dv, coef);
+  hipLaunchKernelGGL(k_coef_reduce, dim3((F * ps.S + 255) / 256), dim3(256), 0, st, part, nchunk, F,
+                     ps.S, dv, coef);
   return hipGetLastError();
 }
 
-hipError_t launch_edot(const float2* d, const float2* E, int F, int L, int S, size_t ng,
-                       double2* gpart, double dv, double2* coef, hipStream_t st) {
-  const int nblk = (int)((ng + 1023) / 1024);
-  hipLaunchKernelGGL(k_edot, dim3(nblk, F), dim3(256), 0, st, d, E, L, ng, gpart);
-  hipLaunchKernelGGL(k_edot_reduce, dim3((F + 255) / 256), dim3(256), 0, st, gpart, nblk, F, S, dv,
-                     coef);
+hipError_t launch_update_x3(float2* d, int F, const PhiSplit& ps, const float2* E, int L, size_t ng,
+                            const double2* coef, float* scratch, hipStream_t st, const MidArgs& mid) {
+  if (F <= 0 || ps.S <= 0 || ps.Sp != clean_sp(ps.S)) return hipErrorInvalidValue;
+  const int Sp = ps.Sp;
+  unsigned short* cth = reinterpret_cast<unsigned short*>(scratch);
+  unsigned short* ctl = cth + (size_t)2 * F * Sp;
+  hipLaunchKernelGGL(k_coef_split, dim3((2 * F * Sp + 255) / 256), dim3(256), 0, st, coef, F, ps.S, Sp,
+                     cth, ctl);
+  const int nrt = (2 * F + XT - 1) / XT;
+  const size_t npt = (ng + XT - 1) / XT;
+  const unsigned ntile = (unsigned)(nrt * npt);
+  const dim3 g(round8(ntile)), b(256);
+  if (mid.on)
+    hipLaunchKernelGGL(k_update_x3<true>, g, b, 0, st, d, F, ps, E, L, ng, cth, ctl, coef, nrt, ntile,
+                       mid);
+  else
+    hipLaunchKernelGGL(k_update_x3<false>, g, b, 0, st, d, F, ps, E, L, ng, cth, ctl, coef, nrt, ntile,
+                       mid);
   return hipGetLastError();
 }
 
-hipError_t launch_update_mfma(float2* d, int F, const float* phi, int S, const float2* E, int L,
-                              size_t ng, const double2* coef, float* coefT, hipStream_t st) {
-  hipLaunchKernelGGL(k_coef_transpose, dim3((F * S + 255) / 256), dim3(256), 0, st, coef, F, S, coefT);
-  dim3 g((unsigned)((ng + CM_BN - 1) / CM_BN), (2 * F + CM_BM - 1) / CM_BM);
-  hipLaunchKernelGGL(k_update_mfma, g, dim3(256), 0, st, d, F, phi, S, E, L, ng, coefT, coef);
-  return hipGetLastError();
+size_t clean_scratch_floats(int F, int L, int S, size_t ng) {
+  const size_t a = (ng + CLEAN_CHUNK_D - 1) / CLEAN_CHUNK_D * 2 * (size_t)F * S;
+  const size_t b = (ng + CLEAN_CHUNK_E - 1) / CLEAN_CHUNK_E * 2 * (size_t)L * S;
+  const size_t c = (size_t)2 * F * clean_sp(S);   // two bf16 arrays of 2F x Sp
+  return std::max(a, std::max(b, c));
 }
 
-size_t coef_part_floats(int F, int S, size_t ng, int chunk) {
-  return (size_t)((ng + chunk - 1) / chunk) * 2 * F * S;
+size_t edot_part_entries(int F, size_t ng) {
+  return (size_t)F * ((ng + CLEAN_CHUNK_D - 1) / CLEAN_CHUNK_D);
 }
-size_t edot_part_entries(int F, size_t ng) { return (size_t)F * ((ng + 1023) / 1024); }
 
 }  // namespace bse

@@ -65,8 +65,10 @@ template <typename T> struct CleanArgs {
   double dv;
   T* dens;             // [F/L][ng]
   const double* eta0;  // [L][ng] eta_l(0), used at t = 0
-  float* part32;       // FP32 matrix-core partials (mixed precision)
-  cplx<double>* gpart; // partial <E_l, d_f> per block of points
+  float* part32;       // matrix-core partials and split coefficients (mixed precision)
+  cplx<double>* gpart; // partial <E_l, d_f> per chunk of points
+  // occupied orbitals as bf16 hi/lo pairs, [S][ng] and [ng][Sp] (mixed precision)
+  const unsigned short *phih, *phil, *phith, *phitl;
 };
 
 template <typename T> bool grid_supported(int n);

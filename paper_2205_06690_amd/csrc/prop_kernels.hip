@@ -842,26 +842,53 @@ hipError_t launch_kick(const double* q, const double* eta0, int L, int F, size_t
   hipLaunchKernelGGL((k_kick<T>), pw_grid(ng, F), dim3(256), 0, st, q, eta0, L, ng, d);
   return hipGetLastError();
 }
+// E_l = Ph H_l (or eta_l(0) at t = 0) for the L unperturbed orbitals only
+template <typename T>
+__global__ void k_clean_e(const cplx<T>* __restrict__ H, const cplx<T>* __restrict__ ph,
+                          const double* __restrict__ eta0, cplx<T>* __restrict__ E, size_t ng, int t0) {
+  using C = cplx<T>;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y;
+  if (i >= ng) return;
+  if (t0) E[(size_t)l * ng + i] = cmk<C>((T)eta0[(size_t)l * ng + i], (T)0);
+  else E[(size_t)l * ng + i] = cmul(ph[i], H[(size_t)l * ng + i]);
+}
+
 template <typename T>
 hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
-  // 1. end-of-step state and E = Ph H
-  hipLaunchKernelGGL((k_clean_finish<T>), pw_grid(a.ng, a.F), dim3(256), 0, st, a.d, a.u, a.H,
-                     a.ph, a.eta0, a.E, a.L, a.ng, a.dt, a.from_mid);
   const int S = a.S;
   if constexpr (std::is_same<T, float>::value) {
-    // 2. coefficients on the matrix cores, <E_l, d_f> by a reduction
-    hipError_t e = launch_coef_mfma(a.d, a.F, a.phi, S, a.ng, a.chunk, a.part32, a.dv, a.coef, st);
+    // 1. E; the mid-step to end-of-step conversion of d is fused into the
+    //    matrix-core kernels (loader of the coefficient GEMM, epilogue of
+    //    the update) instead of a pass of its own
+    hipLaunchKernelGGL((k_clean_e<T>), pw_grid(a.ng, a.L), dim3(256), 0, st, a.H, a.ph, a.eta0, a.E,
+                       a.ng, a.from_mid == 2 ? 1 : 0);
+    MidArgs mid{};
+    mid.on = a.from_mid == 1 ? 1 : 0;
+    mid.u = a.u;
+    mid.H = a.H;
+    mid.ph = a.ph;
+    mid.L = a.L;
+    mid.half_dt = 0.5f * a.dt;
+    mid.ng = a.ng;
+    const MidArgs off{};
+    const PhiSplit ps{a.phih, a.phil, a.phith, a.phitl, S, clean_sp(S)};
+    // 2. coefficients and <E_l, d_f> on the matrix cores
+    hipError_t e = launch_coef_x3(a.d, a.F, ps, a.ng, CLEAN_CHUNK_D, a.part32, a.dv, a.coef, st, mid,
+                                  a.E, a.L, a.gpart);
     if (e != hipSuccess) return e;
-    e = launch_edot(a.d, a.E, a.F, a.L, S, a.ng, a.gpart, a.dv, a.coef, st);
-    if (e != hipSuccess) return e;
-    e = launch_coef_mfma(a.E, a.L, a.phi, S, a.ng, a.chunk, a.part32, a.dv, a.coefE, st);
+    e = launch_coef_x3(a.E, a.L, ps, a.ng, CLEAN_CHUNK_E, a.part32, a.dv, a.coefE, st, off, a.E, a.L,
+                       nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
                        a.coefE, a.n0, a.L, a.renorm);
     // 3. update on the matrix cores
-    e = launch_update_mfma(a.d, a.F, a.phi, S, a.E, a.L, a.ng, a.coef, a.part32, st);
+    e = launch_update_x3(a.d, a.F, ps, a.E, a.L, a.ng, a.coef, a.part32, st, mid);
     if (e != hipSuccess) return e;
   } else {
+    // 1. end-of-step state and E = Ph H
+    hipLaunchKernelGGL((k_clean_finish<T>), pw_grid(a.ng, a.F), dim3(256), 0, st, a.d, a.u, a.H,
+                       a.ph, a.eta0, a.E, a.L, a.ng, a.dt, a.from_mid);
     // 2. coefficients of d against phi_s and E_l, and of E_l against phi_s
     const int nchunk = (int)((a.ng + a.chunk - 1) / a.chunk);
     dim3 g1((a.F + CT_F - 1) / CT_F, (S + CT_S - 1) / CT_S, nchunk);
