@@ -17,6 +17,19 @@
 
 namespace bse {
 
+// The twiddle and kinetic-phase tables are staged in LDS behind the data
+// region: the transforms then read them through the LDS counter instead of
+// the in-order vector-memory counter, which would otherwise make the first
+// table read wait for the whole in-flight prefetch of the next plane.
+template <int N, typename C>
+__device__ __forceinline__ void stage_tables(C* t, const C* __restrict__ tw, const C* __restrict__ kp,
+                                             int tid, int nthr) {
+  for (int i = tid; i < N; i += nthr) {
+    t[i] = tw[i];
+    if (kp) t[N + i] = kp[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // prop_x: pre-kinetic pointwise step fused with the x factor of exp(-iT dt)
 // ---------------------------------------------------------------------------
@@ -57,8 +70,11 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   const size_t ng = (size_t)N * N * N;
   const int c0 = blockIdx.x * TC;
   const int tid = threadIdx.x;
-  const C* __restrict__ tw = a.tw;
-  const C* __restrict__ kp = a.kph;
+  C* tws = s + N * TC;
+  stage_tables<N>(tws, a.tw, a.kph, tid, NTH);
+  __syncthreads();
+  const C* tw = tws;
+  const C* kp = tws + N;
   // global offset of element j1 of item it
   auto gidx = [&](int it, int j1) -> size_t {
     const int w = tid + it * NTH;
@@ -210,11 +226,13 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
   const int x = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t poff = (size_t)x * P;
+  C* tws = s + N * plane_stride<N>();
+  stage_tables<N>(tws, a.tw, a.kph, tid, NT);
   if (!DENS) {
     C* d = a.d + (size_t)blockIdx.y * ng + poff;
     for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = d[e];
     __syncthreads();
-    kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
+    kinetic_yz_plane<N, T, NT>(s, tws, tws + N, tid);
     for (int e = tid; e < P; e += NT) d[e] = s[plane_idx<N>(e)];
     return;
   }
@@ -254,7 +272,7 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
         if (e < P) hc[PREF_H ? i : 0] = h[e];
       }
     }
-    kinetic_yz_plane<N, T, NT>(s, a.tw, a.kph, tid);
+    kinetic_yz_plane<N, T, NT>(s, tws, tws + N, tid);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + i * NT;
@@ -290,16 +308,18 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
   const int b0 = 2 * m, b1 = 2 * m + 1;
   const T* r0 = a.rho + (size_t)b0 * ng + (size_t)x * P;
   const T* r1 = (b1 < a.B) ? a.rho + (size_t)b1 * ng + (size_t)x * P : nullptr;
+  C* tw = s + N * S;
+  stage_tables<N, C>(tw, a.tw, nullptr, tid, NT);
   for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
   __syncthreads();
   NoMul nm;
-  stageA_fwd<N>(s, N, S, 1, a.tw, tid, NT, true);
+  stageA_fwd<N>(s, N, S, 1, tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, S, 1, a.tw, tid, NT, true, nm);
+  stageB<N, 0>(s, N, S, 1, tw, tid, NT, true, nm);
   __syncthreads();
-  stageA_fwd<N>(s, N, 1, S, a.tw, tid, NT, true);
+  stageA_fwd<N>(s, N, 1, S, tw, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, 1, S, a.tw, tid, NT, true, nm);
+  stageB<N, 0>(s, N, 1, S, tw, tid, NT, true, nm);
   __syncthreads();
   C* w = a.work + (size_t)m * ng + (size_t)x * P;
   for (int e = tid; e < P; e += NT) w[e] = s[plane_idx<N>(e)];
@@ -313,14 +333,19 @@ __global__ void __launch_bounds__(256) k_poisson_x(PoisArgs<T> a) {
   const int ng = N * N * N;
   const int c0 = blockIdx.x * TC, m = blockIdx.y, tid = threadIdx.x, nthr = blockDim.x;
   C* w = a.work + (size_t)m * ng;
+  C* tw = s + N * TC;
+  T* k2 = reinterpret_cast<T*>(tw + N);
+  for (int i = tid; i < N; i += nthr) {
+    tw[i] = a.tw[i];
+    k2[i] = a.k2[i];
+  }
   for (int e = tid; e < N * TC; e += nthr) {
     const int x = e / TC, c = e % TC;
     s[x * TC + c] = w[(size_t)x * N * N + c0 + c];
   }
   __syncthreads();
-  stageA_fwd<N>(s, TC, 1, TC, a.tw, tid, nthr, true);
+  stageA_fwd<N>(s, TC, 1, TC, tw, tid, nthr, true);
   __syncthreads();
-  const T* __restrict__ k2 = a.k2;
   const T scale = a.vscale;
   auto mul = [k2, c0, scale](int line, C v, int kx) {
     const int c = c0 + line;
@@ -329,7 +354,7 @@ __global__ void __launch_bounds__(256) k_poisson_x(PoisArgs<T> a) {
     const T f = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / kk;
     return cscale(v, f);
   };
-  stageB<N, 2>(s, TC, 1, TC, a.tw, tid, nthr, true, mul);
+  stageB<N, 2>(s, TC, 1, TC, tw, tid, nthr, true, mul);
   __syncthreads();
   stageC_inv<N>(s, TC, 1, TC, tid, nthr, true);
   __syncthreads();
@@ -349,14 +374,16 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_inv(PoisArgs<T> a) {
   const int ng = N * N * N;
   const int x = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
   const C* w = a.work + (size_t)m * ng + (size_t)x * P;
+  C* tw = s + N * S;
+  stage_tables<N, C>(tw, a.tw, nullptr, tid, NT);
   for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = w[e];
   __syncthreads();
   NoMul nm;
-  stageB<N, 1>(s, N, S, 1, a.tw, tid, NT, true, nm);
+  stageB<N, 1>(s, N, S, 1, tw, tid, NT, true, nm);
   __syncthreads();
   stageC_inv<N>(s, N, S, 1, tid, NT, true);
   __syncthreads();
-  stageB<N, 1>(s, N, 1, S, a.tw, tid, NT, true, nm);
+  stageB<N, 1>(s, N, 1, S, tw, tid, NT, true, nm);
   __syncthreads();
   stageC_inv<N>(s, N, 1, S, tid, NT, true);
   __syncthreads();
@@ -694,6 +721,14 @@ template <int N, int TC> constexpr bool x_valid() {
   return (N * N) % TC == 0 && (TC * Fac<N>::N2) % 256 == 0;
 }
 
+// dynamic LDS of the propagation passes: data region + twiddle and phase tables
+template <int N, int TC, typename T> constexpr size_t x_lds() {
+  return sizeof(cplx<T>) * ((size_t)N * TC + 2 * N);
+}
+template <int N, typename T> constexpr size_t yz_lds() {
+  return sizeof(cplx<T>) * ((size_t)N * plane_stride<N>() + 2 * N);
+}
+
 template <int N, typename T>
 struct Launch {
   template <int TC>
@@ -702,7 +737,7 @@ struct Launch {
       return hipErrorInvalidValue;
     } else {
       dim3 grid(N * N / TC, F);
-      size_t sm = sizeof(cplx<T>) * N * TC;
+      size_t sm = x_lds<N, TC, T>();
       if (a.mode == PX_ETA0)
         hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
       else
@@ -722,7 +757,7 @@ struct Launch {
   }
   template <int NT>
   static hipError_t prop_yz_nt(const PropYZArgs<T>& a, int nb, hipStream_t st) {
-    size_t sm = sizeof(cplx<T>) * N * plane_stride<N>();
+    size_t sm = yz_lds<N, T>();
     if (a.density)
       hipLaunchKernelGGL((k_prop_yz<N, T, NT, true>), dim3(N, nb), dim3(NT), sm, st, a);
     else
@@ -741,30 +776,30 @@ struct Launch {
     constexpr int NT = yz_threads<N>();
     constexpr int TC = x_tc<N>();
     const int M = (a.B + 1) / 2;
-    size_t smp = sizeof(cplx<T>) * N * plane_stride<N>();
+    const size_t smp = yz_lds<N, T>();
+    const size_t smx = x_lds<N, TC, T>();
     hipLaunchKernelGGL((k_poisson_yz_fwd<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
-    hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256),
-                       sizeof(cplx<T>) * N * TC, st, a);
+    hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256), smx, st, a);
     hipLaunchKernelGGL((k_poisson_yz_inv<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
     return hipGetLastError();
   }
   template <int TC> static void conf_x() {
     if constexpr (x_valid<N, TC>()) {
-      const int smx = (int)(sizeof(cplx<T>) * N * TC);
+      const int smx = (int)x_lds<N, TC, T>();
       (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
       (void)hipFuncSetAttribute((const void*)k_prop_x<N, TC, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
     }
   }
   template <int NT> static void conf_yz() {
-    const int smp = (int)(sizeof(cplx<T>) * N * plane_stride<N>());
+    const int smp = (int)yz_lds<N, T>();
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
   }
   static void configure() {
     constexpr int NT = yz_threads<N>();
     constexpr int TC = x_tc<N>();
-    const int smp = (int)(sizeof(cplx<T>) * N * plane_stride<N>());
-    const int smx = (int)(sizeof(cplx<T>) * N * TC);
+    const int smp = (int)yz_lds<N, T>();
+    const int smx = (int)x_lds<N, TC, T>();
     conf_x<16>();
     conf_x<32>();
     conf_x<64>();
@@ -778,7 +813,7 @@ struct Launch {
 
 template <typename T>
 bool grid_supported(int n) {
-  if (sizeof(cplx<T>) * (size_t)n * (n + 1) > 160 * 1024) return false;
+  if (sizeof(cplx<T>) * ((size_t)n * (n + 1) + 2 * (size_t)n) > 160 * 1024) return false;
   switch (n) {
     case 16: case 24: case 32: case 48: case 64: case 112: return true;
     default: return false;
