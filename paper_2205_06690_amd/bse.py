@@ -159,7 +159,8 @@ class System:
         self._h = h_
 
     def close(self):
-        if getattr(self, "_h", None):
+        # LIB is None once the interpreter is tearing the module down
+        if getattr(self, "_h", None) and LIB is not None:
             LIB.bse_destroy_system(self._h)
             self._h = None
 
@@ -255,7 +256,7 @@ class Fno:
         self.n_params = int(LIB.bse_fno_num_params(h))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and LIB is not None:
             LIB.bse_fno_destroy(self._h)
             self._h = None
 

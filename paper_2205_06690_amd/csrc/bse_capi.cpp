@@ -660,7 +660,11 @@ void tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, 
   }
 }
 
-// Lanczos with full re-orthogonalisation on the device copy of A
+// Lanczos with full re-orthogonalisation on the device copy of A.  The
+// iterations run on the device without host round trips: the diagonal
+// elements and squared residual norms stay in device arrays, and the host
+// reads them only at the convergence checks (first at m = n_exc, then every
+// 10 steps), where it also finds the first breakdown, if any.
 void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, const double* w_grid,
               double sig, double* sigma) {
   if (!s) fail(BSE_ERR_ARG, "null system");
@@ -670,12 +674,14 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
     fail(BSE_ERR_ARG, "bse_spectrum: bad arguments");
   hipStream_t st = s->stream;
   s->lz_V.alloc(sizeof(double) * (size_t)(n + 1) * n);
-  s->lz_w.alloc(sizeof(double) * n);
+  s->lz_w.alloc(sizeof(double) * (size_t)n * std::max(1, n_exc));
   s->lz_c.alloc(sizeof(double) * (n + 1));
-  s->lz_s.alloc(sizeof(double) * (n + 1));
+  s->lz_s.alloc(sizeof(double) * ((size_t)n * n_exc + 2 * (size_t)n));
   double* V = s->lz_V.as<double>();
   double* w = s->lz_w.as<double>();
   double* c = s->lz_c.as<double>();
+  double* al_d = s->lz_s.as<double>() + (size_t)n * n_exc;   // alpha_k
+  double* bq_d = al_d + n;                                     // |w_k|^2
   // deterministic start vector (SplitMix64 draws in [-1, 1))
   std::vector<double> v0(n);
   double nr = 0;
@@ -685,52 +691,65 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
   }
   for (int i = 0; i < n; ++i) v0[i] /= std::sqrt(nr);
   HIPC(hipMemcpyAsync(V, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-  std::vector<double> alpha, beta;
+  std::vector<double> al(n), bq(n), alpha, beta;
   std::vector<double> theta;
   std::vector<std::vector<double>> svec;
-  double anorm = 0;
-  int m = 0;
-  for (int k = 0; k < n; ++k) {
+  int m = 0, done = 0;
+  for (int k = 0; k < n && !m; ++k) {
     HIPC(launch_gemv(s->A_d.as<double>(), n, V + (size_t)k * n, w, st));
     // two passes of classical Gram-Schmidt against the whole basis
+    HIPC(launch_reorth(V, n, k + 1, c, w, st, al_d + k));
     HIPC(launch_reorth(V, n, k + 1, c, w, st));
-    double a_k = 0;
-    HIPC(hipMemcpyAsync(&a_k, c + k, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPC(launch_reorth(V, n, k + 1, c, w, st));
-    double bb = 0;
-    HIPC(launch_dot(w, w, n, c, st));
-    HIPC(hipMemcpyAsync(&bb, c, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(launch_dot(w, w, n, bq_d + k, st));
+    if (k + 1 < n) HIPC(launch_scale_norm(w, n, bq_d + k, V + (size_t)(k + 1) * n, st));
+    const int mk = k + 1;
+    if (!(mk >= n_exc && ((mk - n_exc) % 10 == 0 || mk == n))) continue;
+    HIPC(hipMemcpyAsync(al.data() + done, al_d + done, sizeof(double) * (mk - done),
+                        hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(bq.data() + done, bq_d + done, sizeof(double) * (mk - done),
+                        hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
-    alpha.push_back(a_k);
-    const double b_k = std::sqrt(std::max(bb, 0.0));
-    anorm = std::max(anorm, std::fabs(a_k) + b_k);
-    m = k + 1;
-    const bool breakdown = b_k < 1e-13 * std::max(anorm, 1e-300);
-    const bool check = m >= n_exc && ((m - n_exc) % 10 == 0 || m == n || breakdown);
-    if (check) {
-      tridiag_lowest(alpha, beta, m, std::min(n_exc, m), theta, svec);
-      bool conv = m >= n_exc;
-      for (int j = 0; j < (int)theta.size() && conv; ++j)
-        if (b_k * std::fabs(svec[j][m - 1]) > 1e-10 * std::max(anorm, 1.0)) conv = false;
-      if (conv || m == n || breakdown) break;
+    done = mk;
+    // the recurrence in order: running norm estimate and first breakdown
+    alpha.clear();
+    beta.clear();
+    double anorm = 0;
+    int mm = mk;
+    bool breakdown = false;
+    for (int q = 0; q < mk; ++q) {
+      const double b_q = std::sqrt(std::max(bq[q], 0.0));
+      alpha.push_back(al[q]);
+      anorm = std::max(anorm, std::fabs(al[q]) + b_q);
+      if (b_q < 1e-13 * std::max(anorm, 1e-300)) {
+        breakdown = true;
+        mm = q + 1;
+        break;
+      }
+      if (q + 1 < mk) beta.push_back(b_q);
     }
-    if (breakdown || m == n) break;
-    beta.push_back(b_k);
-    HIPC(launch_scale_copy(w, n, 1.0 / b_k, V + (size_t)(k + 1) * n, st));
+    if (mm < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
+    tridiag_lowest(alpha, beta, mm, std::min(n_exc, mm), theta, svec);
+    const double b_last = std::sqrt(std::max(bq[mm - 1], 0.0));
+    bool conv = true;
+    for (int j = 0; j < (int)theta.size() && conv; ++j)
+      if (b_last * std::fabs(svec[j][mm - 1]) > 1e-10 * std::max(anorm, 1.0)) conv = false;
+    if (conv || breakdown || mk == n) m = mm;
   }
-  if ((int)theta.size() < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
-  // Ritz vectors and dipole strengths
-  std::vector<double> f0(3 * (size_t)n), x(n);
+  if (m == 0 || (int)theta.size() < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
+  // Ritz vectors (all at once) and dipole strengths
+  std::vector<double> f0(3 * (size_t)n), x((size_t)n * n_exc), sv((size_t)m * n_exc);
+  for (int j = 0; j < n_exc; ++j)
+    for (int q = 0; q < m; ++q) sv[(size_t)j * m + q] = svec[j][q];
+  HIPC(hipMemcpyAsync(s->lz_s.p, sv.data(), sizeof(double) * sv.size(), hipMemcpyHostToDevice, st));
+  HIPC(launch_ritz(V, n, m, s->lz_s.as<double>(), n_exc, w, st));
+  HIPC(hipMemcpyAsync(x.data(), w, sizeof(double) * x.size(), hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(f0.data(), s->f0_d.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
   for (int j = 0; j < n_exc; ++j) {
-    HIPC(hipMemcpyAsync(s->lz_s.p, svec[j].data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-    HIPC(launch_ritz(V, n, m, s->lz_s.as<double>(), w, st));
-    HIPC(hipMemcpyAsync(x.data(), w, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
     omega[j] = theta[j];
     for (int ax = 0; ax < 3; ++ax) {
       double d = 0;
-      for (int i = 0; i < n; ++i) d += x[i] * f0[(size_t)i * 3 + ax];
+      for (int i = 0; i < n; ++i) d += x[(size_t)j * n + i] * f0[(size_t)i * 3 + ax];
       dip2[(size_t)j * 3 + ax] = d * d;
     }
   }

@@ -22,10 +22,15 @@ hipError_t launch_assemble_a(const double* X, const double* D, int no, int nc, i
 hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double h, double* f0,
                           hipStream_t st);
 hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st);
-hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st);
+// w -= V^T-projection onto the first m basis vectors (c = V w); c[m-1] also to *last
+hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,
+                         double* last = nullptr);
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);
-hipError_t launch_ritz(const double* V, int n, int m, const double* s, double* out, hipStream_t st);
-hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipStream_t st);
+// out[q] = sum_k S[q][k] V[k], q < nq, k < m
+hipError_t launch_ritz(const double* V, int n, int m, const double* S, int nq, double* out,
+                       hipStream_t st);
+// out = w / sqrt(*bsq), bsq on the device
+hipError_t launch_scale_norm(const double* w, int n, const double* bsq, double* out, hipStream_t st);
 }  // namespace bse
 
 namespace bse {

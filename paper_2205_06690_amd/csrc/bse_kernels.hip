@@ -271,9 +271,10 @@ __global__ void __launch_bounds__(256) k_gemv(const double* __restrict__ A, int 
   if (threadIdx.x == 0) y[row] = red[0];
 }
 
-// c[k] = sum_i V[k][i] w[i], k < m
+// c[k] = sum_i V[k][i] w[i], k < m; c[m-1] also goes to *last when given
 __global__ void __launch_bounds__(256) k_vt_w(const double* __restrict__ V, int n, int m,
-                                              const double* __restrict__ w, double* __restrict__ c) {
+                                              const double* __restrict__ w, double* __restrict__ c,
+                                              double* __restrict__ last) {
   const int k = blockIdx.x;
   if (k >= m) return;
   double s = 0;
@@ -285,7 +286,10 @@ __global__ void __launch_bounds__(256) k_vt_w(const double* __restrict__ V, int 
     if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
     __syncthreads();
   }
-  if (threadIdx.x == 0) c[k] = red[0];
+  if (threadIdx.x == 0) {
+    c[k] = red[0];
+    if (last && k == m - 1) *last = red[0];
+  }
 }
 
 // w[i] -= sum_k c[k] V[k][i]
@@ -298,18 +302,23 @@ __global__ void k_w_minus_vc(const double* __restrict__ V, int n, int m,
   w[i] -= s;
 }
 
-// out[j] = sum_k V[k][j] s[k]  (Ritz vector), k < m
-__global__ void k_vt_s(const double* __restrict__ V, int n, int m, const double* __restrict__ s,
+// out[q][j] = sum_k V[k][j] S[q][k]  (Ritz vectors q < nq), k < m
+__global__ void k_vt_s(const double* __restrict__ V, int n, int m, const double* __restrict__ S,
                        double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
   if (j >= n) return;
   double acc = 0;
-  for (int k = 0; k < m; ++k) acc += V[(size_t)k * n + j] * s[k];
-  out[j] = acc;
+  for (int k = 0; k < m; ++k) acc += V[(size_t)k * n + j] * S[(size_t)q * m + k];
+  out[(size_t)q * n + j] = acc;
 }
 
-__global__ void k_scale_copy(const double* __restrict__ w, int n, double s, double* __restrict__ out) {
+// out = w / sqrt(*bsq) (zero after a breakdown, which the host truncates)
+__global__ void k_scale_norm(const double* __restrict__ w, int n, const double* __restrict__ bsq,
+                             double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double b = *bsq;
+  const double s = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
   if (i < n) out[i] = w[i] * s;
 }
 
@@ -404,21 +413,23 @@ hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipSt
   hipLaunchKernelGGL(k_gemv, dim3(n), dim3(256), 0, st, A, n, v, y);
   return hipGetLastError();
 }
-hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st) {
-  hipLaunchKernelGGL(k_vt_w, dim3(m), dim3(256), 0, st, V, n, m, w, c);
+hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,
+                         double* last) {
+  hipLaunchKernelGGL(k_vt_w, dim3(m), dim3(256), 0, st, V, n, m, w, c, last);
   hipLaunchKernelGGL(k_w_minus_vc, dim3((n + 255) / 256), dim3(256), 0, st, V, n, m, c, w);
   return hipGetLastError();
 }
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_vt_w, dim3(1), dim3(256), 0, st, a, n, 1, b, out);
+  hipLaunchKernelGGL(k_vt_w, dim3(1), dim3(256), 0, st, a, n, 1, b, out, (double*)nullptr);
   return hipGetLastError();
 }
-hipError_t launch_ritz(const double* V, int n, int m, const double* s, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_vt_s, dim3((n + 255) / 256), dim3(256), 0, st, V, n, m, s, out);
+hipError_t launch_ritz(const double* V, int n, int m, const double* S, int nq, double* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_vt_s, dim3((n + 255) / 256, nq), dim3(256), 0, st, V, n, m, S, out);
   return hipGetLastError();
 }
-hipError_t launch_scale_copy(const double* w, int n, double s, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, st, w, n, s, out);
+hipError_t launch_scale_norm(const double* w, int n, const double* bsq, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_norm, dim3((n + 255) / 256), dim3(256), 0, st, w, n, bsq, out);
   return hipGetLastError();
 }
 
