@@ -11,6 +11,11 @@ import os
 from typing import Optional
 
 import numpy as np
+# torch is loaded before libbse so that the HIP runtime torch brings is the
+# process's only one: libbse then binds to it by soname.  Loading libbse
+# first pulls in a second runtime, and whichever of the two initialises the
+# device second finds none.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbse.so")
 

@@ -408,6 +408,97 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_inv(PoisArgs<T> a) {
   }
 }
 
+// Poisson for grids whose y-z plane does not fit in LDS (FP64 at 112^3): the
+// plane passes are split into a z-line pass over tiles of PL_TL contiguous
+// lines and a y-line pass over tiles of PL_TL z columns of one x plane.  The
+// transforms, the scrambled spectrum order and the epilogue are those of the
+// plane passes.
+constexpr int PL_TL = 16;
+
+// dir 0: pair of real densities -> work, forward z half; dir 1: work ->
+// inverse z half -> outputs
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_poisson_z(PoisArgs<T> a, int dir) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int TL = PL_TL, S = N + 1, E = TL * N;
+  const int ng = N * N * N;
+  const int m = blockIdx.y, tid = threadIdx.x;
+  const size_t base = (size_t)blockIdx.x * TL * N;   // lines (x, y) = blockIdx.x * TL ...
+  C* tw = s + TL * S;
+  stage_tables<N, C>(tw, a.tw, nullptr, tid, 256);
+  const int b0 = 2 * m, b1 = 2 * m + 1;
+  const bool has1 = b1 < a.B;
+  NoMul nm;
+  if (dir == 0) {
+    const T* r0 = a.rho + (size_t)b0 * ng + base;
+    const T* r1 = has1 ? a.rho + (size_t)b1 * ng + base : nullptr;
+    for (int e = tid; e < E; e += 256) s[(e / N) * S + e % N] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
+    __syncthreads();
+    stageA_fwd<N>(s, TL, S, 1, tw, tid, 256, true);
+    __syncthreads();
+    stageB<N, 0>(s, TL, S, 1, tw, tid, 256, true, nm);
+    __syncthreads();
+    C* w = a.work + (size_t)m * ng + base;
+    for (int e = tid; e < E; e += 256) w[e] = s[(e / N) * S + e % N];
+    return;
+  }
+  const C* w = a.work + (size_t)m * ng + base;
+  for (int e = tid; e < E; e += 256) s[(e / N) * S + e % N] = w[e];
+  __syncthreads();
+  stageB<N, 1>(s, TL, S, 1, tw, tid, 256, true, nm);
+  __syncthreads();
+  stageC_inv<N>(s, TL, S, 1, tid, 256, true);
+  __syncthreads();
+  const size_t o0 = (size_t)b0 * ng + base, o1 = (size_t)b1 * ng + base;
+  for (int e = tid; e < E; e += 256) {
+    const C v = s[(e / N) * S + e % N];
+    if (a.out) {
+      a.out[o0 + e] = v.x;
+      if (has1) a.out[o1 + e] = v.y;
+    }
+    if (a.out64) {
+      a.out64[o0 + e] = (double)v.x;
+      if (has1) a.out64[o1 + e] = (double)v.y;
+    }
+    if (a.acc) {
+      a.acc[o0 + e] += a.wn * (double)v.x;
+      if (has1) a.acc[o1 + e] += a.wn * (double)v.y;
+    }
+  }
+}
+
+// y lines of PL_TL consecutive z columns of one x plane, work in place;
+// dir 0: forward half, dir 1: inverse half
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_poisson_y(PoisArgs<T> a, int dir) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int TL = PL_TL, E = TL * N;
+  const int ng = N * N * N;
+  const int x = blockIdx.x / (N / TL), z0 = (blockIdx.x % (N / TL)) * TL;
+  const int m = blockIdx.y, tid = threadIdx.x;
+  C* w = a.work + (size_t)m * ng + (size_t)x * N * N + z0;
+  C* tw = s + E;
+  stage_tables<N, C>(tw, a.tw, nullptr, tid, 256);
+  for (int e = tid; e < E; e += 256) s[e] = w[(size_t)(e / TL) * N + e % TL];
+  __syncthreads();
+  NoMul nm;
+  if (dir == 0) {
+    stageA_fwd<N>(s, TL, 1, TL, tw, tid, 256, true);
+    __syncthreads();
+    stageB<N, 0>(s, TL, 1, TL, tw, tid, 256, true, nm);
+  } else {
+    stageB<N, 1>(s, TL, 1, TL, tw, tid, 256, true, nm);
+    __syncthreads();
+    stageC_inv<N>(s, TL, 1, TL, tid, 256, true);
+  }
+  __syncthreads();
+  for (int e = tid; e < E; e += 256) w[(size_t)(e / TL) * N + e % TL] = s[e];
+}
+
 // ---------------------------------------------------------------------------
 // pointwise helpers
 // ---------------------------------------------------------------------------
@@ -778,9 +869,22 @@ struct Launch {
     const int M = (a.B + 1) / 2;
     const size_t smp = yz_lds<N, T>();
     const size_t smx = x_lds<N, TC, T>();
-    hipLaunchKernelGGL((k_poisson_yz_fwd<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
-    hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256), smx, st, a);
-    hipLaunchKernelGGL((k_poisson_yz_inv<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
+    if constexpr (yz_lds<N, T>() > 160 * 1024) {
+      // the plane does not fit: separate z-line and y-line passes
+      static_assert(N % PL_TL == 0, "line tiles must divide the grid");
+      const size_t smz = sizeof(cplx<T>) * ((size_t)PL_TL * (N + 1) + N);
+      const size_t smy = sizeof(cplx<T>) * ((size_t)PL_TL * N + N);
+      const dim3 gz(N * N / PL_TL, M), gy(N * (N / PL_TL), M);
+      hipLaunchKernelGGL((k_poisson_z<N, T>), gz, dim3(256), smz, st, a, 0);
+      hipLaunchKernelGGL((k_poisson_y<N, T>), gy, dim3(256), smy, st, a, 0);
+      hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256), smx, st, a);
+      hipLaunchKernelGGL((k_poisson_y<N, T>), gy, dim3(256), smy, st, a, 1);
+      hipLaunchKernelGGL((k_poisson_z<N, T>), gz, dim3(256), smz, st, a, 1);
+    } else {
+      hipLaunchKernelGGL((k_poisson_yz_fwd<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
+      hipLaunchKernelGGL((k_poisson_x<N, TC, T>), dim3(N * N / TC, M), dim3(256), smx, st, a);
+      hipLaunchKernelGGL((k_poisson_yz_inv<N, T, NT>), dim3(N, M), dim3(NT), smp, st, a);
+    }
     return hipGetLastError();
   }
   template <int TC> static void conf_x() {

@@ -108,6 +108,11 @@ class SystemSpec:
         d = dataclasses.asdict(self)
         return hashlib.sha1(json.dumps(d, sort_keys=True).encode()).hexdigest()[:16]
 
+    def potential_key(self) -> str:
+        """Hash of the fields that fix V_ext (and so the orbitals)."""
+        d = {k: getattr(self, k) for k in ("n", "h", "n_wells", "seed", "layout", "depth", "width")}
+        return hashlib.sha1(json.dumps(d, sort_keys=True).encode()).hexdigest()[:16]
+
 
 # The five workloads: a tiny plain-method case, a mid-size molecule, a
 # paper-scale molecule (electron count of the paper's 520-electron system),
@@ -445,7 +450,7 @@ def make_system(spec: SystemSpec, *, n_states: Optional[int] = None, tol: float 
     only), else on the CPU."""
     n_states = spec.n_orb if n_states is None else n_states
     v = make_vext(spec)
-    key = f"{spec.key()}_{n_states}_{tol:g}"
+    key = f"{spec.potential_key()}_{n_states}_{tol:g}"
     path = os.path.join(cache_dir(), f"sys_{key}.npz")
     phi = eps = None
     if use_cache and os.path.exists(path):
