@@ -43,6 +43,46 @@ def _alg_bytes(kernel: str, B: int, L: int, ng: int, cbytes: int) -> float:
     return float("nan")
 
 
+# kernel sources whose code the counter-measured traffic of the propagation
+# passes belongs to
+_PROP_SOURCES = ("paper_2205_06690_amd/csrc/prop_kernels.hip",
+                 "paper_2205_06690_amd/csrc/prop_kernels.h",
+                 "paper_2205_06690_amd/csrc/fft_lines.h")
+
+
+def _sources_sha256() -> str:
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in _PROP_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic_bytes(kernel: str, workload: str):
+    """HBM bytes per launch of ``kernel`` from the calibrated FETCH_SIZE /
+    WRITE_SIZE record in profiles/, or None when there is none for this
+    workload or the kernel sources changed since the counters were taken."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    d = os.path.join(here, "profiles")
+    if not os.path.isdir(d):
+        return None
+    sha = _sources_sha256()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(d, name)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record: "):
+                    continue
+                rec = json.loads(line[len("traffic-record: "):])
+                if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                        and rec.get("sources_sha256") == sha):
+                    return float(rec["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(spec, sysd, pair, steps_sample: int):
     """The FP64 oracle on one pair for ``steps_sample`` time steps, scaled to
     pair solves per second of the full ``spec.n_steps`` propagation."""
@@ -290,10 +330,15 @@ def main():
     avg_ms = kt[dom][0]
     alg = _alg_bytes(dom, B, spec.n_stoch, spec.ng, cbytes)
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic_bytes(dom, args.config)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 4),
+                "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
                 "alg_bytes_per_launch": alg}
+    if traffic is not None:
+        # counter-measured HBM bytes over the same measured launch time
+        roofline["traffic_GBs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
 
     out = {
         "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",

@@ -68,7 +68,9 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   constexpr int IT = TC * N2 / NTH;
   static_assert(TC * N2 % NTH == 0, "work items must fill the block");
   const size_t ng = (size_t)N * N * N;
-  const int c0 = blockIdx.x * TC;
+  // grid: (fields or pairs, tiles) with the field fastest, so that the blocks
+  // of one tile run close together and share its H and phase tiles in L2
+  const int c0 = blockIdx.y * TC;
   const int tid = threadIdx.x;
   C* tws = s + N * TC;
   stage_tables<N>(tws, a.tw, a.kph, tid, NTH);
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   };
   auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
   if (ETA) {
-    const size_t fo = (size_t)blockIdx.y * ng;
+    const size_t fo = (size_t)blockIdx.x * ng;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       C v[N1];
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
     }
     return;
   }
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;
   const bool half = a.mode == PX_HALF;
   const T cu = half ? (T)0.5 * a.dt : a.dt;
   const C* __restrict__ ptab = half ? a.ph : a.pf;
@@ -223,6 +225,9 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
   constexpr int PER = (P + NT - 1) / NT;
   constexpr bool PREF_H = PER <= 8;
   const int ng = N * N * N;
+  // grid: (x planes, fields or pairs) with the plane fastest: blocks running
+  // together stream consecutive planes of one field (measured faster than
+  // sharing the H planes across pairs, which the x pass gains from)
   const int x = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t poff = (size_t)x * P;
@@ -827,7 +832,7 @@ struct Launch {
     if constexpr (!x_valid<N, TC>()) {
       return hipErrorInvalidValue;
     } else {
-      dim3 grid(N * N / TC, F);
+      dim3 grid(F, N * N / TC);
       size_t sm = x_lds<N, TC, T>();
       if (a.mode == PX_ETA0)
         hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
