@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+PEAK_BF16_TFS = 2500.0     # MI355X dense BF16 matrix cores
 
 
 def _alg_bytes(kernel: str, B: int, L: int, ng: int, cbytes: int) -> float:
@@ -246,7 +247,8 @@ def main():
     ap.add_argument("--config", default="mid64")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the CPU sample (0: 200 at 64^3, 40 at 112^3)")
     ap.add_argument("--n-systems", type=int, default=32)
     ap.add_argument("--n-train", type=int, default=4096)
     ap.add_argument("--n-test", type=int, default=512)
@@ -287,7 +289,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.config not in ("mid64", "paper112", "tiny24"):
+        print(f"unknown --config {args.config}", file=sys.stderr)
+        sys.exit(2)
     spec = inputs.CONFIGS[args.config]
+    if args.cpu_steps <= 0:
+        args.cpu_steps = 40 if spec.n >= 112 else min(200, spec.n_steps)
     t_in = time.perf_counter()
     sysd = inputs.make_system(spec)
     print(f"[bench] inputs {args.config} ready in {time.perf_counter() - t_in:.1f}s",
@@ -340,6 +347,25 @@ def main():
         roofline["traffic_GBs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
 
+    # the grid contractions (Eq. 1) on the BF16 matrix cores: issued flops of
+    # the three-term split over the measured launch times
+    contraction = None
+    if prec == bse.BSE_MIXED and "gemm_exchange" in kt and "gemm_direct" in kt:
+        n_ia = spec.n_o * spec.n_c
+        n_ab = spec.n_c * (spec.n_c + 1) // 2
+        fl_x = 3.0 * 2.0 * n_ia * n_ia * spec.ng
+        fl_d = 3.0 * 2.0 * n_ab * B * spec.ng
+        ms_x, ms_d = kt["gemm_exchange"][0], kt["gemm_direct"][0]
+        tf = (fl_x + fl_d) / ((ms_x + ms_d) * 1e-3) / 1e12
+        contraction = {"bound": "mfma", "kernel": "k_gemm_bf16x3 (exchange + direct)",
+                       "achieved": round(tf, 1), "peak": PEAK_BF16_TFS, "unit": "TFLOP/s",
+                       "frac": round(tf / PEAK_BF16_TFS, 4),
+                       "flops_issued": fl_x + fl_d, "ms": round(ms_x + ms_d, 4),
+                       "exchange": {"M": n_ia, "N": n_ia, "K": spec.ng, "ms": round(ms_x, 4),
+                                    "tflops": round(fl_x / (ms_x * 1e-3) / 1e12, 1)},
+                       "direct": {"M": n_ab, "N": B, "K": spec.ng, "ms": round(ms_d, 4),
+                                  "tflops": round(fl_d / (ms_d * 1e-3) / 1e12, 1)}}
+
     out = {
         "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",
         "value": round(value, 3), "unit": "pair solves/s", "n_gpus": 1,
@@ -355,6 +381,8 @@ def main():
         "roofline": roofline,
         "kernels_ms": {k: v[0] for k, v in kt.items()},
     }
+    if contraction is not None:
+        out["roofline_contraction"] = contraction
 
     if not args.no_cpu_baseline:
         pair = tuple(int(x) for x in pairs[-1])

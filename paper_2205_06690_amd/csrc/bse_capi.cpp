@@ -531,8 +531,10 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     v32.alloc(sizeof(float) * ng * n_ia);
     HIPC(launch_to_real<float>(rho64.as<double>(), ng * n_ia, rho32.as<float>(), st));
     HIPC(launch_to_real<float>(v64.as<double>(), ng * n_ia, v32.as<float>(), st));
+    auto* t = s->timer.begin("gemm_exchange");
     HIPC(launch_gemm_bf16x3(rho32.as<float>(), n_ia, v32.as<float>(), n_ia, ng, s->dv,
                             part.as<float>(), X.as<double>(), st));
+    s->timer.end(t);
   }
   // 3. direct (ab|W|ij) over a <= b and i <= j
   HIPC(hipStreamSynchronize(st));
@@ -550,8 +552,10 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     w32.alloc(sizeof(float) * ng * n_ij);
     HIPC(launch_products<float>(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, rab.as<float>(), st));
     HIPC(launch_to_real<float>(s->wij.as<double>(), ng * n_ij, w32.as<float>(), st));
+    auto* t = s->timer.begin("gemm_direct");
     HIPC(launch_gemm_bf16x3(rab.as<float>(), n_ab, w32.as<float>(), n_ij, ng, s->dv,
                             part.as<float>(), Dm.as<double>(), st));
+    s->timer.end(t);
     HIPC(hipStreamSynchronize(st));
   }
   // 4. assemble

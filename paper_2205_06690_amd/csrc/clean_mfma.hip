@@ -133,7 +133,9 @@ __global__ void __launch_bounds__(256) k_coef_x3(const float2* __restrict__ d, i
   __shared__ __attribute__((aligned(16))) __bf16 Bl[XT][XKP];
   const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntile) return;
-  const int rt = (int)(t % nrt), ct = (int)((t / nrt) % nct), kc = (int)(t / ((unsigned)nrt * nct));
+  // column tile fastest: the column tiles of one row tile run together on one
+  // XCD and read its d tile (and the finish inputs) from L2, not HBM
+  const int ct = (int)(t % nct), rt = (int)((t / nct) % nrt), kc = (int)(t / ((unsigned)nrt * nct));
   const int R = 2 * F, S = ps.S;
   const int r0 = rt * XT, s0 = ct * XT, f0 = r0 / 2;
   const size_t k0 = (size_t)kc * chunk;
