@@ -92,3 +92,65 @@ def absorption(omega: np.ndarray, dip2: np.ndarray, w_grid: np.ndarray,
     g = np.exp(-0.5 * ((w_grid[:, None] - omega[None, :]) / sigma) ** 2) / (
         sigma * math.sqrt(2.0 * math.pi))
     return w_grid * (g @ s)
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev spectrum (Eqs. 7-8): sigma(omega) = omega <f0| delta(A - omega)
+# |f0>, the broadened delta expanded in Chebyshev polynomials of the scaled
+# A, with the residues R_n = <f0| T_n(A~) |f0> from the three-term
+# recursion.  A~ = (A - b) / a maps [e_min, e_max] into [-1, 1].
+# ---------------------------------------------------------------------------
+def spectral_bounds(A: np.ndarray):
+    """Gershgorin interval of the symmetric matrix A."""
+    r = np.abs(A).sum(axis=1) - np.abs(np.diag(A))
+    return float(np.min(np.diag(A) - r)), float(np.max(np.diag(A) + r))
+
+
+def chebyshev_scale(e_min: float, e_max: float, margin: float = 0.01):
+    """(a, b) with A~ = (A - b)/a; the interval is widened by ``margin`` of
+    its half-width so that the spectrum sits strictly inside (-1, 1)."""
+    b = 0.5 * (e_max + e_min)
+    a = 0.5 * (e_max - e_min) * (1.0 + margin)
+    return a, b
+
+
+def chebyshev_residues(A: np.ndarray, f0: np.ndarray, n_mom: int, a: float, b: float):
+    """R_n = <f0 | T_n(A~) | f0> for n < n_mom, one column of f0 per
+    polarisation: f^0 = f0, f^1 = A~ f^0, f^{n+1} = 2 A~ f^n - f^{n-1}."""
+    At = (A - b * np.eye(A.shape[0])) / a
+    f_prev = f0.copy()
+    R = np.zeros((n_mom, f0.shape[1]))
+    R[0] = np.sum(f0 * f_prev, axis=0)
+    if n_mom == 1:
+        return R
+    f_cur = At @ f0
+    R[1] = np.sum(f0 * f_cur, axis=0)
+    for n in range(2, n_mom):
+        f_next = 2.0 * (At @ f_cur) - f_prev
+        R[n] = np.sum(f0 * f_next, axis=0)
+        f_prev, f_cur = f_cur, f_next
+    return R
+
+
+def chebyshev_coefficients(w_grid: np.ndarray, n_mom: int, a: float, b: float, sigma: float,
+                           n_nodes: int | None = None):
+    """g_n(omega): Chebyshev coefficients in A~ of the Gaussian delta of
+    standard deviation ``sigma`` centred at omega, by Gauss-Chebyshev
+    quadrature on ``n_nodes`` nodes (default 2 n_mom):
+    g_n = (2 - delta_n0)/M sum_k G(a cos th_k + b - omega) cos(n th_k),
+    th_k = pi (k + 1/2) / M."""
+    M = 2 * n_mom if n_nodes is None else n_nodes
+    th = math.pi * (np.arange(M) + 0.5) / M
+    E = a * np.cos(th) + b
+    G = np.exp(-0.5 * ((E[None, :] - w_grid[:, None]) / sigma) ** 2) / (sigma * math.sqrt(2.0 * math.pi))
+    C = np.cos(np.arange(n_mom)[:, None] * th[None, :])           # [n, k]
+    g = (G @ C.T) / M
+    g[:, 1:] *= 2.0
+    return g                                                       # [n_w, n_mom]
+
+
+def chebyshev_absorption(R: np.ndarray, w_grid: np.ndarray, a: float, b: float, sigma: float,
+                         n_nodes: int | None = None) -> np.ndarray:
+    """Eq. 7 through Eq. 8: sigma(omega) = omega sum_pol sum_n g_n(omega) R_n."""
+    g = chebyshev_coefficients(w_grid, R.shape[0], a, b, sigma, n_nodes)
+    return w_grid * (g @ R.sum(axis=1))

@@ -133,3 +133,67 @@ def test_excitons_uncoupled_and_absorption_sum():
     with np.errstate(divide="ignore", invalid="ignore"):
         integ = np.trapezoid(np.where(wg != 0, sig / wg, 0.0), wg)
     assert abs(integ - dip2.sum()) < 1e-6 * dip2.sum()
+
+
+# --------------------------------------------------------------------------
+# Chebyshev spectrum (Eqs. 7-8)
+# --------------------------------------------------------------------------
+def _sym(n, seed, lo=0.2, hi=1.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(lo, hi, n))
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), rng.standard_normal((n, 3))
+
+
+def test_chebyshev_residues_closed_form():
+    """R_n = sum_k |<X_k|f0>|^2 cos(n arccos((lambda_k - b)/a)) from the
+    eigenpairs; a wrong factor 2, sign or start vector in the recursion
+    breaks it."""
+    A, f0 = _sym(30, 3)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    R = bse.chebyshev_residues(A, f0, 200, a, b)
+    w, X = np.linalg.eigh(A)
+    p = (X.T @ f0) ** 2
+    th = np.arccos((w - b) / a)
+    Rc = np.array([(np.cos(n * th)[:, None] * p).sum(axis=0) for n in range(200)])
+    assert np.abs(R - Rc).max() < 1e-12 * np.abs(Rc).max()
+    assert np.allclose(R[0], (f0 ** 2).sum(axis=0))
+
+
+def test_chebyshev_absorption_converges_to_eigen_sum():
+    """With enough moments the Chebyshev spectrum equals the Gaussian-
+    broadened sum over excitons; too few moments leave a visible error."""
+    A, f0 = _sym(40, 5)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    s = 0.02
+    wg = np.linspace(0.1, 1.1, 150)
+    w, X = np.linalg.eigh(A)
+    ref = bse.absorption(w, (X.T @ f0) ** 2, wg, s)
+    errs = []
+    for N in (int(a / s), int(8 * a / s)):
+        R = bse.chebyshev_residues(A, f0, N, a, b)
+        errs.append(np.abs(bse.chebyshev_absorption(R, wg, a, b, s) - ref).max() / np.abs(ref).max())
+    assert errs[0] > 1e-3
+    assert errs[1] < 1e-10
+
+
+def test_chebyshev_single_level():
+    """A = [[E0]]: sigma(omega) = omega f^2 G(E0 - omega) exactly (the
+    interval is widened around the single level)."""
+    E0, f = 0.37, 1.3
+    A = np.array([[E0]])
+    f0 = np.array([[f, 0.0, 0.0]])
+    a, b = bse.chebyshev_scale(E0 - 0.2, E0 + 0.2)
+    s = 0.01
+    wg = np.linspace(0.3, 0.45, 31)
+    R = bse.chebyshev_residues(A, f0, 400, a, b)
+    g = np.exp(-0.5 * ((wg - E0) / s) ** 2) / (s * math.sqrt(2 * math.pi))
+    assert np.abs(bse.chebyshev_absorption(R, wg, a, b, s) - wg * f * f * g).max() < 1e-9 * (wg * f * f * g).max()
+
+
+def test_gershgorin_bounds_contain_spectrum():
+    A, _ = _sym(25, 9, lo=-0.5, hi=2.0)
+    lo, hi = bse.spectral_bounds(A)
+    w = np.linalg.eigvalsh(A)
+    assert lo <= w[0] and w[-1] <= hi
