@@ -259,6 +259,7 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--train-seconds", type=float, default=420.0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -347,6 +348,21 @@ def main():
         roofline["traffic_GBs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
 
+    # the Chebyshev spectrum (Eqs. 7-8) of the same A, timed outside the step:
+    # 6 a / sigma residues over the Gershgorin interval, 0.08 eV broadening
+    cheb = None
+    if "chebyshev" not in args.skip:
+        sig = 0.08 / inputs.HARTREE_EV
+        _, _, bo = S.chebyshev_spectrum(2, None)
+        n_mom = 2 * int(math.ceil(3.0 * 1.01 * (bo[1] - bo[0]) / 2 / sig))
+        wg = np.linspace(bo[0], bo[1], 2000)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        S.chebyshev_spectrum(n_mom, wg, sig, bounds=bo)
+        torch.cuda.synchronize()
+        cheb = {"n_residues": n_mom, "ms": round((time.perf_counter() - tc0) * 1e3, 3),
+                "interval_Ha": [round(float(bo[0]), 6), round(float(bo[1]), 6)], "n_omega": 2000}
+
     # the grid contractions (Eq. 1) on the BF16 matrix cores: issued flops of
     # the three-term split over the measured launch times
     contraction = None
@@ -383,6 +399,8 @@ def main():
     }
     if contraction is not None:
         out["roofline_contraction"] = contraction
+    if cheb is not None:
+        out["chebyshev_spectrum"] = cheb
 
     if not args.no_cpu_baseline:
         pair = tuple(int(x) for x in pairs[-1])

@@ -123,6 +123,24 @@ bse_status bse_build_A(bse_system* sys, int32_t n_o, int32_t n_c, double* A);
 bse_status bse_spectrum(bse_system* sys, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
                         const double* w_grid, double sigma_broad, double* sigma);
 
+/* Absorption by the Chebyshev expansion of the broadened delta (Eqs. 7-8)
+ * on the A of the last bse_build_A, in FP64 on the device.  For each of
+ * the three polarisations, with the electron-hole dipoles
+ * f0_ia = <phi_a| r_axis - box centre |phi_i> as start vector, the
+ * residues R_n = <f0| T_n(A~) |f0>, n < n_mom, where A~ = (A - b)/a,
+ * b = (e_min + e_max)/2 and a = 1.01 (e_max - e_min)/2; then
+ * sigma(w) = w sum_axis sum_n g_n(w) R_n with g_n(w) the Chebyshev
+ * coefficients (in A~) of a normalised Gaussian of standard deviation
+ * sigma_broad centred at w, by Gauss-Chebyshev quadrature on 2 n_mom nodes.
+ * e_min < e_max: caller's bound on the spectrum of A (Hartree); otherwise
+ * the Gershgorin interval of A is used.  n_mom: even, >= 2.  Outputs (host):
+ * sigma[n_w] if n_w > 0, residues[3][n_mom] (nullable unless n_w == 0),
+ * bounds[2] = the interval used (nullable).  Errors: BSE_ERR_STATE before
+ * bse_build_A; BSE_ERR_ARG on bad sizes or a degenerate interval. */
+bse_status bse_chebyshev_spectrum(bse_system* sys, int32_t n_mom, double e_min, double e_max,
+                                  int32_t n_w, const double* w_grid, double sigma_broad,
+                                  double* sigma, double* residues, double* bounds);
+
 /* Uneven batch: the W-action for several systems at once (different grids,
  * orbital counts and pair counts, same device).  System k propagates
  * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and

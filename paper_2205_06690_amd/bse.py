@@ -31,7 +31,7 @@ EXPORTS = (
     "bse_tuned_shape", "bse_fno_create", "bse_fno_num_params", "bse_fno_set_params",
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
-    "bse_fno_make_samples", "bse_apply_W_surrogate",
+    "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
 )
 
 
@@ -74,6 +74,8 @@ def _load():
     lib.bse_apply_W_device.argtypes = [P, C.c_int32, ip, P, P]
     lib.bse_build_A.argtypes = [P, C.c_int32, C.c_int32, dp]
     lib.bse_spectrum.argtypes = [P, C.c_int32, dp, dp, C.c_int32, dp, C.c_double, dp]
+    lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
+                                           C.c_double, dp, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
     lib.bse_generate_signs.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
@@ -210,6 +212,22 @@ class System:
         A = np.empty((n_o * n_c, n_o * n_c))
         _check(LIB.bse_build_A(self._h, n_o, n_c, _dptr(A)))
         return A
+
+    def chebyshev_spectrum(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
+                           bounds=None):
+        """(sigma on w_grid or None, residues [3][n_mom], interval used)."""
+        res = np.empty((3, n_mom))
+        bo = np.empty(2)
+        lo, hi = (0.0, 0.0) if bounds is None else (float(bounds[0]), float(bounds[1]))
+        if w_grid is None:
+            _check(LIB.bse_chebyshev_spectrum(self._h, n_mom, lo, hi, 0, None, sigma, None,
+                                              _dptr(res), _dptr(bo)))
+            return None, res, bo
+        wg = np.ascontiguousarray(w_grid, dtype=np.float64)
+        sg = np.empty(wg.size)
+        _check(LIB.bse_chebyshev_spectrum(self._h, n_mom, lo, hi, wg.size, _dptr(wg), sigma, _dptr(sg),
+                                          _dptr(res), _dptr(bo)))
+        return sg, res, bo
 
     def spectrum(self, n_exc: int, w_grid=None, sigma: float = 0.08 / 27.211386245988):
         om = np.empty(n_exc)

@@ -767,6 +767,71 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
   }
 }
 
+// Chebyshev absorption (Eqs. 7-8) on the device copy of A: the residues of
+// the three dipole start vectors by the recursion in A~ = (A - b)/a, then the
+// broadened delta through its Chebyshev coefficients (Gauss-Chebyshev
+// quadrature on M = 2 n_mom nodes, summed at the nodes).
+void chebyshev_spectrum(bse_system* s, int n_mom, double e_min, double e_max, int n_w,
+                        const double* w_grid, double sig, double* sigma, double* residues,
+                        double* bounds) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_chebyshev_spectrum: call bse_build_A first");
+  const int n = s->a_no * s->a_nc;
+  if (n_mom < 2 || n_mom % 2 != 0 || n_w < 0 || (n_w > 0 && (!w_grid || !sigma || !(sig > 0))) ||
+      (n_w == 0 && !residues))
+    fail(BSE_ERR_ARG, "bse_chebyshev_spectrum: bad arguments");
+  hipStream_t st = s->stream;
+  const double* A = s->A_d.as<double>();
+  if (!(e_min < e_max)) {
+    DBuf lohi;
+    lohi.alloc(sizeof(double) * 2 * (size_t)n);
+    HIPC(launch_gershgorin(A, n, lohi.as<double>(), st));
+    std::vector<double> h(2 * (size_t)n);
+    HIPC(hipMemcpyAsync(h.data(), lohi.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    e_min = *std::min_element(h.begin(), h.begin() + n);
+    e_max = *std::max_element(h.begin() + n, h.end());
+    if (!(e_min < e_max)) fail(BSE_ERR_ARG, "bse_chebyshev_spectrum: degenerate interval; pass bounds");
+  }
+  const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
+  const int K = n_mom / 2, nblk = cheb_blocks(n), M = 2 * n_mom;
+  DBuf fv, part, mu, D, wd, sd;
+  fv.alloc(sizeof(double) * 9 * (size_t)n);
+  part.alloc(sizeof(double) * 6 * (size_t)K * nblk);
+  mu.alloc(sizeof(double) * 3 * (size_t)n_mom);
+  D.alloc(sizeof(double) * 3 * (size_t)M);
+  if (n_w > 0) {
+    wd.alloc(sizeof(double) * n_w);
+    sd.alloc(sizeof(double) * n_w);
+    HIPC(hipMemcpyAsync(wd.p, w_grid, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
+  }
+  // f^0 = dipoles, [n][3] -> [3][n]
+  std::vector<double> f0(3 * (size_t)n), f0t(3 * (size_t)n);
+  HIPC(hipMemcpyAsync(f0.data(), s->f0_d.p, sizeof(double) * f0.size(), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    for (int p = 0; p < 3; ++p) f0t[(size_t)p * n + i] = f0[(size_t)i * 3 + p];
+  double* buf = fv.as<double>();
+  HIPC(hipMemcpyAsync(buf, f0t.data(), sizeof(double) * f0t.size(), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < K; ++k) {
+    const double* fc = buf + (size_t)(k % 3) * 3 * n;
+    const double* fp = buf + (size_t)((k + 2) % 3) * 3 * n;
+    double* fn = buf + (size_t)((k + 1) % 3) * 3 * n;
+    HIPC(launch_cheb_step(A, n, fc, fp, fn, a, b, k == 0 ? 1 : 0,
+                          part.as<double>() + (size_t)k * nblk * 6, st));
+  }
+  HIPC(launch_cheb_spectrum(part.as<double>(), K, nblk, mu.as<double>(), M, D.as<double>(), a, b,
+                            wd.as<double>(), n_w, sig, sd.as<double>(), st));
+  if (n_w > 0) HIPC(hipMemcpyAsync(sigma, sd.p, sizeof(double) * n_w, hipMemcpyDeviceToHost, st));
+  if (residues)
+    HIPC(hipMemcpyAsync(residues, mu.p, sizeof(double) * 3 * (size_t)n_mom, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (bounds) {
+    bounds[0] = e_min;
+    bounds[1] = e_max;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // autotuner: x-tile width and plane-pass block size for this system's grid,
 // batch size and precision, timed on the system's own buffers; results are
@@ -1282,6 +1347,14 @@ bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip
                         const double* w_grid, double sigma_broad, double* sigma) {
   API_BEGIN
   spectrum(s, n_exc, omega, dip2, n_w, w_grid, sigma_broad, sigma);
+  API_END
+}
+
+bse_status bse_chebyshev_spectrum(bse_system* s, int32_t n_mom, double e_min, double e_max,
+                                  int32_t n_w, const double* w_grid, double sigma_broad,
+                                  double* sigma, double* residues, double* bounds) {
+  API_BEGIN
+  chebyshev_spectrum(s, n_mom, e_min, e_max, n_w, w_grid, sigma_broad, sigma, residues, bounds);
   API_END
 }
 

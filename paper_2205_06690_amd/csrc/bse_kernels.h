@@ -29,6 +29,16 @@ hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipS
 // out[q] = sum_k S[q][k] V[k], q < nq, k < m
 hipError_t launch_ritz(const double* V, int n, int m, const double* S, int nq, double* out,
                        hipStream_t st);
+// Chebyshev spectrum (Eqs. 7-8): Gershgorin rows lohi[2][n]; one recursion
+// step on [3][n] vectors with per-block partial residues part[cheb_blocks(n)][6];
+// residues mu[3][2K], node weights D[3][M] and sigma[n_w] from the partials
+hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t st);
+int cheb_blocks(int n);
+hipError_t launch_cheb_step(const double* A, int n, const double* fc, const double* fp, double* fn,
+                            double a, double b, int first, double* part, hipStream_t st);
+hipError_t launch_cheb_spectrum(const double* part, int K, int nblk, double* mu, int M, double* D,
+                                double a, double b, const double* w, int n_w, double sig,
+                                double* out, hipStream_t st);
 // out = w / sqrt(*bsq), bsq on the device
 hipError_t launch_scale_norm(const double* w, int n, const double* bsq, double* out, hipStream_t st);
 }  // namespace bse

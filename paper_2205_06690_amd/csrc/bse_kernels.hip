@@ -323,6 +323,135 @@ __global__ void k_scale_norm(const double* __restrict__ w, int n, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Chebyshev spectrum (Eqs. 7-8), FP64.  Vectors are [3][n], one row per
+// polarisation.  With A~ = (A - b)/a the recursion f^{n+1} = 2 A~ f^n -
+// f^{n-1} (f^1 = A~ f^0) runs K = n_mom/2 steps; step n also yields
+// S_nn = <f^n|f^n> and S_n1n = <f^{n+1}|f^n>, from which the doubling
+// identities T_2n = 2 T_n^2 - T_0 and T_2n+1 = 2 T_n+1 T_n - T_1 give the
+// residues mu_2n = 2 S_nn - mu_0 and mu_2n+1 = 2 S_n1n - mu_1.
+// ---------------------------------------------------------------------------
+// row i: lo = A_ii - sum_{j != i} |A_ij|, hi = A_ii + sum_{j != i} |A_ij|
+__global__ void __launch_bounds__(256) k_gershgorin(const double* __restrict__ A, int n,
+                                                    double* __restrict__ lohi) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  double r = 0;
+  for (int j = lane; j < n; j += 64)
+    if (j != row) r += fabs(A[(size_t)row * n + j]);
+  for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
+  if (lane == 0) {
+    const double d = A[(size_t)row * n + row];
+    lohi[row] = d - r;
+    lohi[n + row] = d + r;
+  }
+}
+
+// one recursion step, one wave per row; part[blk][0..2] = <fc|fc>,
+// part[blk][3..5] = <fn|fc> over the block's rows
+__global__ void __launch_bounds__(256) k_cheb_step(const double* __restrict__ A, int n,
+                                                   const double* __restrict__ fc,
+                                                   const double* __restrict__ fp,
+                                                   double* __restrict__ fn, double ia, double b,
+                                                   int first, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + w;
+  double s0 = 0, s1 = 0, s2 = 0;
+  if (row < n) {
+    const double* a = A + (size_t)row * n;
+    for (int j = lane; j < n; j += 64) {
+      const double v = a[j];
+      s0 += v * fc[j];
+      s1 += v * fc[n + j];
+      s2 += v * fc[2 * n + j];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+    s2 += __shfl_down(s2, off, 64);
+  }
+  __shared__ double red[4][6];
+  if (lane == 0) {
+    double c[6] = {0, 0, 0, 0, 0, 0};
+    if (row < n) {
+      const double sp[3] = {s0, s1, s2};
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const double cur = fc[(size_t)p * n + row];
+        const double t = (sp[p] - b * cur) * ia;
+        const double nx = first ? t : 2.0 * t - fp[(size_t)p * n + row];
+        fn[(size_t)p * n + row] = nx;
+        c[p] = cur * cur;
+        c[3 + p] = nx * cur;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red[w][q] = c[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6)
+    part[(size_t)blockIdx.x * 6 + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// S[k][q] = sum over blocks of part[k][blk][q] (fixed order), then the
+// residues mu[p][m] for m < 2K
+__global__ void k_cheb_moments(const double* __restrict__ part, int K, int nblk,
+                               double* __restrict__ mu) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (m >= 2 * K) return;
+  auto S = [&](int k, int q) {
+    double acc = 0;
+    for (int i = 0; i < nblk; ++i) acc += part[((size_t)k * nblk + i) * 6 + q];
+    return acc;
+  };
+  const double mu0 = S(0, p), mu1 = S(0, 3 + p);
+  double v;
+  if (m == 0) v = mu0;
+  else if (m == 1) v = mu1;
+  else if (m % 2 == 0) v = 2.0 * S(m / 2, p) - mu0;
+  else v = 2.0 * S(m / 2, 3 + p) - mu1;
+  mu[(size_t)p * 2 * K + m] = v;
+}
+
+// D[p][k] = (1/M) (2 sum_{m<N} mu[p][m] T_m(x_k) - mu[p][0]), x_k = cos(pi (k+1/2)/M),
+// by Clenshaw's recurrence
+__global__ void k_cheb_nodes(const double* __restrict__ mu, int N, int M, double* __restrict__ D) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= M) return;
+  const double x = cos(M_PI * (k + 0.5) / M);
+  const double* m = mu + (size_t)p * N;
+  double b1 = 0, b2 = 0;
+  for (int j = N - 1; j >= 1; --j) {
+    const double b0 = m[j] + 2.0 * x * b1 - b2;
+    b2 = b1;
+    b1 = b0;
+  }
+  const double sum = m[0] + x * b1 - b2;   // sum_j mu_j T_j(x)
+  D[(size_t)p * M + k] = (2.0 * sum - m[0]) / M;
+}
+
+// sigma(omega_q) = omega_q sum_p sum_k G(a x_k + b - omega_q) D[p][k]
+__global__ void k_cheb_sigma(const double* __restrict__ D, int M, double a, double b,
+                             const double* __restrict__ w, int n_w, double sig,
+                             double* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_w) return;
+  const double om = w[q];
+  const double norm = 1.0 / (sig * sqrt(2.0 * M_PI));
+  double acc = 0;
+  for (int k = 0; k < M; ++k) {
+    const double E = a * cos(M_PI * (k + 0.5) / M) + b;
+    const double z = (E - om) / sig;
+    acc += exp(-0.5 * z * z) * (D[k] + D[M + k] + D[2 * M + k]);
+  }
+  out[q] = om * norm * acc;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 __global__ void k_fill_zero_words(unsigned int* __restrict__ p, size_t n) {
@@ -411,6 +540,27 @@ hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double
 
 hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_gemv, dim3(n), dim3(256), 0, st, A, n, v, y);
+  return hipGetLastError();
+}
+hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t st) {
+  hipLaunchKernelGGL(k_gershgorin, dim3((n + 3) / 4), dim3(256), 0, st, A, n, lohi);
+  return hipGetLastError();
+}
+int cheb_blocks(int n) { return (n + 3) / 4; }
+hipError_t launch_cheb_step(const double* A, int n, const double* fc, const double* fp, double* fn,
+                            double a, double b, int first, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_cheb_step, dim3(cheb_blocks(n)), dim3(256), 0, st, A, n, fc, fp, fn, 1.0 / a, b,
+                     first, part);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_spectrum(const double* part, int K, int nblk, double* mu, int M, double* D,
+                                double a, double b, const double* w, int n_w, double sig,
+                                double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cheb_moments, dim3((2 * K + 255) / 256, 3), dim3(256), 0, st, part, K, nblk, mu);
+  hipLaunchKernelGGL(k_cheb_nodes, dim3((M + 255) / 256, 3), dim3(256), 0, st, mu, 2 * K, M, D);
+  if (n_w > 0)
+    hipLaunchKernelGGL(k_cheb_sigma, dim3((n_w + 255) / 256), dim3(256), 0, st, D, M, a, b, w, n_w, sig,
+                       out);
   return hipGetLastError();
 }
 hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,

@@ -66,3 +66,39 @@ def test_build_a_symmetric_and_errors(tiny_a):
     assert e.value.code == bse.BSE_ERR_ARG
     A = s.build_a(spec.n_o, spec.n_c)
     assert np.array_equal(A, A.T)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiny24_chebyshev_spectrum(tiny_a, precision):
+    """Residues and spectrum of the Chebyshev path (Eqs. 7-8) against the
+    oracle on the oracle's A, dipoles and Gershgorin interval.  FP64: the
+    recursion error grows about linearly in n from an A that agrees to
+    1e-11.  Mixed: A agrees to ~1e-7 Ha, which moves a spectrum broadened
+    by 3 mHa by ~1e-7/3e-3 of its size; 1e-3 of the peak is the bar."""
+    spec, sysd, A_o, f0 = tiny_a
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    s.build_a(spec.n_o, spec.n_c)
+    lo, hi = obse.spectral_bounds(A_o)
+    a, b = obse.chebyshev_scale(lo, hi)
+    sig = 0.003
+    n_mom = 2 * int(4 * a / sig)
+    w = np.linalg.eigvalsh(A_o)
+    wg = np.linspace(w[0] - 0.02, w[-1] + 0.02, 300)
+    R_o = obse.chebyshev_residues(A_o, f0, n_mom, a, b)
+    sg_o = obse.chebyshev_absorption(R_o, wg, a, b, sig)
+    sg, R, bo = s.chebyshev_spectrum(n_mom, wg, sig, bounds=(lo, hi))
+    assert np.allclose(bo, [lo, hi])
+    er = np.abs(R - R_o.T).max() / np.abs(R_o[0]).max()
+    es = np.abs(sg - sg_o).max() / np.abs(sg_o).max()
+    say(f"chebyshev prec {precision}: n_mom {n_mom}, residues {er:.2e}, spectrum {es:.2e}")
+    if precision == 0:
+        assert er < 1e-8 and es < 1e-9
+    else:
+        assert es < 1e-3
+    # the Gershgorin interval of the library's A contains the oracle's spectrum
+    _, _, bo2 = s.chebyshev_spectrum(4, None)
+    assert bo2[0] <= w[0] + 1e-6 and w[-1] - 1e-6 <= bo2[1]
+    from paper_2205_06690_amd import bse
+    with pytest.raises(bse.BseError) as e:
+        s.chebyshev_spectrum(7, wg)
+    assert e.value.code == bse.BSE_ERR_ARG

@@ -38,6 +38,23 @@ def test_mid64_bench_batch_w_and_a_block():
     s = gpu_system(spec, sysd, bse.BSE_MIXED, max_batch=len(pairs))
     w, wp = s.apply_w(pairs, want_wpol=True)
     A = s.build_a(spec.n_o, spec.n_c)
+    # Chebyshev spectrum (Eqs. 7-8) of this A: properties at full size
+    sig = 0.08 / inputs.HARTREE_EV
+    om, d2 = s.spectrum(20)
+    wg = np.linspace(om[0] - 10 * sig, om[-1] + 0.1, 2000)
+    _, _, bo = s.chebyshev_spectrum(2, None)                # the Gershgorin interval
+    # the Gaussian's Chebyshev coefficients fall as exp(-(n sig / a)^2 / 2):
+    # 6 a / sig moments leave ~1e-8 of the peak
+    n_mom = 2 * int(np.ceil(3.0 * 1.01 * (bo[1] - bo[0]) / 2 / sig))
+    sg_c, R, _ = s.chebyshev_spectrum(n_mom, wg, sig, bounds=bo)
+    _, _, sg_l = s.spectrum(20, wg, sig)
+    # sigma / omega is the smooth broadened density; the grid avoids omega = 0
+    # exactly (the lowest exciton of this synthetic molecule is below zero)
+    lower = om[0] - 10 * sig
+    full = np.linspace(lower, bo[1] + 10 * sig, int((bo[1] + 10 * sig - lower) / (0.25 * sig)) + 2)
+    if np.abs(full).min() < 1e-12:
+        full = full + 0.5 * (full[1] - full[0])
+    sg_full, _, _ = s.chebyshev_spectrum(n_mom, full, sig, bounds=bo)
     s.close()
     say("mid64: oracle W for the sampled pair (400 steps)")
     w_o, wp_o = oracle_w(spec, sysd, pairs[k:k + 1])
@@ -64,6 +81,23 @@ def test_mid64_bench_batch_w_and_a_block():
     say(f"mid64: A block max|dA| {err:.3e}, max|D| {np.abs(D).max():.3e}")
     assert err < 1e-3 * np.abs(D).max()
     assert np.array_equal(A, A.T)
+    # R_0 = |f0|^2 with the oracle's dipoles; |R_n| <= R_0; the sum rule of
+    # the normalised Gaussians; more than 6 sigma below the 20th exciton the
+    # spectrum equals the Lanczos excitons' one
+    phv = phi[v0:spec.n_occ]
+    f0 = obse.dipoles(grid, phv, cond)
+    R0 = (f0 ** 2).sum(axis=0)
+    say(f"mid64: chebyshev interval {bo}, {n_mom} residues, R0 rel err "
+        f"{np.abs(R[:, 0] - R0).max() / R0.max():.2e}")
+    assert np.abs(R[:, 0] - R0).max() < 1e-10 * R0.max()
+    assert np.abs(R).max() <= R0.max() * (1 + 1e-9)
+    sr = np.trapezoid(sg_full / full, full) if hasattr(np, "trapezoid") else np.trapz(sg_full / full, full)
+    say(f"mid64: sum rule {sr:.10e} vs {R0.sum():.10e}")
+    assert abs(sr - R0.sum()) < 1e-6 * R0.sum()
+    low = wg < om[19] - 6 * sig
+    el = np.abs(sg_c[low] - sg_l[low]).max() / np.abs(sg_l[low]).max()
+    say(f"mid64: chebyshev vs lanczos below the 20th exciton - 6 sigma {el:.2e}")
+    assert el < 1e-6
 
 
 @pytest.mark.timeout(400)
