@@ -154,3 +154,29 @@ def chebyshev_absorption(R: np.ndarray, w_grid: np.ndarray, a: float, b: float, 
     """Eq. 7 through Eq. 8: sigma(omega) = omega sum_pol sum_n g_n(omega) R_n."""
     g = chebyshev_coefficients(w_grid, R.shape[0], a, b, sigma, n_nodes)
     return w_grid * (g @ R.sum(axis=1))
+
+
+# ---------------------------------------------------------------------------
+# Matrix-free action of A in the mixed hole-grid representation (Eq. 6 with
+# A = Q A-bar): f_j(r) for the n_o valence orbitals j,
+#   (A-bar f)_j = (H0 + Delta - eps_j) f_j + dv phi_j - sum_i f_i W_ij,
+#   dv = v[dn], dn = 2 sum_i phi_i f_i,
+# and Q = 1 - sum_{s < N_occ} |phi_s><phi_s| applied to every f_j.
+# ---------------------------------------------------------------------------
+def apply_a_mixed(grid: Grid, v_ext: np.ndarray, phi_occ: np.ndarray, eps_v: np.ndarray,
+                  w_full: np.ndarray, f: np.ndarray, scissors: float = 0.0) -> np.ndarray:
+    """A f for f [n_o, nx, ny, nz] (real); phi_occ [N_occ, ...] with the
+    valence window as its last n_o rows; eps_v [n_o]; w_full [n_o, n_o, ...]
+    the symmetric W_ij stack."""
+    n_o, n_occ = f.shape[0], phi_occ.shape[0]
+    phv = phi_occ[n_occ - n_o:]
+    dv = grid.poisson(2.0 * np.sum(phv * f, axis=0))
+    out = np.empty_like(f)
+    for j in range(n_o):
+        t = np.real(grid.kinetic(f[j])) + (v_ext + scissors - eps_v[j]) * f[j] + dv * phv[j]
+        for i in range(n_o):
+            t = t - f[i] * w_full[i, j]
+        out[j] = t
+    P = phi_occ.reshape(n_occ, -1)
+    c = (out.reshape(n_o, -1) @ P.T) * grid.dv
+    return out - (c @ P).reshape(out.shape)

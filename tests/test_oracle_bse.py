@@ -197,3 +197,76 @@ def test_gershgorin_bounds_contain_spectrum():
     lo, hi = bse.spectral_bounds(A)
     w = np.linalg.eigvalsh(A)
     assert lo <= w[0] and w[-1] <= hi
+
+
+# --------------------------------------------------------------------------
+# matrix-free A f in the mixed representation (Eq. 6)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def mixed_system():
+    """Eigenstates of a small well potential on 12^3: 6 occupied (the last 2
+    the valence window), 4 conduction, and a symmetric synthetic W_ij stack
+    (smooth, negative-definite like a screened interaction)."""
+    from paper_2205_06690_amd import inputs
+    spec = inputs.SystemSpec(n=12, h=0.7, n_wells=4, seed=11, n_occ=6, n_o=2, n_c=4)
+    sysd = inputs.make_system(spec, use_cache=False)
+    grid = Grid(spec.shape, spec.h)
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    rng = np.random.default_rng(4)
+    x = [np.arange(n) * spec.h for n in spec.shape]
+    X, Y, Z = np.meshgrid(*x, indexing="ij")
+    w = np.zeros((2, 2) + spec.shape)
+    for i in range(2):
+        for j in range(i, 2):
+            c = rng.uniform(2, 6, 3)
+            w[i, j] = w[j, i] = -0.3 * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / 4.0)
+    return spec, grid, sysd["v_ext"], phi, sysd["eps"], w
+
+
+def test_apply_a_mixed_matches_eq1_in_the_conduction_space(mixed_system):
+    """For f_j = sum_b c_jb phi_b, <phi_a| (A f)_i> = sum_jb A(ia; jb) c_jb
+    with A from the electron-hole assembly of Eq. 1."""
+    spec, grid, v, phi, eps, w = mixed_system
+    phv, phc = phi[4:6], phi[6:10]
+    A = bse.build_a(grid, phv, phc, eps[4:6], eps[6:10], w, scissors=0.01)
+    c = np.random.default_rng(2).standard_normal((2, 4))
+    f = (c @ phc.reshape(4, -1)).reshape((2,) + spec.shape)
+    Af = bse.apply_a_mixed(grid, v, phi[:6], eps[4:6], w, f, scissors=0.01)
+    proj = (Af.reshape(2, -1) @ phc.reshape(4, -1).T) * grid.dv                # [i, a]
+    assert np.abs(proj.reshape(-1) - A @ c.reshape(-1)).max() < 1e-9
+
+
+def test_apply_a_mixed_projected_and_symmetric(mixed_system):
+    spec, grid, v, phi, eps, w = mixed_system
+    rng = np.random.default_rng(7)
+    P = phi[:6].reshape(6, -1)
+
+    def q(g):
+        g = g.reshape(2, -1)
+        return (g - ((g @ P.T) * grid.dv) @ P).reshape((2,) + spec.shape)
+    f = q(rng.standard_normal((2,) + spec.shape))
+    g = q(rng.standard_normal((2,) + spec.shape))
+    Af = bse.apply_a_mixed(grid, v, phi[:6], eps[4:6], w, f)
+    Ag = bse.apply_a_mixed(grid, v, phi[:6], eps[4:6], w, g)
+    assert np.abs((Af.reshape(2, -1) @ P.T) * grid.dv).max() < 1e-10
+    lhs = np.sum(g * Af) * grid.dv
+    rhs = np.sum(Ag * f) * grid.dv
+    assert abs(lhs - rhs) < 1e-10 * max(abs(lhs), 1.0)
+
+
+def test_apply_a_mixed_without_interaction(mixed_system):
+    """W = 0 and no Hartree term (the density coupling is removed by taking
+    a conduction state for one hole only and checking against
+    eps_a - eps_j): phi_a is an eigenvector of Q(H0 - eps_j)."""
+    spec, grid, v, phi, eps, w = mixed_system
+    f = np.zeros((2,) + spec.shape)
+    f[1] = phi[7]
+    Af = bse.apply_a_mixed(grid, v, phi[:6], eps[4:6], np.zeros_like(w), f)
+    # the Hartree term 2 phi_j v[phi_j f_j] is present; remove it explicitly
+    dv = grid.poisson(2.0 * phi[5] * phi[7])
+    hart = np.stack([dv * phi[4], dv * phi[5]])
+    P = phi[:6].reshape(6, -1)
+    hart = (hart.reshape(2, -1) - ((hart.reshape(2, -1) @ P.T) * grid.dv) @ P).reshape(hart.shape)
+    rest = Af - hart
+    assert np.abs(rest[0]).max() < 1e-9
+    assert np.abs(rest[1] - (eps[7] - eps[5]) * phi[7]).max() < 1e-7 * np.abs(phi[7]).max()
