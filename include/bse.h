@@ -123,6 +123,19 @@ bse_status bse_build_A(bse_system* sys, int32_t n_o, int32_t n_c, double* A);
 bse_status bse_spectrum(bse_system* sys, int32_t n_exc, double* omega, double* dip2, int32_t n_w,
                         const double* w_grid, double sigma_broad, double* sigma);
 
+/* Matrix-free action of the Tamm-Dancoff operator in the mixed hole-grid
+ * representation (Eq. 6, with A = Q A-bar of the preceding equations), in
+ * FP64 on the device, for the valence window of the last bse_build_A (its
+ * n_o orbitals and the W_ij it keeps): for each of n_vec vectors
+ * f[n_vec][n_o][nx*ny*nz] (host, real, orbital j = n_occ - n_o + index),
+ *   af_j = Q [ (H0 + Delta - eps_j) f_j + v[2 sum_i phi_i f_i] phi_j
+ *              - sum_i f_i W_ij ],
+ * H0 = -1/2 Laplacian (spectral) + V_ext, v the periodic Coulomb kernel with
+ * k = 0 removed, Q = 1 - sum_{s < n_occ} |phi_s><phi_s|.  af has f's layout
+ * (host, caller-allocated).  Errors: BSE_ERR_STATE before bse_build_A;
+ * BSE_ERR_ARG on null pointers or n_o * n_occ > 8192. */
+bse_status bse_apply_A_mixed(bse_system* sys, int32_t n_vec, const double* f, double* af);
+
 /* Absorption by the Chebyshev expansion of the broadened delta (Eqs. 7-8)
  * on the A of the last bse_build_A, in FP64 on the device.  For each of
  * the three polarisations, with the electron-hole dipoles

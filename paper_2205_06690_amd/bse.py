@@ -32,6 +32,7 @@ EXPORTS = (
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
+    "bse_apply_A_mixed",
 )
 
 
@@ -76,6 +77,7 @@ def _load():
     lib.bse_spectrum.argtypes = [P, C.c_int32, dp, dp, C.c_int32, dp, C.c_double, dp]
     lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                            C.c_double, dp, dp, dp]
+    lib.bse_apply_A_mixed.argtypes = [P, C.c_int32, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
     lib.bse_generate_signs.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
@@ -212,6 +214,16 @@ class System:
         A = np.empty((n_o * n_c, n_o * n_c))
         _check(LIB.bse_build_A(self._h, n_o, n_c, _dptr(A)))
         return A
+
+    def apply_a_mixed(self, f: np.ndarray) -> np.ndarray:
+        """A f in the mixed representation; f [n_vec][n_o][ng] or [n_o][ng]."""
+        x = np.ascontiguousarray(f, dtype=np.float64)
+        one = x.ndim == 2
+        if one:
+            x = x[None]
+        out = np.empty_like(x)
+        _check(LIB.bse_apply_A_mixed(self._h, x.shape[0], _dptr(x), _dptr(out)))
+        return out[0] if one else out
 
     def chebyshev_spectrum(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
                            bounds=None):

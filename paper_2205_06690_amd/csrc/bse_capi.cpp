@@ -158,6 +158,7 @@ struct bse_system {
   hipStream_t own_stream = nullptr;
   // surrogate descriptors and buffers
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
+  DBuf mx_f, mx_tf, mx_out, mx_rho, mx_dv, mx_c, mx_part, mx_eps;  // matrix-free A f
   double n0_scale = 0, v_scale = 0;
 };
 
@@ -767,6 +768,69 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
   }
 }
 
+// Matrix-free A f in the mixed hole-grid representation (Eq. 6 with
+// A = Q A-bar) for the valence window of the last bse_build_A, FP64: the
+// kinetic term by the FFT pipeline with the k^2/2 multiplier, the Hartree
+// term from dn = 2 sum phi_i f_i, the exchange-like term from the cached
+// W_ij, then the occupied-space projection as a GEMM and an update.
+void apply_a_mixed_device(bse_system* s, const double* f_dev, double* af_dev) {
+  const int n_o = s->a_no, S = s->cfg.n_occ;
+  const size_t ng = s->ng;
+  hipStream_t st = s->stream;
+  const double* phv = s->phi64.as<double>() + (size_t)(S - n_o) * ng;
+  s->mx_tf.alloc(sizeof(double) * ng * n_o);
+  s->mx_rho.alloc(sizeof(double) * ng);
+  s->mx_dv.alloc(sizeof(double) * ng);
+  s->mx_c.alloc(sizeof(double) * (size_t)n_o * S);
+  s->mx_part.alloc(sizeof(double) * gemm_part_elems(n_o, S, ng));
+  s->work64.alloc(sizeof(cplx<double>) * ng * (size_t)((n_o + 1) / 2));
+  if (!s->vdev.p || s->vdev.bytes < sizeof(double) * ng) {
+    s->vdev.alloc(sizeof(double) * ng);
+    HIPC(hipMemcpy(s->vdev.p, s->vext.data(), sizeof(double) * ng, hipMemcpyHostToDevice));
+  }
+  s->mx_eps.alloc(sizeof(double) * n_o);
+  HIPC(hipMemcpyAsync(s->mx_eps.p, s->eps.data() + (S - n_o), sizeof(double) * n_o,
+                      hipMemcpyHostToDevice, st));
+  // kinetic term: T f_j for the n_o real fields (two per complex transform)
+  PoisArgs<double> a{};
+  a.rho = f_dev;
+  a.B = n_o;
+  a.work = s->work64.as<cplx<double>>();
+  a.tw = s->td.tw.as<cplx<double>>();
+  a.k2 = s->td.k2.as<double>();
+  a.vscale = 1.0 / (double)ng;
+  a.kinetic = 1;
+  a.out64 = s->mx_tf.as<double>();
+  HIPC(launch_poisson<double>(s->n, a, st));
+  // Hartree term
+  HIPC(launch_mixed_density(phv, f_dev, n_o, ng, s->mx_rho.as<double>(), st));
+  poisson64(s, s->mx_rho.as<double>(), 1, s->mx_dv.as<double>(), nullptr, 0.0);
+  HIPC(launch_mixed_combine(f_dev, s->mx_tf.as<double>(), s->vdev.as<double>(), s->mx_eps.as<double>(),
+                            s->cfg.scissors, s->mx_dv.as<double>(), phv, s->wij.as<double>(), n_o, ng,
+                            af_dev, st));
+  // Q: coefficients on the occupied orbitals, then the update
+  HIPC(launch_gemm_f64(af_dev, n_o, s->phi64.as<double>(), S, ng, s->dv, s->mx_part.as<double>(),
+                       s->mx_c.as<double>(), st));
+  HIPC(launch_project_out(af_dev, n_o, s->phi64.as<double>(), S, s->mx_c.as<double>(), ng, st));
+}
+
+void apply_a_mixed(bse_system* s, int n_vec, const double* f, double* af) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_apply_A_mixed: call bse_build_A first");
+  if (n_vec < 0 || (n_vec > 0 && (!f || !af))) fail(BSE_ERR_ARG, "bse_apply_A_mixed: bad arguments");
+  if ((size_t)s->a_no * s->cfg.n_occ * sizeof(double) > 64 * 1024)
+    fail(BSE_ERR_ARG, "bse_apply_A_mixed: n_o * n_occ above 8192");
+  const size_t len = (size_t)s->a_no * s->ng;
+  s->mx_f.alloc(sizeof(double) * len);
+  s->mx_out.alloc(sizeof(double) * len);
+  for (int v = 0; v < n_vec; ++v) {
+    HIPC(hipMemcpyAsync(s->mx_f.p, f + v * len, sizeof(double) * len, hipMemcpyHostToDevice, s->stream));
+    apply_a_mixed_device(s, s->mx_f.as<double>(), s->mx_out.as<double>());
+    HIPC(hipMemcpyAsync(af + v * len, s->mx_out.p, sizeof(double) * len, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPC(hipStreamSynchronize(s->stream));
+}
+
 // Chebyshev absorption (Eqs. 7-8) on the device copy of A: the residues of
 // the three dipole start vectors by the recursion in A~ = (A - b)/a, then the
 // broadened delta through its Chebyshev coefficients (Gauss-Chebyshev
@@ -1347,6 +1411,12 @@ bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip
                         const double* w_grid, double sigma_broad, double* sigma) {
   API_BEGIN
   spectrum(s, n_exc, omega, dip2, n_w, w_grid, sigma_broad, sigma);
+  API_END
+}
+
+bse_status bse_apply_A_mixed(bse_system* s, int32_t n_vec, const double* f, double* af) {
+  API_BEGIN
+  apply_a_mixed(s, n_vec, f, af);
   API_END
 }
 

@@ -29,6 +29,17 @@ hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipS
 // out[q] = sum_k S[q][k] V[k], q < nq, k < m
 hipError_t launch_ritz(const double* V, int n, int m, const double* S, int nq, double* out,
                        hipStream_t st);
+// matrix-free A f (Eq. 6), FP64, fields [n_o][ng]: rho = 2 sum phi_i f_i;
+// out_j = Tf_j + (V + Delta - eps_j) f_j + dv phi_j - sum_i f_i W_ij (W stack
+// of pairs i <= j in row order); out_j -= sum_s C[j][s] phi_s (n_o S <= 8192)
+hipError_t launch_mixed_density(const double* phv, const double* f, int n_o, size_t ng, double* rho,
+                                hipStream_t st);
+hipError_t launch_mixed_combine(const double* f, const double* tf, const double* vext,
+                                const double* eps_v, double scissors, const double* dv,
+                                const double* phv, const double* wij, int n_o, size_t ng,
+                                double* out, hipStream_t st);
+hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
+                              size_t ng, hipStream_t st);
 // Chebyshev spectrum (Eqs. 7-8): Gershgorin rows lohi[2][n]; one recursion
 // step on [3][n] vectors with per-block partial residues part[cheb_blocks(n)][6];
 // residues mu[3][2K], node weights D[3][M] and sigma[n_w] from the partials

@@ -452,6 +452,66 @@ __global__ void k_cheb_sigma(const double* __restrict__ D, int M, double a, doub
 }
 
 // ---------------------------------------------------------------------------
+// matrix-free A f in the mixed hole-grid representation (Eq. 6), FP64: f, Tf
+// and out are [n_o][ng] real fields of the valence window; W_ij comes from
+// the [n_ij][ng] stack of pairs i <= j in row order.
+// ---------------------------------------------------------------------------
+// rho = 2 sum_i phi_i f_i
+__global__ void k_mixed_density(const double* __restrict__ phv, const double* __restrict__ f,
+                                int n_o, size_t ng, double* __restrict__ rho) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  double acc = 0;
+  for (int i = 0; i < n_o; ++i) acc += phv[(size_t)i * ng + r] * f[(size_t)i * ng + r];
+  rho[r] = 2.0 * acc;
+}
+
+// out_j = Tf_j + (V + Delta - eps_j) f_j + dv phi_j - sum_i f_i W_ij
+__global__ void k_mixed_combine(const double* __restrict__ f, const double* __restrict__ tf,
+                                const double* __restrict__ vext, const double* __restrict__ eps_v,
+                                double scissors, const double* __restrict__ dv,
+                                const double* __restrict__ phv, const double* __restrict__ wij,
+                                int n_o, size_t ng, double* __restrict__ out) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= ng) return;
+  const double fj = f[(size_t)j * ng + r];
+  double v = tf[(size_t)j * ng + r] + (vext[r] + scissors - eps_v[j]) * fj + dv[r] * phv[(size_t)j * ng + r];
+  for (int i = 0; i < n_o; ++i) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int p = lo * n_o - lo * (lo - 1) / 2 + (hi - lo);
+    v -= f[(size_t)i * ng + r] * wij[(size_t)p * ng + r];
+  }
+  out[(size_t)j * ng + r] = v;
+}
+
+// out_j -= sum_s C[j][s] phi_s (the occupied-space projection), C staged in LDS
+__global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, int n_o,
+                                                     const double* __restrict__ phi, int S,
+                                                     const double* __restrict__ C, size_t ng) {
+  extern __shared__ double cs[];
+  for (int i = threadIdx.x; i < n_o * S; i += blockDim.x) cs[i] = C[i];
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  constexpr int JB = 8;
+  for (int j0 = 0; j0 < n_o; j0 += JB) {
+    double acc[JB];
+#pragma unroll
+    for (int q = 0; q < JB; ++q) acc[q] = 0;
+    for (int s = 0; s < S; ++s) {
+      const double p = phi[(size_t)s * ng + r];
+#pragma unroll
+      for (int q = 0; q < JB; ++q)
+        if (j0 + q < n_o) acc[q] += cs[(j0 + q) * S + s] * p;
+    }
+#pragma unroll
+    for (int q = 0; q < JB; ++q)
+      if (j0 + q < n_o) out[(size_t)(j0 + q) * ng + r] -= acc[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 __global__ void k_fill_zero_words(unsigned int* __restrict__ p, size_t n) {
@@ -540,6 +600,28 @@ hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double
 
 hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_gemv, dim3(n), dim3(256), 0, st, A, n, v, y);
+  return hipGetLastError();
+}
+hipError_t launch_mixed_density(const double* phv, const double* f, int n_o, size_t ng, double* rho,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_density, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, phv, f, n_o,
+                     ng, rho);
+  return hipGetLastError();
+}
+hipError_t launch_mixed_combine(const double* f, const double* tf, const double* vext,
+                                const double* eps_v, double scissors, const double* dv,
+                                const double* phv, const double* wij, int n_o, size_t ng,
+                                double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_combine, dim3((unsigned)((ng + 255) / 256), n_o), dim3(256), 0, st, f, tf,
+                     vext, eps_v, scissors, dv, phv, wij, n_o, ng, out);
+  return hipGetLastError();
+}
+hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
+                              size_t ng, hipStream_t st) {
+  const size_t sm = sizeof(double) * (size_t)n_o * S;
+  if (sm > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project_out, dim3((unsigned)((ng + 255) / 256)), dim3(256), sm, st, out, n_o, phi,
+                     S, C, ng);
   return hipGetLastError();
 }
 hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t st) {

@@ -43,6 +43,7 @@ template <typename T> struct PoisArgs {
   double* out64;       // nullable [B][ng]
   double* acc;         // nullable [B][ng]: acc += wn * v[rho]
   double wn;
+  int kinetic;         // 1: multiplier vscale k^2/2 (the kinetic operator) instead of vscale/k^2
 };
 
 template <typename T> struct CleanArgs {

@@ -352,11 +352,12 @@ __global__ void __launch_bounds__(256) k_poisson_x(PoisArgs<T> a) {
   stageA_fwd<N>(s, TC, 1, TC, tw, tid, nthr, true);
   __syncthreads();
   const T scale = a.vscale;
-  auto mul = [k2, c0, scale](int line, C v, int kx) {
+  const bool kin = a.kinetic != 0;
+  auto mul = [k2, c0, scale, kin](int line, C v, int kx) {
     const int c = c0 + line;
     const int ky = scr2k<N>(c / N), kz = scr2k<N>(c % N);
     const T kk = k2[kx] + k2[ky] + k2[kz];
-    const T f = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / kk;
+    const T f = kin ? scale * (T)0.5 * kk : ((kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / kk);
     return cscale(v, f);
   };
   stageB<N, 2>(s, TC, 1, TC, tw, tid, nthr, true, mul);

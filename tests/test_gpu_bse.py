@@ -102,3 +102,35 @@ def test_tiny24_chebyshev_spectrum(tiny_a, precision):
     with pytest.raises(bse.BseError) as e:
         s.chebyshev_spectrum(7, wg)
     assert e.value.code == bse.BSE_ERR_ARG
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-3)])
+def test_tiny24_apply_a_mixed(precision, tol):
+    """Matrix-free A f (Eq. 6) against the oracle on random virtual-space
+    vectors, with the oracle's own W_ij.  Mixed precision: the library's W
+    carries the propagation's error (bar 1e-3 on W), which enters A f only
+    through the sum_i f_i W_ij term."""
+    spec, sysd = system("tiny24")
+    pairs = inputs.ij_pairs(spec)
+    w, _ = oracle_w(spec, sysd, pairs)
+    grid = Grid(spec.shape, spec.h)
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    v0 = spec.n_occ - spec.n_o
+    wf = obse.w_stack(spec.n_o, [(i - v0, j - v0) for i, j in pairs], w)
+    rng = np.random.default_rng(12)
+    P = phi[:spec.n_occ].reshape(spec.n_occ, -1)
+    f = rng.standard_normal((spec.n_o, spec.ng))
+    f = f - ((f @ P.T) * grid.dv) @ P
+    f = f.reshape((spec.n_o,) + spec.shape)
+    ref = obse.apply_a_mixed(grid, sysd["v_ext"], phi[:spec.n_occ], sysd["eps"][v0:spec.n_occ], wf, f)
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    s.build_a(spec.n_o, spec.n_c)
+    got = s.apply_a_mixed(f.reshape(spec.n_o, -1)).reshape(f.shape)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"apply_a_mixed prec {precision}: rel {err:.2e}")
+    assert err < tol
+    from paper_2205_06690_amd import bse
+    s2 = gpu_system(spec, sysd, precision, max_batch=3)
+    with pytest.raises(bse.BseError) as e:
+        s2.apply_a_mixed(f.reshape(spec.n_o, -1))
+    assert e.value.code == bse.BSE_ERR_STATE
