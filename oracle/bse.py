@@ -180,3 +180,40 @@ def apply_a_mixed(grid: Grid, v_ext: np.ndarray, phi_occ: np.ndarray, eps_v: np.
     P = phi_occ.reshape(n_occ, -1)
     c = (out.reshape(n_o, -1) @ P.T) * grid.dv
     return out - (c @ P).reshape(out.shape)
+
+
+def chebyshev_residues_op(apply, f0_list, n_mom: int, a: float, b: float, inner):
+    """R_n[p] = inner(f0_p, T_n(A~) f0_p) for a linear operator given by
+    ``apply`` (A~ = (A - b)/a), n < n_mom, by the three-term recursion."""
+    R = np.zeros((n_mom, len(f0_list)))
+    for p, f0 in enumerate(f0_list):
+        f_prev = f0
+        R[0, p] = inner(f0, f0)
+        if n_mom == 1:
+            continue
+        f_cur = (apply(f0) - b * f0) / a
+        R[1, p] = inner(f0, f_cur)
+        for n in range(2, n_mom):
+            f_next = 2.0 * (apply(f_cur) - b * f_cur) / a - f_prev
+            R[n, p] = inner(f0, f_next)
+            f_prev, f_cur = f_cur, f_next
+    return R
+
+
+def mixed_dipole_start(grid: Grid, phi_occ: np.ndarray, n_o: int):
+    """Start vectors of the mixed representation, one per axis:
+    f0_j = Q (r_axis - box centre) phi_j for the valence window (the last
+    n_o occupied orbitals); [3][n_o, nx, ny, nz]."""
+    n_occ = phi_occ.shape[0]
+    phv = phi_occ[n_occ - n_o:]
+    P = phi_occ.reshape(n_occ, -1)
+    xs = grid.coords()
+    out = []
+    for ax in range(3):
+        shp = [1, 1, 1]
+        shp[ax] = -1
+        x = (xs[ax] - 0.5 * grid.shape[ax] * grid.h).reshape(shp)
+        f = (phv * x).reshape(n_o, -1)
+        f = f - ((f @ P.T) * grid.dv) @ P
+        out.append(f.reshape((n_o,) + grid.shape))
+    return out

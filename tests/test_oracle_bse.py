@@ -270,3 +270,28 @@ def test_apply_a_mixed_without_interaction(mixed_system):
     rest = Af - hart
     assert np.abs(rest[0]).max() < 1e-9
     assert np.abs(rest[1] - (eps[7] - eps[5]) * phi[7]).max() < 1e-7 * np.abs(phi[7]).max()
+
+
+def test_chebyshev_residues_operator_form_closed_form():
+    """The operator form of the recursion against the eigenpair closed form."""
+    A, f0 = _sym(20, 13)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    R = bse.chebyshev_residues_op(lambda v: A @ v, [f0[:, p] for p in range(3)], 120, a, b,
+                                  lambda u, v: float(u @ v))
+    w, X = np.linalg.eigh(A)
+    p = (X.T @ f0) ** 2
+    th = np.arccos((w - b) / a)
+    Rc = np.array([(np.cos(n * th)[:, None] * p).sum(axis=0) for n in range(120)])
+    assert np.abs(R - Rc).max() < 1e-12 * np.abs(Rc).max()
+
+
+def test_mixed_dipole_start_projects_to_eh_dipoles(mixed_system):
+    """<phi_a| f0_j> = <phi_a| x |phi_j> for conduction a (Q leaves the
+    virtual components alone) and <phi_s| f0_j> = 0 for occupied s."""
+    spec, grid, v, phi, eps, w = mixed_system
+    f0 = bse.mixed_dipole_start(grid, phi[:6], 2)
+    d = bse.dipoles(grid, phi[4:6], phi[6:10])                 # [(i, a), axis]
+    for ax in range(3):
+        proj = (f0[ax].reshape(2, -1) @ phi[6:10].reshape(4, -1).T) * grid.dv
+        assert np.abs(proj.reshape(-1) - d[:, ax]).max() < 1e-12
+        assert np.abs((f0[ax].reshape(2, -1) @ phi[:6].reshape(6, -1).T) * grid.dv).max() < 1e-12
