@@ -136,6 +136,23 @@ bse_status bse_spectrum(bse_system* sys, int32_t n_exc, double* omega, double* d
  * BSE_ERR_ARG on null pointers or n_o * n_occ > 8192. */
 bse_status bse_apply_A_mixed(bse_system* sys, int32_t n_vec, const double* f, double* af);
 
+/* The paper's spectrum algorithm (Eqs. 6-8): the Chebyshev recursion of
+ * bse_chebyshev_spectrum with A applied matrix-free in the mixed
+ * representation (bse_apply_A_mixed) instead of the electron-hole matrix,
+ * so the excitations range over the whole virtual space of the grid.  Start
+ * vectors, one per axis: f0_j = Q (r_axis - box centre) phi_j over the
+ * valence window of the last bse_build_A; residues R_n = sum_j
+ * <f0_j| T_n(A~) f0_j> (h^3 sum over the grid), A~ = (A - b)/a with
+ * b = (e_min + e_max)/2, a = 1.01 (e_max - e_min)/2, where e_min < e_max
+ * must bound the spectrum of A on the virtual space (required; the kinetic
+ * part reaches 3 (pi/h)^2 / 2).  sigma[n_w], residues[3][n_mom] (nullable
+ * unless n_w == 0) as in bse_chebyshev_spectrum.  FP64 on the device;
+ * costs 3 n_mom / 2 applications of A.  Errors: BSE_ERR_STATE before
+ * bse_build_A; BSE_ERR_ARG on bad sizes or bounds. */
+bse_status bse_chebyshev_mixed(bse_system* sys, int32_t n_mom, double e_min, double e_max,
+                               int32_t n_w, const double* w_grid, double sigma_broad,
+                               double* sigma, double* residues);
+
 /* Absorption by the Chebyshev expansion of the broadened delta (Eqs. 7-8)
  * on the A of the last bse_build_A, in FP64 on the device.  For each of
  * the three polarisations, with the electron-hole dipoles

@@ -32,7 +32,7 @@ EXPORTS = (
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
-    "bse_apply_A_mixed",
+    "bse_apply_A_mixed", "bse_chebyshev_mixed",
 )
 
 
@@ -78,6 +78,8 @@ def _load():
     lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                            C.c_double, dp, dp, dp]
     lib.bse_apply_A_mixed.argtypes = [P, C.c_int32, dp, dp]
+    lib.bse_chebyshev_mixed.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
+                                        C.c_double, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
     lib.bse_generate_signs.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
@@ -224,6 +226,21 @@ class System:
         out = np.empty_like(x)
         _check(LIB.bse_apply_A_mixed(self._h, x.shape[0], _dptr(x), _dptr(out)))
         return out[0] if one else out
+
+    def chebyshev_mixed(self, n_mom: int, bounds, w_grid=None,
+                        sigma: float = 0.08 / 27.211386245988):
+        """(sigma on w_grid or None, residues [3][n_mom]) of the mixed
+        representation; bounds = (e_min, e_max) of A on the virtual space."""
+        res = np.empty((3, n_mom))
+        lo, hi = float(bounds[0]), float(bounds[1])
+        if w_grid is None:
+            _check(LIB.bse_chebyshev_mixed(self._h, n_mom, lo, hi, 0, None, sigma, None, _dptr(res)))
+            return None, res
+        wg = np.ascontiguousarray(w_grid, dtype=np.float64)
+        sg = np.empty(wg.size)
+        _check(LIB.bse_chebyshev_mixed(self._h, n_mom, lo, hi, wg.size, _dptr(wg), sigma, _dptr(sg),
+                                       _dptr(res)))
+        return sg, res
 
     def chebyshev_spectrum(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
                            bounds=None):

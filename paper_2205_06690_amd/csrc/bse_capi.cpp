@@ -831,6 +831,62 @@ void apply_a_mixed(bse_system* s, int n_vec, const double* f, double* af) {
   HIPC(hipStreamSynchronize(s->stream));
 }
 
+// The paper's spectrum algorithm (Eqs. 6-8): the Chebyshev recursion with A
+// applied matrix-free in the mixed representation, from the dipole states
+// f0_j = Q (r_axis - centre) phi_j of each axis; residues by the doubling
+// identities, the spectrum as in chebyshev_spectrum.
+void chebyshev_mixed(bse_system* s, int n_mom, double e_min, double e_max, int n_w,
+                     const double* w_grid, double sig, double* sigma, double* residues) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_chebyshev_mixed: call bse_build_A first");
+  if (n_mom < 2 || n_mom % 2 != 0 || !(e_min < e_max) || n_w < 0 ||
+      (n_w > 0 && (!w_grid || !sigma || !(sig > 0))) || (n_w == 0 && !residues))
+    fail(BSE_ERR_ARG, "bse_chebyshev_mixed: bad arguments");
+  if ((size_t)s->a_no * s->cfg.n_occ * sizeof(double) > 64 * 1024)
+    fail(BSE_ERR_ARG, "bse_chebyshev_mixed: n_o * n_occ above 8192");
+  hipStream_t st = s->stream;
+  const int n_o = s->a_no, S = s->cfg.n_occ;
+  const size_t ng = s->ng, len = (size_t)n_o * ng;
+  const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
+  const int K = n_mom / 2, nblk = mixed_cheb_blocks(), M = 2 * n_mom;
+  DBuf fv, af, part, mu, D, wd, sd, cq, pq;
+  fv.alloc(sizeof(double) * 9 * len);               // [pol][3 rotating vectors][n_o][ng]
+  af.alloc(sizeof(double) * len);
+  part.alloc(sizeof(double) * 6 * (size_t)K * nblk);
+  mu.alloc(sizeof(double) * 3 * (size_t)n_mom);
+  D.alloc(sizeof(double) * 3 * (size_t)M);
+  cq.alloc(sizeof(double) * (size_t)n_o * S);
+  pq.alloc(sizeof(double) * gemm_part_elems(n_o, S, ng));
+  if (n_w > 0) {
+    wd.alloc(sizeof(double) * n_w);
+    sd.alloc(sizeof(double) * n_w);
+    HIPC(hipMemcpyAsync(wd.p, w_grid, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
+  }
+  double* buf = fv.as<double>();
+  auto vec = [&](int p, int k) { return buf + ((size_t)p * 3 + (size_t)(k % 3)) * len; };
+  const double* phv = s->phi64.as<double>() + (size_t)(S - n_o) * ng;
+  for (int p = 0; p < 3; ++p) {
+    double* f0 = vec(p, 0);
+    HIPC(launch_mixed_dipole(phv, n_o, s->n, s->cfg.h, p, f0, st));
+    HIPC(launch_gemm_f64(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st));
+    HIPC(launch_project_out(f0, n_o, s->phi64.as<double>(), S, cq.as<double>(), ng, st));
+  }
+  for (int k = 0; k < K; ++k)
+    for (int p = 0; p < 3; ++p) {
+      const double* fc = vec(p, k);
+      apply_a_mixed_device(s, fc, af.as<double>());
+      HIPC(launch_mixed_cheb_update(af.as<double>(), fc, vec(p, k + 2), vec(p, k + 1), len, a, b,
+                                    k == 0 ? 1 : 0, s->dv, p, part.as<double>() + (size_t)k * nblk * 6,
+                                    st));
+    }
+  HIPC(launch_cheb_spectrum(part.as<double>(), K, nblk, mu.as<double>(), M, D.as<double>(), a, b,
+                            wd.as<double>(), n_w, sig, sd.as<double>(), st));
+  if (n_w > 0) HIPC(hipMemcpyAsync(sigma, sd.p, sizeof(double) * n_w, hipMemcpyDeviceToHost, st));
+  if (residues)
+    HIPC(hipMemcpyAsync(residues, mu.p, sizeof(double) * 3 * (size_t)n_mom, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+}
+
 // Chebyshev absorption (Eqs. 7-8) on the device copy of A: the residues of
 // the three dipole start vectors by the recursion in A~ = (A - b)/a, then the
 // broadened delta through its Chebyshev coefficients (Gauss-Chebyshev
@@ -1417,6 +1473,14 @@ bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip
 bse_status bse_apply_A_mixed(bse_system* s, int32_t n_vec, const double* f, double* af) {
   API_BEGIN
   apply_a_mixed(s, n_vec, f, af);
+  API_END
+}
+
+bse_status bse_chebyshev_mixed(bse_system* s, int32_t n_mom, double e_min, double e_max, int32_t n_w,
+                               const double* w_grid, double sigma_broad, double* sigma,
+                               double* residues) {
+  API_BEGIN
+  chebyshev_mixed(s, n_mom, e_min, e_max, n_w, w_grid, sigma_broad, sigma, residues);
   API_END
 }
 

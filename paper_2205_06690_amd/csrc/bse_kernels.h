@@ -40,6 +40,14 @@ hipError_t launch_mixed_combine(const double* f, const double* tf, const double*
                                 double* out, hipStream_t st);
 hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
                               size_t ng, hipStream_t st);
+// mixed-representation Chebyshev: one step of polarisation p over len values
+// with partials part[mixed_cheb_blocks()][6]; dipole start f_j = (r_axis - c) phi_j
+int mixed_cheb_blocks();
+hipError_t launch_mixed_cheb_update(const double* af, const double* fc, const double* fp, double* fn,
+                                    size_t len, double a, double b, int first, double dv, int p,
+                                    double* part, hipStream_t st);
+hipError_t launch_mixed_dipole(const double* phv, int n_o, int n, double h, int axis, double* f,
+                               hipStream_t st);
 // Chebyshev spectrum (Eqs. 7-8): Gershgorin rows lohi[2][n]; one recursion
 // step on [3][n] vectors with per-block partial residues part[cheb_blocks(n)][6];
 // residues mu[3][2K], node weights D[3][M] and sigma[n_w] from the partials

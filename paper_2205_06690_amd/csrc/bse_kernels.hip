@@ -511,6 +511,54 @@ __global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, i
   }
 }
 
+// mixed-representation Chebyshev step for polarisation p: fn = 2 (af - b fc)/a
+// - fp (first: (af - b fc)/a) over len values, with the block partials
+// dv <fc|fc> and dv <fn|fc> into part[blk][p] and part[blk][3 + p]
+__global__ void __launch_bounds__(256) k_mixed_cheb_update(const double* __restrict__ af,
+                                                           const double* __restrict__ fc,
+                                                           const double* __restrict__ fp,
+                                                           double* __restrict__ fn, size_t len,
+                                                           double ia, double b, int first, double dv,
+                                                           int p, double* __restrict__ part) {
+  double c0 = 0, c1 = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (size_t)gridDim.x * 256) {
+    const double cur = fc[i];
+    const double t = (af[i] - b * cur) * ia;
+    const double nx = first ? t : 2.0 * t - fp[i];
+    fn[i] = nx;
+    c0 += cur * cur;
+    c1 += nx * cur;
+  }
+  __shared__ double r0[256], r1[256];
+  r0[threadIdx.x] = c0;
+  r1[threadIdx.x] = c1;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[(size_t)blockIdx.x * 6 + p] = r0[0] * dv;
+    part[(size_t)blockIdx.x * 6 + 3 + p] = r1[0] * dv;
+  }
+}
+
+// f0_j(r) = (r_axis - centre) phi_j(r), before the occupied-space projection
+__global__ void k_mixed_dipole(const double* __restrict__ phv, int n_o, int n, double h, int axis,
+                               double* __restrict__ f) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const size_t ng = (size_t)n * n * n;
+  if (r >= ng) return;
+  const int ix = (int)(r / ((size_t)n * n)), iy = (int)((r / n) % n), iz = (int)(r % n);
+  const int c = axis == 0 ? ix : (axis == 1 ? iy : iz);
+  const double x = c * h - 0.5 * n * h;
+  f[(size_t)j * ng + r] = x * phv[(size_t)j * ng + r];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -622,6 +670,21 @@ hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, co
   if (sm > 64 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_project_out, dim3((unsigned)((ng + 255) / 256)), dim3(256), sm, st, out, n_o, phi,
                      S, C, ng);
+  return hipGetLastError();
+}
+int mixed_cheb_blocks() { return 256; }
+hipError_t launch_mixed_cheb_update(const double* af, const double* fc, const double* fp, double* fn,
+                                    size_t len, double a, double b, int first, double dv, int p,
+                                    double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_cheb_update, dim3(mixed_cheb_blocks()), dim3(256), 0, st, af, fc, fp, fn,
+                     len, 1.0 / a, b, first, dv, p, part);
+  return hipGetLastError();
+}
+hipError_t launch_mixed_dipole(const double* phv, int n_o, int n, double h, int axis, double* f,
+                               hipStream_t st) {
+  const size_t ng = (size_t)n * n * n;
+  hipLaunchKernelGGL(k_mixed_dipole, dim3((unsigned)((ng + 255) / 256), n_o), dim3(256), 0, st, phv, n_o,
+                     n, h, axis, f);
   return hipGetLastError();
 }
 hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t st) {

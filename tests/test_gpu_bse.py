@@ -134,3 +134,52 @@ def test_tiny24_apply_a_mixed(precision, tol):
     with pytest.raises(bse.BseError) as e:
         s2.apply_a_mixed(f.reshape(spec.n_o, -1))
     assert e.value.code == bse.BSE_ERR_STATE
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
+def test_tiny24_chebyshev_mixed(precision, tol):
+    """The paper's algorithm: Chebyshev residues with A applied matrix-free
+    in the mixed representation, against the oracle's operator recursion
+    from the same dipole start vectors and interval (the oracle's extreme
+    eigenvalues of Q A-bar Q, widened by 2 %).  Mixed precision: the
+    library's W moves A f by ~3e-9 relative, which the recursion carries
+    about linearly in n."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    spec, sysd = system("tiny24")
+    pairs = inputs.ij_pairs(spec)
+    w, _ = oracle_w(spec, sysd, pairs)
+    grid = Grid(spec.shape, spec.h)
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    v0 = spec.n_occ - spec.n_o
+    wf = obse.w_stack(spec.n_o, [(i - v0, j - v0) for i, j in pairs], w)
+    phio, epsv = phi[:spec.n_occ], sysd["eps"][v0:spec.n_occ]
+    shp = (spec.n_o,) + spec.shape
+    P = phio.reshape(spec.n_occ, -1)
+
+    def q(x):
+        x = x.reshape(spec.n_o, -1)
+        return x - ((x @ P.T) * grid.dv) @ P
+
+    def op(f):
+        return obse.apply_a_mixed(grid, sysd["v_ext"], phio, epsv, wf, f)
+
+    lin = LinearOperator((spec.n_o * spec.ng,) * 2, dtype=np.float64,
+                         matvec=lambda x: op(q(x).reshape(shp)).reshape(-1))
+    lmax = eigsh(lin, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+    lmin = eigsh(lin, k=1, which="SA", return_eigenvectors=False, tol=1e-6)[0]
+    lo, hi = lmin - 0.02 * (lmax - lmin), lmax + 0.02 * (lmax - lmin)
+    a, b = obse.chebyshev_scale(lo, hi)
+    n_mom = 200
+    f0 = obse.mixed_dipole_start(grid, phio, spec.n_o)
+    R_o = obse.chebyshev_residues_op(op, f0, n_mom, a, b, lambda u, v: float(np.sum(u * v)) * grid.dv)
+    wg = np.linspace(lo, hi, 400)
+    sig = 0.05 * (hi - lo)
+    sg_o = obse.chebyshev_absorption(R_o, wg, a, b, sig)
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    s.build_a(spec.n_o, spec.n_c)
+    sg, R = s.chebyshev_mixed(n_mom, (lo, hi), wg, sig)
+    er = np.abs(R - R_o.T).max() / np.abs(R_o[0]).max()
+    es = np.abs(sg - sg_o).max() / np.abs(sg_o).max()
+    say(f"chebyshev mixed prec {precision}: interval ({lo:.3f}, {hi:.3f}) Ha, residues {er:.2e}, "
+        f"spectrum {es:.2e}")
+    assert er < tol and es < tol
