@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--train-seconds", type=float, default=420.0)
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev)")
+    ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev, mixed)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -363,6 +363,19 @@ def main():
         cheb = {"n_residues": n_mom, "ms": round((time.perf_counter() - tc0) * 1e3, 3),
                 "interval_Ha": [round(float(bo[0]), 6), round(float(bo[1]), 6)], "n_omega": 2000}
 
+    # the matrix-free A f of the mixed representation (Eq. 6), FP64, timed
+    # outside the step: the inner operation of the paper's spectrum loop
+    mixed = None
+    if "mixed" not in args.skip:
+        fm = np.random.default_rng(0).standard_normal((4, spec.n_o, spec.ng))
+        S.apply_a_mixed(fm[:1])
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        S.apply_a_mixed(fm)
+        torch.cuda.synchronize()
+        mixed = {"ms_per_application": round((time.perf_counter() - tm0) * 1e3 / 4, 3),
+                 "fields": spec.n_o, "note": "includes the host<->device copy of f and A f"}
+
     # the grid contractions (Eq. 1) on the BF16 matrix cores: issued flops of
     # the three-term split over the measured launch times
     contraction = None
@@ -401,6 +414,8 @@ def main():
         out["roofline_contraction"] = contraction
     if cheb is not None:
         out["chebyshev_spectrum"] = cheb
+    if mixed is not None:
+        out["apply_a_mixed"] = mixed
 
     if not args.no_cpu_baseline:
         pair = tuple(int(x) for x in pairs[-1])
