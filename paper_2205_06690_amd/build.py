@@ -21,8 +21,8 @@ OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libbse.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["prop_kernels.hip", "clean_mfma.hip", "bse_kernels.hip", "fno_kernels.hip", "bse_capi.cpp",
-           "fno.cpp"]
+SOURCES = ["prop_kernels.hip", "clean_mfma.hip", "contract_mfma.hip", "bse_kernels.hip",
+           "fno_kernels.hip", "bse_capi.cpp", "fno.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -17,6 +17,7 @@
 #include "bse_kernels.h"
 #include "prop_kernels.h"
 #include "clean_mfma.h"
+#include "contract_mfma.h"
 
 using namespace bse;
 
@@ -508,11 +509,11 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
   DBuf pq;
   pq.alloc(sizeof(int) * 2 * (size_t)std::max(std::max(n_ia, n_ab), n_ij));
   const bool fp64 = s->cfg.precision == BSE_FP64;
-  DBuf X, Dm, part, rho64, v64, rho32, v32;
+  DBuf X, Dm, part, rho64, v64, cpart;
   X.alloc(sizeof(double) * (size_t)n_ia * n_ia);
   Dm.alloc(sizeof(double) * (size_t)n_ab * n_ij);
   const size_t pe = std::max(gemm_part_elems(n_ia, n_ia, ng), gemm_part_elems(n_ab, n_ij, ng));
-  part.alloc(pe * (fp64 ? sizeof(double) : sizeof(float)));
+  if (fp64) part.alloc(pe * sizeof(double));
   // 2. exchange (ia|jb): Coulomb potentials of rho_jb in FP64, then the grid GEMM
   HIPC(hipMemcpyAsync(pq.p, pia.data(), sizeof(int) * 2 * n_ia, hipMemcpyHostToDevice, st));
   rho64.alloc(sizeof(double) * ng * n_ia);
@@ -528,14 +529,20 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     HIPC(launch_gemm_f64(rho64.as<double>(), n_ia, v64.as<double>(), n_ia, ng, s->dv,
                          part.as<double>(), X.as<double>(), st));
   } else {
-    rho32.alloc(sizeof(float) * ng * n_ia);
-    v32.alloc(sizeof(float) * ng * n_ia);
-    HIPC(launch_to_real<float>(rho64.as<double>(), ng * n_ia, rho32.as<float>(), st));
-    HIPC(launch_to_real<float>(v64.as<double>(), ng * n_ia, v32.as<float>(), st));
+    // operands split once from FP64 into bf16 pairs for the matrix cores
+    DBuf rh, rl, vh, vl;
+    rh.alloc(sizeof(unsigned short) * ng * n_ia);
+    rl.alloc(sizeof(unsigned short) * ng * n_ia);
+    vh.alloc(sizeof(unsigned short) * ng * n_ia);
+    vl.alloc(sizeof(unsigned short) * ng * n_ia);
+    HIPC(launch_split64(rho64.as<double>(), ng * n_ia, rh.as<unsigned short>(), rl.as<unsigned short>(), st));
+    HIPC(launch_split64(v64.as<double>(), ng * n_ia, vh.as<unsigned short>(), vl.as<unsigned short>(), st));
+    cpart.alloc(sizeof(float) * contract_part_floats(n_ia, n_ia, ng));
     auto* t = s->timer.begin("gemm_exchange");
-    HIPC(launch_gemm_bf16x3(rho32.as<float>(), n_ia, v32.as<float>(), n_ia, ng, s->dv,
-                            part.as<float>(), X.as<double>(), st));
+    HIPC(launch_contract_x3(rh.as<unsigned short>(), rl.as<unsigned short>(), n_ia, vh.as<unsigned short>(),
+                            vl.as<unsigned short>(), n_ia, ng, s->dv, cpart.as<float>(), X.as<double>(), st));
     s->timer.end(t);
+    HIPC(hipStreamSynchronize(st));   // the split operands are freed at the end of this scope
   }
   // 3. direct (ab|W|ij) over a <= b and i <= j
   HIPC(hipStreamSynchronize(st));
@@ -548,14 +555,20 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
                          part.as<double>(), Dm.as<double>(), st));
     HIPC(hipStreamSynchronize(st));
   } else {
-    DBuf rab, w32;
-    rab.alloc(sizeof(float) * ng * n_ab);
-    w32.alloc(sizeof(float) * ng * n_ij);
-    HIPC(launch_products<float>(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, rab.as<float>(), st));
-    HIPC(launch_to_real<float>(s->wij.as<double>(), ng * n_ij, w32.as<float>(), st));
+    rho64.release();
+    v64.release();
+    DBuf abh, abl, wh, wl;
+    abh.alloc(sizeof(unsigned short) * ng * n_ab);
+    abl.alloc(sizeof(unsigned short) * ng * n_ab);
+    wh.alloc(sizeof(unsigned short) * ng * n_ij);
+    wl.alloc(sizeof(unsigned short) * ng * n_ij);
+    HIPC(launch_products_split(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, abh.as<unsigned short>(),
+                               abl.as<unsigned short>(), st));
+    HIPC(launch_split64(s->wij.as<double>(), ng * n_ij, wh.as<unsigned short>(), wl.as<unsigned short>(), st));
+    cpart.alloc(sizeof(float) * contract_part_floats(n_ab, n_ij, ng));
     auto* t = s->timer.begin("gemm_direct");
-    HIPC(launch_gemm_bf16x3(rab.as<float>(), n_ab, w32.as<float>(), n_ij, ng, s->dv,
-                            part.as<float>(), Dm.as<double>(), st));
+    HIPC(launch_contract_x3(abh.as<unsigned short>(), abl.as<unsigned short>(), n_ab, wh.as<unsigned short>(),
+                            wl.as<unsigned short>(), n_ij, ng, s->dv, cpart.as<float>(), Dm.as<double>(), st));
     s->timer.end(t);
     HIPC(hipStreamSynchronize(st));
   }

@@ -24,33 +24,13 @@
 #include <hip/hip_runtime.h>
 
 #include "clean_mfma.h"
+#include "mfma_tiles.h"
 
 #include <algorithm>
 
 namespace bse {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-constexpr int XT = 128;       // tile rows and columns
-constexpr int XK = 32;        // K per stage: one 16x16x32 step
-constexpr int XKP = XK + 8;   // padded LDS row in bf16 (80 bytes, 16-byte aligned)
-
 int clean_sp(int S) { return (S + XK - 1) / XK * XK; }
-
-__device__ __forceinline__ void split_hl(float x, unsigned short& h, unsigned short& l) {
-  const __bf16 bh = (__bf16)x;
-  const __bf16 bl = (__bf16)(x - (float)bh);
-  h = __builtin_bit_cast(unsigned short, bh);
-  l = __builtin_bit_cast(unsigned short, bl);
-}
-
-// Workgroup ids are dealt round-robin to the 8 XCDs; renumber them so that
-// each XCD works through a contiguous range of tiles (nb is a multiple of 8)
-// and tiles that share an operand tile share that XCD's L2.
-__device__ __forceinline__ unsigned xcd_tile(unsigned id, unsigned nb) {
-  return (id & 7u) * (nb >> 3) + (id >> 3);
-}
 
 __device__ __forceinline__ float2 cm(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -67,34 +47,6 @@ __device__ __forceinline__ float2 finish_mid(const MidArgs& m, int f, size_t r, 
   return finish1(v, m.H[(size_t)l * m.ng + r], m.u[(size_t)b * m.ng + r], m.ph[r], m.half_dt);
 }
 
-// One stage of MFMA work on the staged 128 x 32 tiles: wave (wm, wn) owns a
-// 64 x 64 block of 4 x 4 result tiles.
-__device__ __forceinline__ void mma_stage(const __bf16 (*Ah)[XKP], const __bf16 (*Al)[XKP],
-                                          const __bf16 (*Bh)[XKP], const __bf16 (*Bl)[XKP],
-                                          int lane, int wm, int wn, f4 (&acc)[4][4]) {
-  const int kk = 8 * (lane >> 4);
-  bf8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = wm * 64 + i * 16 + (lane & 15);
-    ah[i] = *reinterpret_cast<const bf8*>(&Ah[row][kk]);
-    al[i] = *reinterpret_cast<const bf8*>(&Al[row][kk]);
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int col = wn * 64 + j * 16 + (lane & 15);
-    bh[j] = *reinterpret_cast<const bf8*>(&Bh[col][kk]);
-    bl[j] = *reinterpret_cast<const bf8*>(&Bl[col][kk]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-    }
-}
 
 // phi [S][ng] FP32 -> hi/lo in [S][ng] and, zero-padded to Sp states, [ng][Sp]
 __global__ void k_phi_split(const float* __restrict__ phi, int S, int Sp, size_t ng,
@@ -234,7 +186,7 @@ __global__ void __launch_bounds__(256) k_coef_x3(const float2* __restrict__ d, i
     store();
     __syncthreads();
     if (kb + XK < k1) load(kb + XK);
-    mma_stage(Ah, Al, Bh, Bl, lane, wm, wn, acc);
+    mma_stage<XKP>(Ah, Al, Bh, Bl, lane, wm, wn, acc);
   }
   float* out = part + (size_t)kc * R * S;
 #pragma unroll
@@ -376,7 +328,7 @@ __global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F
     store();
     __syncthreads();
     if (kb + XK < Sp) load(kb + XK);
-    mma_stage(Ah, Al, Bh, Bl, lane, wm, wn, acc);
+    mma_stage<XKP>(Ah, Al, Bh, Bl, lane, wm, wn, acc);
   }
   // epilogue: lane holds rows 4q..4q+3 = fields 2q, 2q+1 (re, im) at one point
 #pragma unroll

@@ -1,0 +1,202 @@
+// Grid contractions of the Tamm-Dancoff matrix (Eq. 1) on the gfx950 matrix
+// cores: C[m][n] = scale sum_r A[m][r] B[n][r] over the grid points r, with
+// both operands split once from FP64 into bf16 pairs x = hi + lo and the
+// three-term product a_hi b_hi + a_hi b_lo + a_lo b_hi.
+//
+//   exchange (ia|jb): A = rho_ia = phi_i phi_a, B = v[rho_jb]
+//   direct (ab|W|ij): A = phi_a phi_b,          B = W_ij
+//
+// Tiles of 128 x 128 outputs over chunks of the grid (split K), staged in
+// LDS 64 points at a time with the next stage's loads in flight; FP32 sums
+// per tile and chunk, FP64 sums over chunks.
+#include <hip/hip_runtime.h>
+
+#include "contract_mfma.h"
+#include "mfma_tiles.h"
+
+#include <algorithm>
+
+namespace bse {
+
+// hi/lo of x [n] (FP64)
+__global__ void k_split64(const double* __restrict__ x, size_t n, unsigned short* __restrict__ h,
+                          unsigned short* __restrict__ l) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    split_hl64(x[i], h[i], l[i]);
+}
+
+// hi/lo of the products phi_p phi_q (FP64) for the K index pairs pq[K][2]
+__global__ void k_products_split(const double* __restrict__ phi, const int* __restrict__ pq, int K,
+                                 size_t ng, unsigned short* __restrict__ h,
+                                 unsigned short* __restrict__ l) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= ng || k >= K) return;
+  const int p = pq[2 * k], q = pq[2 * k + 1];
+  split_hl64(phi[(size_t)p * ng + r] * phi[(size_t)q * ng + r], h[(size_t)k * ng + r],
+             l[(size_t)k * ng + r]);
+}
+
+// part[kc][m][n] = sum over chunk kc of A[m][r] B[n][r], staged KS grid
+// points at a time.  Tile order (with remap): column tile fastest, then row
+// tile, then chunk, renumbered so that each XCD works through a contiguous
+// range and the tiles of one chunk share their row and column panels in L2.
+template <int KS>
+__global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __restrict__ ah,
+                                                     const unsigned short* __restrict__ al, int M,
+                                                     const unsigned short* __restrict__ bh,
+                                                     const unsigned short* __restrict__ bl, int N,
+                                                     size_t K, size_t chunk, int ntm, int ntn,
+                                                     unsigned ntile, int remap,
+                                                     float* __restrict__ part) {
+  constexpr int P = KS + 8;            // padded LDS row (bf16), a multiple of 8
+  constexpr int NV = KS / 16;          // uint4 per thread and array
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_c[];
+  __bf16 (*Ah)[P] = reinterpret_cast<__bf16 (*)[P]>(smem_c);
+  __bf16 (*Al)[P] = Ah + XT;
+  __bf16 (*Bh)[P] = Al + XT;
+  __bf16 (*Bl)[P] = Bh + XT;
+  const unsigned t = remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  if (t >= ntile) return;
+  const int tn = (int)(t % ntn), tm = (int)((t / ntn) % ntm), kc = (int)(t / ((unsigned)ntn * ntm));
+  const int m0 = tm * XT, n0 = tn * XT;
+  const size_t k0 = (size_t)kc * chunk, k1 = min(K, k0 + chunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int sb = tid >> 1, hb = (tid & 1) * (KS / 2);   // row sb, K values hb .. hb + KS/2 - 1
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  uint4 rah[NV], ral[NV], rbh[NV], rbl[NV];
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  auto load = [&](size_t kb) {
+    const int m = m0 + sb, n = n0 + sb;
+    if (m < M) {
+      const uint4* qh = reinterpret_cast<const uint4*>(ah + (size_t)m * K + kb + hb);
+      const uint4* ql = reinterpret_cast<const uint4*>(al + (size_t)m * K + kb + hb);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        rah[q] = qh[q];
+        ral[q] = ql[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) rah[q] = ral[q] = z4;
+    }
+    if (n < N) {
+      const uint4* qh = reinterpret_cast<const uint4*>(bh + (size_t)n * K + kb + hb);
+      const uint4* ql = reinterpret_cast<const uint4*>(bl + (size_t)n * K + kb + hb);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        rbh[q] = qh[q];
+        rbl[q] = ql[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) rbh[q] = rbl[q] = z4;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      *reinterpret_cast<uint4*>(&Ah[sb][hb + 8 * q]) = rah[q];
+      *reinterpret_cast<uint4*>(&Al[sb][hb + 8 * q]) = ral[q];
+      *reinterpret_cast<uint4*>(&Bh[sb][hb + 8 * q]) = rbh[q];
+      *reinterpret_cast<uint4*>(&Bl[sb][hb + 8 * q]) = rbl[q];
+    }
+  };
+  load(k0);
+  for (size_t kb = k0; kb < k1; kb += KS) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kb + KS < k1) load(kb + KS);
+#pragma unroll
+    for (int ko = 0; ko < KS; ko += XK) mma_stage<P>(Ah, Al, Bh, Bl, lane, wm, wn, acc, ko);
+  }
+  float* out = part + (size_t)kc * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (m < M && n < N) out[(size_t)m * N + n] = acc[i][j][v];
+      }
+}
+
+// C[m][n] = scale sum_kc part[kc][m][n] in FP64
+__global__ void k_contract_reduce(const float* __restrict__ part, int nchunk, size_t MN, double scale,
+                                  double* __restrict__ C) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  double acc = 0;
+  for (int k = 0; k < nchunk; ++k) acc += part[(size_t)k * MN + i];
+  C[i] = acc * scale;
+}
+
+static unsigned round8u(unsigned n) { return (n + 7u) & ~7u; }
+
+template <int KS> constexpr size_t contract_lds() { return 4ull * XT * (KS + 8) * sizeof(unsigned short); }
+
+// Stages of 64 points; chunks of 2048 points keep the row and column panels
+// of the tiles running together small enough to be served from cache (at
+// M = N = 800, K = 112^3: 9.5 ms with 33472-point chunks and 32-point
+// stages, 7.1 ms with 2048 and 64).
+constexpr int CK_STAGE = 64;
+constexpr size_t CK_CHUNK = 2048;
+
+void contract_plan(int M, int N, size_t K, size_t* chunk, int* nchunk) {
+  (void)M;
+  (void)N;
+  const size_t c = std::min(K, CK_CHUNK);
+  *chunk = c;
+  *nchunk = (int)((K + c - 1) / c);
+}
+
+size_t contract_part_floats(int M, int N, size_t K) {
+  size_t c;
+  int nc;
+  contract_plan(M, N, K, &c, &nc);
+  return (size_t)nc * M * N;
+}
+
+hipError_t launch_split64(const double* x, size_t n, unsigned short* h, unsigned short* l,
+                          hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split64, dim3(blocks), dim3(256), 0, st, x, n, h, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_products_split(const double* phi, const int* pq, int K, size_t ng, unsigned short* h,
+                                 unsigned short* l, hipStream_t st) {
+  hipLaunchKernelGGL(k_products_split, dim3((unsigned)((ng + 255) / 256), K), dim3(256), 0, st, phi, pq,
+                     K, ng, h, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_x3(const unsigned short* ah, const unsigned short* al, int M,
+                              const unsigned short* bh, const unsigned short* bl, int N, size_t K,
+                              double scale, float* part, double* C, hipStream_t st) {
+  if (M <= 0 || N <= 0 || K % CK_STAGE != 0) return hipErrorInvalidValue;
+  size_t chunk;
+  int nchunk;
+  contract_plan(M, N, K, &chunk, &nchunk);
+  const int ntm = (M + XT - 1) / XT, ntn = (N + XT - 1) / XT;
+  const unsigned ntile = (unsigned)ntm * ntn * nchunk;
+  (void)hipFuncSetAttribute((const void*)k_contract_x3<CK_STAGE>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)contract_lds<CK_STAGE>());
+  hipLaunchKernelGGL(k_contract_x3<CK_STAGE>, dim3(round8u(ntile)), dim3(256), contract_lds<CK_STAGE>(), st,
+                     ah, al, M, bh, bl, N, K, chunk, ntm, ntn, ntile, 1, part);
+  const size_t MN = (size_t)M * N;
+  hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, part,
+                     nchunk, MN, scale, C);
+  return hipGetLastError();
+}
+
+}  // namespace bse
