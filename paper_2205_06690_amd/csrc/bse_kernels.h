@@ -12,8 +12,6 @@ hipError_t launch_products(const double* phi, const int* pq, int K, size_t ng, T
 size_t gemm_chunk(int M, int N, size_t K);
 size_t gemm_part_elems(int M, int N, size_t K);
 // C[m][n] = scale * sum_r A[m][r] B[n][r]
-hipError_t launch_gemm_bf16x3(const float* A, int M, const float* B, int N, size_t K, double scale,
-                              float* part, double* C, hipStream_t st);
 hipError_t launch_gemm_f64(const double* A, int M, const double* B, int N, size_t K, double scale,
                            double* part, double* C, hipStream_t st);
 hipError_t launch_assemble_a(const double* X, const double* D, int no, int nc, int nij,

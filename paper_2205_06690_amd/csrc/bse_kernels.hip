@@ -1,11 +1,11 @@
-// Tamm-Dancoff matrix (Eq. 1), dipoles and Lanczos helpers for gfx950.
+// Tamm-Dancoff matrix (Eq. 1) assembly, dipoles, the FP64 contractions,
+// the Lanczos and Chebyshev spectra (Eqs. 7-8), the matrix-free A f of the
+// mixed representation (Eq. 6) and the surrogate's features, for gfx950.
 //
 // The exchange 2(ia|jb) and direct (ab|W|ij) terms are grid contractions
 // C[m][n] = h^3 sum_r A_m(r) B_n(r) with K = n_g in the thousands to
-// millions and small M, N: split-K GEMMs.  Mixed precision runs them on the
-// BF16 matrix cores with a three-term split (a = a_hi + a_lo, b = b_hi + b_lo,
-// a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation per K chunk,
-// FP64 sum over chunks); FP64 mode uses FP64 FMA.
+// millions and small M, N: split-K GEMMs.  FP64 mode runs them here with
+// FP64 FMA; mixed precision on the BF16 matrix cores (contract_mfma.hip).
 #include <hip/hip_runtime.h>
 
 #include "bse_kernels.h"
@@ -14,8 +14,6 @@
 
 namespace bse {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // flags[b] = 1 if row b of w has a non-finite value
 __global__ void k_finite_check(const double* __restrict__ w, size_t ng, int* __restrict__ flags) {
@@ -47,108 +45,8 @@ __global__ void k_products(const double* __restrict__ phi, const int* __restrict
   out[(size_t)k * ng + r] = (T)(phi[(size_t)p * ng + r] * phi[(size_t)q * ng + r]);
 }
 
-// ---------------------------------------------------------------------------
-// split-K NT GEMM, BF16x3 on the matrix cores:
-//   part[kc][m][n] = sum_{r in chunk kc} A[m][r] B[n][r]   (A, B FP32 row-major)
-// v_mfma_f32_16x16x32_bf16: lane l supplies row (l%16) of A and column (l%16)
-// of B with the 8 k-values 8(l/16)..8(l/16)+7; result D[4(l/16)+v][l%16].
-// ---------------------------------------------------------------------------
-constexpr int G_BM = 64, G_BN = 64, G_BK = 64, G_KP = 8;  // k padding (bf16)
-
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
-__global__ void __launch_bounds__(256) k_gemm_bf16x3(const float* __restrict__ A, int M,
-                                                     const float* __restrict__ B, int N,
-                                                     size_t K, size_t chunk,
-                                                     float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[G_BM][G_BK + G_KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[G_BM][G_BK + G_KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[G_BN][G_BK + G_KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[G_BN][G_BK + G_KP];
-  const int m0 = blockIdx.x * G_BM, n0 = blockIdx.y * G_BN, kc = blockIdx.z;
-  const size_t k0 = (size_t)kc * chunk, k1 = min(K, k0 + chunk);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  f4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  constexpr int NL = G_BM * G_BK / 256;  // 16 floats per thread per operand
-  float ra[NL], rb[NL];
-  auto load = [&](size_t kb) {
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int e = tid + i * 256;
-      const int row = e / G_BK, kk = e % G_BK;
-      const size_t k = kb + kk;
-      ra[i] = (m0 + row < M && k < k1) ? A[(size_t)(m0 + row) * K + k] : 0.f;
-      rb[i] = (n0 + row < N && k < k1) ? B[(size_t)(n0 + row) * K + k] : 0.f;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int e = tid + i * 256;
-      const int row = e / G_BK, kk = e % G_BK;
-      __bf16 h, l;
-      split_bf16(ra[i], h, l);
-      Ah[row][kk] = h;
-      Al[row][kk] = l;
-      split_bf16(rb[i], h, l);
-      Bh[row][kk] = h;
-      Bl[row][kk] = l;
-    }
-  };
-  load(k0);
-  for (size_t kb = k0; kb < k1; kb += G_BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (kb + G_BK < k1) load(kb + G_BK);
-#pragma unroll
-    for (int ks = 0; ks < G_BK / 32; ++ks) {
-      const int kk = ks * 32 + 8 * (lane >> 4);
-      bf8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = wm * 32 + i * 16 + (lane & 15);
-        ah[i] = *reinterpret_cast<const bf8*>(&Ah[row][kk]);
-        al[i] = *reinterpret_cast<const bf8*>(&Al[row][kk]);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = wn * 32 + j * 16 + (lane & 15);
-        bh[j] = *reinterpret_cast<const bf8*>(&Bh[col][kk]);
-        bl[j] = *reinterpret_cast<const bf8*>(&Bl[col][kk]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    }
-  }
-  float* out = part + (size_t)kc * M * N;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m < M && n < N) out[(size_t)m * N + n] = acc[i][j][v];
-      }
-}
-
 // FP64 split-K NT GEMM (vector FMA), 64x64 tile, 4x4 per thread
+constexpr int G_BM = 64, G_BN = 64;
 __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int M,
                                                   const double* __restrict__ B, int N, size_t K,
                                                   size_t chunk, double* __restrict__ part) {
@@ -595,7 +493,6 @@ hipError_t launch_products(const double* phi, const int* pq, int K, size_t ng, T
                      pq, K, ng, out);
   return hipGetLastError();
 }
-template hipError_t launch_products<float>(const double*, const int*, int, size_t, float*, hipStream_t);
 template hipError_t launch_products<double>(const double*, const int*, int, size_t, double*, hipStream_t);
 
 size_t gemm_chunk(int M, int N, size_t K) {
@@ -609,16 +506,6 @@ size_t gemm_part_elems(int M, int N, size_t K) {
   return ((K + chunk - 1) / chunk) * (size_t)M * N;
 }
 
-hipError_t launch_gemm_bf16x3(const float* A, int M, const float* B, int N, size_t K, double scale,
-                              float* part, double* C, hipStream_t st) {
-  const size_t chunk = gemm_chunk(M, N, K);
-  const int nchunk = (int)((K + chunk - 1) / chunk);
-  dim3 g((M + G_BM - 1) / G_BM, (N + G_BN - 1) / G_BN, nchunk);
-  hipLaunchKernelGGL(k_gemm_bf16x3, g, dim3(256), 0, st, A, M, B, N, K, chunk, part);
-  hipLaunchKernelGGL((k_part_sum<float>), dim3((M * N + 255) / 256), dim3(256), 0, st, part, nchunk,
-                     M * N, scale, C);
-  return hipGetLastError();
-}
 
 hipError_t launch_gemm_f64(const double* A, int M, const double* B, int N, size_t K, double scale,
                            double* part, double* C, hipStream_t st) {
