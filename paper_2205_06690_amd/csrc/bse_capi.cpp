@@ -248,7 +248,7 @@ void ensure_batch(bse_system* s, int B) {
   s->coef.alloc(sizeof(cplx<double>) * (size_t)F * (S + 1));
   if (sizeof(T) == 4) {
     s->part32.alloc(sizeof(float) * clean_scratch_floats(F, L, S, ng));
-    s->gpart.alloc(sizeof(cplx<double>) * edot_part_entries(F, ng));
+    s->gpart.alloc(sizeof(cplx<double>) * edot_part_entries(F, L, S, ng));
   }
   s->coefE.alloc(sizeof(cplx<double>) * (size_t)L * (S + 1));
   s->pq_d.alloc(sizeof(int) * 2 * B);

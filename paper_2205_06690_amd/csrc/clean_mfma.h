@@ -5,8 +5,10 @@
 #include <cstddef>
 
 namespace bse {
-constexpr int CLEAN_CHUNK_D = 4096;   // points per split-K chunk, perturbed set
 constexpr int CLEAN_CHUNK_E = 1024;   // points per split-K chunk, the L unperturbed orbitals
+// points per split-K chunk of the perturbed set's coefficient GEMM: about
+// 2048 blocks of 128 x 128 tiles whatever the batch and grid
+int clean_chunk_d(int F, int S, size_t ng);
 
 // mid-step to end-of-step conversion applied on the fly: d <- ph (d - i hdt u_b H_l)
 struct MidArgs {
@@ -41,6 +43,8 @@ hipError_t launch_coef_x3(const float2* d, int F, const PhiSplit& ps, size_t ng,
 // scratch holds the split coefficient rows (clean_scratch_floats)
 hipError_t launch_update_x3(float2* d, int F, const PhiSplit& ps, const float2* E, int L, size_t ng,
                             const double2* coef, float* scratch, hipStream_t st, const MidArgs& mid);
+// for batches of up to F = B L fields
 size_t clean_scratch_floats(int F, int L, int S, size_t ng);
-size_t edot_part_entries(int F, size_t ng);
+// for batches of up to F = B L fields
+size_t edot_part_entries(int F, int L, int S, size_t ng);
 }  // namespace bse

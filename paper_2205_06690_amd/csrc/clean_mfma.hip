@@ -268,10 +268,16 @@ __global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F
                                                    const unsigned short* __restrict__ ctl,
                                                    const double2* __restrict__ coef, int nrt,
                                                    unsigned ntile, MidArgs mid) {
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[XT][XKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[XT][XKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[XT][XKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[XT][XKP];
+  // operand tiles during the K loop; afterwards the same LDS holds half of
+  // the result tile (64 rows x 128 points, rows padded) at a time
+  constexpr int TP = XT + 4;
+  static_assert(4 * XT * XKP * sizeof(__bf16) >= 64 * TP * sizeof(float), "result half fits");
+  __shared__ __attribute__((aligned(16))) __bf16 lds_u[4 * XT * XKP];
+  __bf16 (*Ah)[XKP] = reinterpret_cast<__bf16 (*)[XKP]>(lds_u);
+  __bf16 (*Al)[XKP] = Ah + XT;
+  __bf16 (*Bh)[XKP] = Al + XT;
+  __bf16 (*Bl)[XKP] = Bh + XT;
+  float* T = reinterpret_cast<float*>(lds_u);
   const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntile) return;
   const int rt = (int)(t % nrt);
@@ -330,28 +336,82 @@ __global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F
     if (kb + XK < Sp) load(kb + XK);
     mma_stage<XKP>(Ah, Al, Bh, Bl, lane, wm, wn, acc);
   }
-  // epilogue: lane holds rows 4q..4q+3 = fields 2q, 2q+1 (re, im) at one point
+  // epilogue, two halves of 32 fields: the waves owning the half write their
+  // results to LDS, then every thread streams 4 fields x 4 consecutive points
+  // (16-byte accesses; a wave covers 128 points of two fields)
+  const int pg = tid & 31, fs = tid >> 5;
+  const size_t pr = p0 + 4 * pg;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();
+    if (wm == half) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = r0 + wm * 64 + i * 16 + 4 * (lane >> 4);
-      const size_t r = p0 + wn * 64 + j * 16 + (lane & 15);
-      if (r >= ng) continue;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int f = row / 2 + h;
-        if (2 * f >= R) continue;
-        const int l = f % L;
-        const float cr = (float)coef[(size_t)f * (S + 1) + S].x;
-        const float2 e = E[(size_t)l * ng + r];
-        float2 v = d[(size_t)f * ng + r];
-        if (MID) v = finish_mid(mid, f, r, v);
-        v.x -= acc[i][j][2 * h] + cr * e.x;
-        v.y -= acc[i][j][2 * h + 1] + cr * e.y;
-        d[(size_t)f * ng + r] = v;
-      }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            T[(i * 16 + 4 * (lane >> 4) + v) * TP + wn * 64 + j * 16 + (lane & 15)] = acc[i][j][v];
     }
+    __syncthreads();
+    if (pr >= ng) continue;
+    float4 p01 = make_float4(0.f, 0.f, 0.f, 0.f), p23 = p01;
+    if (MID) {
+      p01 = *reinterpret_cast<const float4*>(mid.ph + pr);
+      p23 = *reinterpret_cast<const float4*>(mid.ph + pr + 2);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int fl = fs + 8 * q;                 // field within the half
+      const int f = r0 / 2 + half * 32 + fl;
+      if (2 * f >= R) continue;
+      const int l = f % L;
+      const float cr = (float)coef[(size_t)f * (S + 1) + S].x;
+      float2* dp = d + (size_t)f * ng + pr;
+      float4 d01 = reinterpret_cast<const float4*>(dp)[0];
+      float4 d23 = reinterpret_cast<const float4*>(dp)[1];
+      float4 e01, e23;
+      if (MID) {
+        const float2* hp = mid.H + (size_t)l * ng + pr;
+        const float4 h01 = reinterpret_cast<const float4*>(hp)[0];
+        const float4 h23 = reinterpret_cast<const float4*>(hp)[1];
+        const float4 uu = *reinterpret_cast<const float4*>(mid.u + (size_t)(f / L) * ng + pr);
+        const float2 hv[4] = {make_float2(h01.x, h01.y), make_float2(h01.z, h01.w),
+                              make_float2(h23.x, h23.y), make_float2(h23.z, h23.w)};
+        const float2 pv[4] = {make_float2(p01.x, p01.y), make_float2(p01.z, p01.w),
+                              make_float2(p23.x, p23.y), make_float2(p23.z, p23.w)};
+        const float uv[4] = {uu.x, uu.y, uu.z, uu.w};
+        float2 dv[4] = {make_float2(d01.x, d01.y), make_float2(d01.z, d01.w),
+                        make_float2(d23.x, d23.y), make_float2(d23.z, d23.w)};
+        float2 ev[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          dv[k] = finish1(dv[k], hv[k], uv[k], pv[k], mid.half_dt);
+          ev[k] = cm(pv[k], hv[k]);
+        }
+        d01 = make_float4(dv[0].x, dv[0].y, dv[1].x, dv[1].y);
+        d23 = make_float4(dv[2].x, dv[2].y, dv[3].x, dv[3].y);
+        e01 = make_float4(ev[0].x, ev[0].y, ev[1].x, ev[1].y);
+        e23 = make_float4(ev[2].x, ev[2].y, ev[3].x, ev[3].y);
+      } else {
+        const float2* ep = E + (size_t)l * ng + pr;
+        e01 = reinterpret_cast<const float4*>(ep)[0];
+        e23 = reinterpret_cast<const float4*>(ep)[1];
+      }
+      const float4 are = *reinterpret_cast<const float4*>(&T[(2 * fl) * TP + 4 * pg]);
+      const float4 aim = *reinterpret_cast<const float4*>(&T[(2 * fl + 1) * TP + 4 * pg]);
+      d01.x -= are.x + cr * e01.x;
+      d01.y -= aim.x + cr * e01.y;
+      d01.z -= are.y + cr * e01.z;
+      d01.w -= aim.y + cr * e01.w;
+      d23.x -= are.z + cr * e23.x;
+      d23.y -= aim.z + cr * e23.y;
+      d23.z -= are.w + cr * e23.z;
+      d23.w -= aim.w + cr * e23.w;
+      reinterpret_cast<float4*>(dp)[0] = d01;
+      reinterpret_cast<float4*>(dp)[1] = d23;
+    }
+  }
 }
 
 static unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
@@ -411,15 +471,36 @@ hipError_t launch_update_x3(float2* d, int F, const PhiSplit& ps, const float2* 
   return hipGetLastError();
 }
 
+int clean_chunk_d(int F, int S, size_t ng) {
+  const size_t tiles = (size_t)((2 * F + XT - 1) / XT) * ((S + XT - 1) / XT);
+  const size_t nc = std::max<size_t>(1, (2048 + tiles - 1) / tiles);
+  const size_t c = ((ng + nc - 1) / nc + XK - 1) / XK * XK;
+  return (int)std::min<size_t>(c, 1u << 30);
+}
+
+// coefficient partials of F fields: nchunk(F) x 2F x S floats
+static size_t coef_part_d(int F, int S, size_t ng) {
+  const size_t cd = (size_t)clean_chunk_d(F, S, ng);
+  return (ng + cd - 1) / cd * 2 * (size_t)F * S;
+}
+
+// F = B L fields for batches of up to B pairs: the chunk count depends on the
+// batch, so the partials are sized by the largest need over every batch size
 size_t clean_scratch_floats(int F, int L, int S, size_t ng) {
-  const size_t a = (ng + CLEAN_CHUNK_D - 1) / CLEAN_CHUNK_D * 2 * (size_t)F * S;
+  size_t a = 0;
+  for (int f = L; f <= F; f += L) a = std::max(a, coef_part_d(f, S, ng));
   const size_t b = (ng + CLEAN_CHUNK_E - 1) / CLEAN_CHUNK_E * 2 * (size_t)L * S;
   const size_t c = (size_t)2 * F * clean_sp(S);   // two bf16 arrays of 2F x Sp
   return std::max(a, std::max(b, c));
 }
 
-size_t edot_part_entries(int F, size_t ng) {
-  return (size_t)F * ((ng + CLEAN_CHUNK_D - 1) / CLEAN_CHUNK_D);
+size_t edot_part_entries(int F, int L, int S, size_t ng) {
+  size_t m = 0;
+  for (int f = L; f <= F; f += L) {
+    const size_t cd = (size_t)clean_chunk_d(f, S, ng);
+    m = std::max(m, (size_t)f * ((ng + cd - 1) / cd));
+  }
+  return m;
 }
 
 }  // namespace bse

@@ -1019,7 +1019,7 @@ hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
     const MidArgs off{};
     const PhiSplit ps{a.phih, a.phil, a.phith, a.phitl, S, clean_sp(S)};
     // 2. coefficients and <E_l, d_f> on the matrix cores
-    hipError_t e = launch_coef_x3(a.d, a.F, ps, a.ng, CLEAN_CHUNK_D, a.part32, a.dv, a.coef, st, mid,
+    hipError_t e = launch_coef_x3(a.d, a.F, ps, a.ng, clean_chunk_d(a.F, S, a.ng), a.part32, a.dv, a.coef, st, mid,
                                   a.E, a.L, a.gpart);
     if (e != hipSuccess) return e;
     e = launch_coef_x3(a.E, a.L, ps, a.ng, CLEAN_CHUNK_E, a.part32, a.dv, a.coefE, st, off, a.E, a.L,
