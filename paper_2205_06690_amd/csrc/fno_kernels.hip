@@ -18,6 +18,13 @@ template <int N> constexpr int fplane_stride() { return N + 1; }
 template <int N> __device__ __forceinline__ int fplane_idx(int e) {
   return (e / N) * fplane_stride<N>() + (e % N);
 }
+// the twiddle table copied into LDS (the transforms then read it through the
+// LDS counter, not behind the vector-memory loads of the data)
+template <int N>
+__device__ __forceinline__ void fno_tw_lds(float2* t, const float2* __restrict__ tw, int tid, int nthr) {
+  for (int i = tid; i < N; i += nthr) t[i] = tw[i];
+}
+
 // scrambled slot of natural frequency index k (inverse of scr2k)
 template <int N> __device__ __forceinline__ int k2scr(int k) {
   constexpr int N1 = Fac<N>::N1, N2 = Fac<N>::N2;
@@ -38,16 +45,18 @@ __global__ void __launch_bounds__(256) k_fno_yz_fwd_t(const float* __restrict__ 
   const size_t ng = (size_t)N * N * N;
   const int x = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
   const float* src = in + (size_t)f * ng + (size_t)x * P;
+  float2* twl = s + N * S;
+  fno_tw_lds<N>(twl, tw, tid, NT);
   for (int e = tid; e < P; e += NT) s[fplane_idx<N>(e)] = make_float2(src[e], 0.f);
   __syncthreads();
   NoMul nm;
-  stageA_fwd<N>(s, N, S, 1, tw, tid, NT, true);
+  stageA_fwd<N>(s, N, S, 1, twl, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, S, 1, tw, tid, NT, true, nm);
+  stageB<N, 0>(s, N, S, 1, twl, tid, NT, true, nm);
   __syncthreads();
-  stageA_fwd<N>(s, N, 1, S, tw, tid, NT, true);
+  stageA_fwd<N>(s, N, 1, S, twl, tid, NT, true);
   __syncthreads();
-  stageB<N, 0>(s, N, 1, S, tw, tid, NT, true, nm);
+  stageB<N, 0>(s, N, 1, S, twl, tid, NT, true, nm);
   __syncthreads();
   float2* dst = work + (size_t)f * ng + (size_t)x * P;
   for (int e = tid; e < P; e += NT) dst[e] = s[fplane_idx<N>(e)];
@@ -60,6 +69,8 @@ __global__ void __launch_bounds__(256) k_fno_x_gather(const float2* __restrict__
                                                       const float2* __restrict__ tw, int m,
                                                       int ck_scale, float2* __restrict__ V) {
   __shared__ float2 s[N * KC];
+  __shared__ float2 twl[N];
+  fno_tw_lds<N>(twl, tw, threadIdx.x, 256);
   const size_t ng = (size_t)N * N * N;
   const int f = blockIdx.y, tid = threadIdx.x;
   const int ncol = 2 * m * m;
@@ -80,9 +91,9 @@ __global__ void __launch_bounds__(256) k_fno_x_gather(const float2* __restrict__
   }
   __syncthreads();
   NoMul nm;
-  stageA_fwd<N>(s, KC, 1, KC, tw, tid, 256, true);
+  stageA_fwd<N>(s, KC, 1, KC, twl, tid, 256, true);
   __syncthreads();
-  stageB<N, 0>(s, KC, 1, KC, tw, tid, 256, true, nm);
+  stageB<N, 0>(s, KC, 1, KC, twl, tid, 256, true, nm);
   __syncthreads();
   const float inv = 1.0f / (float)ng;
   for (int e = tid; e < 2 * m * KC; e += 256) {
@@ -111,6 +122,8 @@ __global__ void __launch_bounds__(256) k_fno_x_scatter(const float2* __restrict_
                                                        const float2* __restrict__ tw, int m,
                                                        int ck_scale, float2* __restrict__ work) {
   __shared__ float2 s[N * KC];
+  __shared__ float2 twl[N];
+  fno_tw_lds<N>(twl, tw, threadIdx.x, 256);
   const size_t ng = (size_t)N * N * N;
   const int f = blockIdx.y, tid = threadIdx.x;
   const int ncol = 2 * m * m;
@@ -135,7 +148,7 @@ __global__ void __launch_bounds__(256) k_fno_x_scatter(const float2* __restrict_
   }
   __syncthreads();
   NoMul nm;
-  stageB<N, 1>(s, KC, 1, KC, tw, tid, 256, true, nm);
+  stageB<N, 1>(s, KC, 1, KC, twl, tid, 256, true, nm);
   __syncthreads();
   stageC_inv<N>(s, KC, 1, KC, tid, 256, true);
   __syncthreads();
@@ -160,14 +173,16 @@ __global__ void __launch_bounds__(256) k_fno_yz_inv(const float2* __restrict__ w
   const size_t ng = (size_t)N * N * N;
   const int x = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
   const float2* src = work + (size_t)f * ng + (size_t)x * P;
+  float2* twl = s + N * S;
+  fno_tw_lds<N>(twl, tw, tid, NT);
   for (int e = tid; e < P; e += NT) s[fplane_idx<N>(e)] = src[e];
   __syncthreads();
   NoMul nm;
-  stageB<N, 1>(s, N, S, 1, tw, tid, NT, true, nm);
+  stageB<N, 1>(s, N, S, 1, twl, tid, NT, true, nm);
   __syncthreads();
   stageC_inv<N>(s, N, S, 1, tid, NT, true);
   __syncthreads();
-  stageB<N, 1>(s, N, 1, S, tw, tid, NT, true, nm);
+  stageB<N, 1>(s, N, 1, S, twl, tid, NT, true, nm);
   __syncthreads();
   stageC_inv<N>(s, N, 1, S, tid, NT, true);
   __syncthreads();
@@ -454,7 +469,7 @@ template <int N>
 struct FnoLaunch {
   static hipError_t fwd(const float* in, int F, const float2* tw, int m, int ck, float2* work,
                         float2* V, hipStream_t st) {
-    const size_t sm = sizeof(float2) * N * fplane_stride<N>();
+    const size_t sm = sizeof(float2) * (N * fplane_stride<N>() + N);
     hipLaunchKernelGGL(k_fno_yz_fwd_t<N>, dim3(N, F), dim3(256), sm, st, in, work, tw);
     const int ncol = 2 * m * m;
     hipLaunchKernelGGL(k_fno_x_gather<N>, dim3((ncol + KC - 1) / KC, F), dim3(256), 0, st, work,
@@ -469,12 +484,12 @@ struct FnoLaunch {
     const int ncol = 2 * m * m;
     hipLaunchKernelGGL(k_fno_x_scatter<N>, dim3((ncol + KC - 1) / KC, F), dim3(256), 0, st, U, tw,
                        m, ck, work);
-    const size_t sm = sizeof(float2) * N * fplane_stride<N>();
+    const size_t sm = sizeof(float2) * (N * fplane_stride<N>() + N);
     hipLaunchKernelGGL(k_fno_yz_inv<N>, dim3(N, F), dim3(256), sm, st, work, tw, out, accumulate);
     return hipGetLastError();
   }
   static void configure() {
-    const int sm = (int)(sizeof(float2) * N * fplane_stride<N>());
+    const int sm = (int)(sizeof(float2) * (N * fplane_stride<N>() + N));
     (void)hipFuncSetAttribute((const void*)k_fno_yz_fwd_t<N>, hipFuncAttributeMaxDynamicSharedMemorySize, sm);
     (void)hipFuncSetAttribute((const void*)k_fno_yz_inv<N>, hipFuncAttributeMaxDynamicSharedMemorySize, sm);
   }
