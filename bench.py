@@ -386,7 +386,7 @@ def main():
         fl_d = 3.0 * 2.0 * n_ab * B * spec.ng
         ms_x, ms_d = kt["gemm_exchange"][0], kt["gemm_direct"][0]
         tf = (fl_x + fl_d) / ((ms_x + ms_d) * 1e-3) / 1e12
-        contraction = {"bound": "mfma", "kernel": "k_gemm_bf16x3 (exchange + direct)",
+        contraction = {"bound": "mfma", "kernel": "k_contract_x3 (exchange + direct)",
                        "achieved": round(tf, 1), "peak": PEAK_BF16_TFS, "unit": "TFLOP/s",
                        "frac": round(tf / PEAK_BF16_TFS, 4),
                        "flops_issued": fl_x + fl_d, "ms": round(ms_x + ms_d, 4),

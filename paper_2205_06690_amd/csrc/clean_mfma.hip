@@ -215,31 +215,55 @@ __global__ void __launch_bounds__(256) k_coef_x3(const float2* __restrict__ d, i
 }
 
 // coef[f][s] = dv * (sum_kc part[kc][2f][s] + i sum_kc part[kc][2f+1][s]),
-// stored with row stride S+1 (slot S holds the E dot).
-__global__ void k_coef_reduce(const float* __restrict__ part, int nchunk, int F, int S, double dv,
-                              double2* __restrict__ coef) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F * S) return;
-  const int f = i / S, s = i % S;
+// stored with row stride S+1 (slot S holds the E dot).  A block sums 32
+// outputs in RED_SL slices of the chunks (slice j: kc = j, j + RED_SL, ...),
+// then adds the slices in order: a fixed summation order with enough loads
+// in flight to stream the partials.
+constexpr int RED_SL = 8;
+__global__ void __launch_bounds__(256) k_coef_reduce(const float* __restrict__ part, int nchunk, int F,
+                                                     int S, double dv, double2* __restrict__ coef) {
+  __shared__ double2 red[RED_SL][32];
+  const int o = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + o;
+  const bool live = i < F * S;
+  const int f = live ? i / S : 0, s = live ? i % S : 0;
   const size_t RS = (size_t)2 * F * S;
   double x = 0, y = 0;
-  for (int k = 0; k < nchunk; ++k) {
-    x += part[k * RS + (size_t)(2 * f) * S + s];
-    y += part[k * RS + (size_t)(2 * f + 1) * S + s];
+  if (live)
+    for (int k = j; k < nchunk; k += RED_SL) {
+      x += part[k * RS + (size_t)(2 * f) * S + s];
+      y += part[k * RS + (size_t)(2 * f + 1) * S + s];
+    }
+  red[j][o] = make_double2(x, y);
+  __syncthreads();
+  if (j == 0 && live) {
+    double sx = 0, sy = 0;
+#pragma unroll
+    for (int q = 0; q < RED_SL; ++q) {
+      sx += red[q][o].x;
+      sy += red[q][o].y;
+    }
+    coef[(size_t)f * (S + 1) + s] = make_double2(sx * dv, sy * dv);
   }
-  coef[(size_t)f * (S + 1) + s] = make_double2(x * dv, y * dv);
 }
 
-__global__ void k_edot_reduce(const double2* __restrict__ gpart, int nblk, int F, int S, double dv,
-                              double2* __restrict__ coef) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// coef[f][S] = dv sum_k gpart[f][k]: one wave per field, lanes over k, then a
+// fixed shuffle tree
+__global__ void __launch_bounds__(256) k_edot_reduce(const double2* __restrict__ gpart, int nblk, int F,
+                                                     int S, double dv, double2* __restrict__ coef) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (f >= F) return;
   double x = 0, y = 0;
-  for (int k = 0; k < nblk; ++k) {
-    x += gpart[(size_t)f * nblk + k].x;
-    y += gpart[(size_t)f * nblk + k].y;
+  for (int k = lane; k < nblk; k += 64) {
+    const double2 g = gpart[(size_t)f * nblk + k];
+    x += g.x;
+    y += g.y;
   }
-  coef[(size_t)f * (S + 1) + S] = make_double2(x * dv, y * dv);
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_down(x, off, 64);
+    y += __shfl_down(y, off, 64);
+  }
+  if (lane == 0) coef[(size_t)f * (S + 1) + S] = make_double2(x * dv, y * dv);
 }
 
 // coefficient rows for the update: ct[row][s], row 2f = Re C[f][s], 2f+1 =
@@ -443,10 +467,10 @@ hipError_t launch_coef_x3(const float2* d, int F, const PhiSplit& ps, size_t ng,
     hipLaunchKernelGGL((k_coef_x3<false, false>), g, b, 0, st, d, F, ps, ng, chunk, nrt, nct, nchunk,
                        ntile, mid, E, L, part, gpart);
   if (gpart)
-    hipLaunchKernelGGL(k_edot_reduce, dim3((F + 255) / 256), dim3(256), 0, st, gpart, nchunk, F, ps.S,
-                       dv, coef);
-  hipLaunchKernelGGL(k_coef_reduce, dim3((F * ps.S + 255) / 256), dim3(256), 0, st, part, nchunk, F,
-                     ps.S, dv, coef);
+    hipLaunchKernelGGL(k_edot_reduce, dim3((F + 3) / 4), dim3(256), 0, st, gpart, nchunk, F, ps.S, dv,
+                       coef);
+  hipLaunchKernelGGL(k_coef_reduce, dim3((F * ps.S + 31) / 32), dim3(256), 0, st, part, nchunk, F, ps.S,
+                     dv, coef);
   return hipGetLastError();
 }
 

@@ -130,14 +130,28 @@ __global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __res
       }
 }
 
-// C[m][n] = scale sum_kc part[kc][m][n] in FP64
-__global__ void k_contract_reduce(const float* __restrict__ part, int nchunk, size_t MN, double scale,
-                                  double* __restrict__ C) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= MN) return;
+// C[m][n] = scale sum_kc part[kc][m][n] in FP64.  A block sums 32 outputs in
+// CR_SL slices of the chunks (slice j: kc = j, j + CR_SL, ...) and adds the
+// slices in order: a fixed summation order with enough loads in flight to
+// stream the partials.
+constexpr int CR_SL = 8;
+__global__ void __launch_bounds__(256) k_contract_reduce(const float* __restrict__ part, int nchunk,
+                                                         size_t MN, double scale,
+                                                         double* __restrict__ C) {
+  __shared__ double red[CR_SL][32];
+  const int o = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const size_t i = (size_t)blockIdx.x * 32 + o;
   double acc = 0;
-  for (int k = 0; k < nchunk; ++k) acc += part[(size_t)k * MN + i];
-  C[i] = acc * scale;
+  if (i < MN)
+    for (int k = j; k < nchunk; k += CR_SL) acc += part[(size_t)k * MN + i];
+  red[j][o] = acc;
+  __syncthreads();
+  if (j == 0 && i < MN) {
+    double s = 0;
+#pragma unroll
+    for (int q = 0; q < CR_SL; ++q) s += red[q][o];
+    C[i] = s * scale;
+  }
 }
 
 static unsigned round8u(unsigned n) { return (n + 7u) & ~7u; }
@@ -194,7 +208,7 @@ hipError_t launch_contract_x3(const unsigned short* ah, const unsigned short* al
   hipLaunchKernelGGL(k_contract_x3<CK_STAGE>, dim3(round8u(ntile)), dim3(256), contract_lds<CK_STAGE>(), st,
                      ah, al, M, bh, bl, N, K, chunk, ntm, ntn, ntile, 1, part);
   const size_t MN = (size_t)M * N;
-  hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((MN + 31) / 32)), dim3(256), 0, st, part,
                      nchunk, MN, scale, C);
   return hipGetLastError();
 }

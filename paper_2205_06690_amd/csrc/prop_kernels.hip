@@ -697,21 +697,26 @@ __global__ void k_clean_reduce(const cplx<double>* __restrict__ part, int nchunk
   coef[i] = cmk<cplx<double>>(x * dv, y * dv);
 }
 
-// renormalisation factor per field: c_f = Re(<E,d> - sum_s conj(De[l][s]) C[f][s]) / N0_l
-__global__ void k_clean_renorm(cplx<double>* __restrict__ coef, int F, int S,
-                               const cplx<double>* __restrict__ coefE, const double* __restrict__ n0,
-                               int L, int renorm) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// renormalisation factor per field: c_f = Re(<E,d> - sum_s conj(De[l][s]) C[f][s]) / N0_l;
+// one wave per field, lanes over s, a fixed shuffle tree
+__global__ void __launch_bounds__(256) k_clean_renorm(cplx<double>* __restrict__ coef, int F, int S,
+                                                      const cplx<double>* __restrict__ coefE,
+                                                      const double* __restrict__ n0, int L, int renorm) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (f >= F) return;
   const int l = f % L;
   cplx<double>* c = coef + (size_t)f * (S + 1);
-  double r = c[S].x;
-  for (int s = 0; s < S; ++s) {
+  double r = 0;
+  for (int s = lane; s < S; s += 64) {
     const cplx<double> de = coefE[(size_t)l * (S + 1) + s];
     const cplx<double> cc = c[s];
-    r -= de.x * cc.x + de.y * cc.y;
+    r += de.x * cc.x + de.y * cc.y;
   }
-  c[S] = cmk<cplx<double>>(renorm ? r / n0[l] : 0.0, 0.0);
+  for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
+  if (lane == 0) {
+    const double v = c[S].x - r;
+    c[S] = cmk<cplx<double>>(renorm ? v / n0[l] : 0.0, 0.0);
+  }
 }
 
 // d_f(r) -= sum_s C[f][s] phi_s(r) + c_f E_l(r)
@@ -1025,7 +1030,7 @@ hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
     e = launch_coef_x3(a.E, a.L, ps, a.ng, CLEAN_CHUNK_E, a.part32, a.dv, a.coefE, st, off, a.E, a.L,
                        nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
+    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 3) / 4), dim3(256), 0, st, a.coef, a.F, S,
                        a.coefE, a.n0, a.L, a.renorm);
     // 3. update on the matrix cores
     e = launch_update_x3(a.d, a.F, ps, a.E, a.L, a.ng, a.coef, a.part32, st, mid);
@@ -1046,7 +1051,7 @@ hipError_t launch_clean(const CleanArgs<T>& a, hipStream_t st) {
                        a.chunk, a.part);
     hipLaunchKernelGGL(k_clean_reduce, dim3((a.L * (S + 1) + 255) / 256), dim3(256), 0, st, a.part,
                        nchunk, a.L * (S + 1), a.dv, a.coefE);
-    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 255) / 256), dim3(256), 0, st, a.coef, a.F, S,
+    hipLaunchKernelGGL(k_clean_renorm, dim3((a.F + 3) / 4), dim3(256), 0, st, a.coef, a.F, S,
                        a.coefE, a.n0, a.L, a.renorm);
     // 3. update
     dim3 g3((unsigned)((a.ng + 63) / 64), (a.F + 15) / 16);
