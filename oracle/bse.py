@@ -156,6 +156,36 @@ def chebyshev_absorption(R: np.ndarray, w_grid: np.ndarray, a: float, b: float, 
     return w_grid * (g @ R.sum(axis=1))
 
 
+def chebyshev_states(A: np.ndarray, f0: np.ndarray, n_mom: int, a: float, b: float,
+                     w_grid: np.ndarray, sigma: float, n_nodes: int | None = None) -> np.ndarray:
+    """Eq. 8: the frequency-resolved exciton states
+    |f(omega)> = sum_{n < n_mom} g_n(omega) T_n(A~) |f^0>, the f^n by the
+    three-term recursion in A~ = (A - b)/a, one column of f0 per
+    polarisation; [n_w, n, n_pol]."""
+    g = chebyshev_coefficients(np.asarray(w_grid, dtype=float), n_mom, a, b, sigma, n_nodes)
+    At = (A - b * np.eye(A.shape[0])) / a
+    out = g[:, 0, None, None] * f0[None]
+    if n_mom == 1:
+        return out
+    f_prev, f_cur = f0, At @ f0
+    out = out + g[:, 1, None, None] * f_cur[None]
+    for n in range(2, n_mom):
+        f_next = 2.0 * (At @ f_cur) - f_prev
+        out = out + g[:, n, None, None] * f_next[None]
+        f_prev, f_cur = f_cur, f_next
+    return out
+
+
+def exciton_density(phi_v: np.ndarray, phi_c: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """Exciton density of an electron-hole vector F [n_o n_c] (rows of A,
+    valence index major): the mixed-representation density 2 sum_i phi_i f_i
+    with f_i = sum_a F_ia phi_a, i.e. 2 sum_ia F_ia phi_i phi_a."""
+    n_o, n_c = phi_v.shape[0], phi_c.shape[0]
+    Fm = np.asarray(F, dtype=float).reshape(n_o, n_c)
+    f_i = np.tensordot(Fm, phi_c, axes=(1, 0))          # [n_o, ...]
+    return 2.0 * np.sum(phi_v * f_i, axis=0)
+
+
 # ---------------------------------------------------------------------------
 # Matrix-free action of A in the mixed hole-grid representation (Eq. 6 with
 # A = Q A-bar): f_j(r) for the n_o valence orbitals j,

@@ -199,6 +199,62 @@ def test_gershgorin_bounds_contain_spectrum():
     assert lo <= w[0] and w[-1] <= hi
 
 
+def test_chebyshev_states_equal_gaussian_of_a():
+    """Eq. 8 with enough moments is the broadened delta of A applied to
+    f0: sum_k G(lambda_k - omega) X_k <X_k|f0> from the eigenpairs; too
+    few moments leave a visible error."""
+    A, f0 = _sym(30, 7)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    s = 0.02
+    wg = np.array([0.25, 0.48, 0.61, 0.9])
+    w, X = np.linalg.eigh(A)
+    G = np.exp(-0.5 * ((w[None, :] - wg[:, None]) / s) ** 2) / (s * math.sqrt(2 * math.pi))
+    ref = np.einsum("qk,nk,kp->qnp", G, X, X.T @ f0)
+    errs = []
+    for n_mom in (int(a / s), int(8 * a / s)):
+        F = bse.chebyshev_states(A, f0, n_mom, a, b, wg, s)
+        errs.append(np.abs(F - ref).max() / np.abs(ref).max())
+    assert errs[0] > 1e-3
+    assert errs[1] < 1e-10
+
+
+def test_chebyshev_states_carry_the_residue_spectrum():
+    """<f0|f(omega)> summed over polarisations is sigma(omega)/omega of the
+    residue path (Eq. 7), itself pinned to the eigenpairs above."""
+    A, f0 = _sym(20, 8)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    s, n_mom = 0.03, 400
+    wg = np.linspace(0.3, 0.9, 7)
+    F = bse.chebyshev_states(A, f0, n_mom, a, b, wg, s)
+    R = bse.chebyshev_residues(A, f0, n_mom, a, b)
+    sg = bse.chebyshev_absorption(R, wg, a, b, s)
+    assert np.allclose(wg * np.einsum("np,qnp->q", f0, F), sg, rtol=1e-11, atol=1e-14)
+
+
+def test_exciton_density_charge_and_dipole(gauss):
+    """For Gaussian orbitals the pair products are Gaussian charges Q_ia at
+    M_ia, so the exciton density of F integrates to 2 sum F_ia Q_ia and its
+    dipole is 2 sum F_ia Q_ia (M_ia - c) = 2 F.f0; a transposed F, a lost
+    factor 2 or a swapped orbital set breaks both."""
+    grid, Rv, Rc, phv, phc = gauss
+    nc = len(Rc)
+    rng = np.random.default_rng(12)
+    F = rng.standard_normal(len(Rv) * nc)
+    dn = bse.exciton_density(phv, phc, F)
+    c = N * H / 2
+    q = sum(F[i * nc + a] * _pair(Rv[i], Rc[a])[0] for i in range(len(Rv)) for a in range(nc))
+    dip = sum(F[i * nc + a] * _pair(Rv[i], Rc[a])[0] * (_pair(Rv[i], Rc[a])[1] - c)
+              for i in range(len(Rv)) for a in range(nc))
+    assert abs(np.sum(dn) * grid.dv - 2 * q) < 1e-9
+    xs = grid.coords()
+    for ax in range(3):
+        shp = [1, 1, 1]
+        shp[ax] = -1
+        mom = np.sum(dn * (xs[ax] - c).reshape(shp)) * grid.dv
+        assert abs(mom - 2 * dip[ax]) < 1e-9
+        assert abs(mom - 2 * F @ bse.dipoles(grid, phv, phc)[:, ax]) < 1e-9
+
+
 # --------------------------------------------------------------------------
 # matrix-free A f in the mixed representation (Eq. 6)
 # --------------------------------------------------------------------------
