@@ -362,6 +362,18 @@ def main():
         torch.cuda.synchronize()
         cheb = {"n_residues": n_mom, "ms": round((time.perf_counter() - tc0) * 1e3, 3),
                 "interval_Ha": [round(float(bo[0]), 6), round(float(bo[1]), 6)], "n_omega": 2000}
+        # frequency-resolved exciton states (Eq. 8) at the four lowest
+        # excitons, with their densities on the grid: the full recursion of
+        # n_mom - 1 applications of A
+        om4, _ = S.spectrum(4)
+        S.exciton_states(4, om4, sig, bounds=bo, densities=False)
+        torch.cuda.synchronize()
+        te0 = time.perf_counter()
+        S.exciton_states(n_mom, om4, sig, bounds=bo, densities=True)
+        torch.cuda.synchronize()
+        cheb["exciton_states"] = {"n_moments": n_mom, "n_omega": 4, "densities": True,
+                                  "ms": round((time.perf_counter() - te0) * 1e3, 3),
+                                  "note": "includes the host copy of 12 densities"}
 
     # the matrix-free A f of the mixed representation (Eq. 6), FP64, timed
     # outside the step: the inner operation of the paper's spectrum loop

@@ -171,6 +171,29 @@ bse_status bse_chebyshev_spectrum(bse_system* sys, int32_t n_mom, double e_min, 
                                   int32_t n_w, const double* w_grid, double sigma_broad,
                                   double* sigma, double* residues, double* bounds);
 
+/* Frequency-resolved exciton states (Eq. 8) and their densities, on the A
+ * of the last bse_build_A, in FP64 on the device.  For each frequency
+ * w_list[q] (Hartree) and each of the three dipole start vectors f0 (as in
+ * bse_chebyshev_spectrum):
+ *   F[q][axis] = sum_{n < n_mom} g_n(w_q) T_n(A~) f0_axis,
+ * A~ = (A - b)/a, b = (e_min + e_max)/2, a = 1.01 (e_max - e_min)/2, g_n the
+ * Chebyshev coefficients of a normalised Gaussian of standard deviation
+ * sigma_broad centred at w_q (Gauss-Chebyshev quadrature on 2 n_mom nodes),
+ * i.e. the broadened delta(A - w_q) applied to f0; its components are the
+ * transition amplitudes f_ia(w) in the row order of A.  The exciton density
+ * of each state is dn(r) = 2 sum_i phi_i(r) f_i(r) with f_i = sum_a F_ia phi_a
+ * (the density of the mixed representation), i.e. 2 sum_ia F_ia phi_i phi_a.
+ * e_min < e_max: caller's bound on the spectrum of A; otherwise the
+ * Gershgorin interval.  n_mom >= 2 (the full recursion: n_mom - 1
+ * applications of A); 1 <= n_w <= 8; sigma_broad > 0.  Outputs (host,
+ * caller-allocated): f_out[n_w][3][n_o n_c]; dens_out[n_w][3][nx*ny*nz]
+ * (nullable); bounds[2] the interval used (nullable).  Errors:
+ * BSE_ERR_STATE before bse_build_A; BSE_ERR_ARG on bad sizes, null
+ * required pointers or a degenerate interval. */
+bse_status bse_exciton_states(bse_system* sys, int32_t n_mom, double e_min, double e_max,
+                              int32_t n_w, const double* w_list, double sigma_broad,
+                              double* f_out, double* dens_out, double* bounds);
+
 /* Uneven batch: the W-action for several systems at once (different grids,
  * orbital counts and pair counts, same device).  System k propagates
  * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and

@@ -32,7 +32,7 @@ EXPORTS = (
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
-    "bse_apply_A_mixed", "bse_chebyshev_mixed",
+    "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states",
 )
 
 
@@ -78,6 +78,8 @@ def _load():
     lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                            C.c_double, dp, dp, dp]
     lib.bse_apply_A_mixed.argtypes = [P, C.c_int32, dp, dp]
+    lib.bse_exciton_states.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp, C.c_double,
+                                       dp, dp, dp]
     lib.bse_chebyshev_mixed.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                         C.c_double, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
@@ -215,6 +217,7 @@ class System:
     def build_a(self, n_o: int, n_c: int) -> np.ndarray:
         A = np.empty((n_o * n_c, n_o * n_c))
         _check(LIB.bse_build_A(self._h, n_o, n_c, _dptr(A)))
+        self.a_window = (n_o, n_c)
         return A
 
     def apply_a_mixed(self, f: np.ndarray) -> np.ndarray:
@@ -241,6 +244,21 @@ class System:
         _check(LIB.bse_chebyshev_mixed(self._h, n_mom, lo, hi, wg.size, _dptr(wg), sigma, _dptr(sg),
                                        _dptr(res)))
         return sg, res
+
+    def exciton_states(self, n_mom: int, w_list, sigma: float = 0.08 / 27.211386245988, bounds=None,
+                       densities: bool = True):
+        """Frequency-resolved exciton states (Eq. 8) of the last A:
+        (F [n_w][3][n_o n_c], densities [n_w][3][nx, ny, nz] or None,
+        interval used)."""
+        wl = np.ascontiguousarray(w_list, dtype=np.float64).reshape(-1)
+        n_o, n_c = getattr(self, "a_window", (0, 0))
+        F = np.empty((wl.size, 3, max(1, n_o * n_c)))
+        dn = np.empty((wl.size, 3, self.n, self.n, self.n)) if densities else None
+        bo = np.empty(2)
+        lo, hi = (0.0, 0.0) if bounds is None else bounds
+        _check(LIB.bse_exciton_states(self._h, n_mom, lo, hi, wl.size, _dptr(wl), sigma, _dptr(F),
+                                      _dptr(dn) if densities else None, _dptr(bo)))
+        return F, dn, bo
 
     def chebyshev_spectrum(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
                            bounds=None):

@@ -900,6 +900,35 @@ void chebyshev_mixed(bse_system* s, int n_mom, double e_min, double e_max, int n
   HIPC(hipStreamSynchronize(st));
 }
 
+// The Chebyshev interval: the caller's [e_min, e_max] if e_min < e_max,
+// otherwise the Gershgorin interval of the device copy of A
+void cheb_interval(bse_system* s, int n, double* e_min, double* e_max, const char* who) {
+  if (*e_min < *e_max) return;
+  hipStream_t st = s->stream;
+  DBuf lohi;
+  lohi.alloc(sizeof(double) * 2 * (size_t)n);
+  HIPC(launch_gershgorin(s->A_d.as<double>(), n, lohi.as<double>(), st));
+  std::vector<double> h(2 * (size_t)n);
+  HIPC(hipMemcpyAsync(h.data(), lohi.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  *e_min = *std::min_element(h.begin(), h.begin() + n);
+  *e_max = *std::max_element(h.begin() + n, h.end());
+  if (!(*e_min < *e_max)) fail(BSE_ERR_ARG, std::string(who) + ": degenerate interval; pass bounds");
+}
+
+// electron-hole dipoles of the last bse_build_A as three start vectors
+// [3][n] on the device (f0_d holds them as [n][3])
+void cheb_start(bse_system* s, int n, double* dst) {
+  hipStream_t st = s->stream;
+  std::vector<double> f0(3 * (size_t)n), f0t(3 * (size_t)n);
+  HIPC(hipMemcpyAsync(f0.data(), s->f0_d.p, sizeof(double) * f0.size(), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    for (int p = 0; p < 3; ++p) f0t[(size_t)p * n + i] = f0[(size_t)i * 3 + p];
+  HIPC(hipMemcpyAsync(dst, f0t.data(), sizeof(double) * f0t.size(), hipMemcpyHostToDevice, st));
+  HIPC(hipStreamSynchronize(st));
+}
+
 // Chebyshev absorption (Eqs. 7-8) on the device copy of A: the residues of
 // the three dipole start vectors by the recursion in A~ = (A - b)/a, then the
 // broadened delta through its Chebyshev coefficients (Gauss-Chebyshev
@@ -915,17 +944,7 @@ void chebyshev_spectrum(bse_system* s, int n_mom, double e_min, double e_max, in
     fail(BSE_ERR_ARG, "bse_chebyshev_spectrum: bad arguments");
   hipStream_t st = s->stream;
   const double* A = s->A_d.as<double>();
-  if (!(e_min < e_max)) {
-    DBuf lohi;
-    lohi.alloc(sizeof(double) * 2 * (size_t)n);
-    HIPC(launch_gershgorin(A, n, lohi.as<double>(), st));
-    std::vector<double> h(2 * (size_t)n);
-    HIPC(hipMemcpyAsync(h.data(), lohi.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
-    e_min = *std::min_element(h.begin(), h.begin() + n);
-    e_max = *std::max_element(h.begin() + n, h.end());
-    if (!(e_min < e_max)) fail(BSE_ERR_ARG, "bse_chebyshev_spectrum: degenerate interval; pass bounds");
-  }
+  cheb_interval(s, n, &e_min, &e_max, "bse_chebyshev_spectrum");
   const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
   const int K = n_mom / 2, nblk = cheb_blocks(n), M = 2 * n_mom;
   DBuf fv, part, mu, D, wd, sd;
@@ -938,14 +957,9 @@ void chebyshev_spectrum(bse_system* s, int n_mom, double e_min, double e_max, in
     sd.alloc(sizeof(double) * n_w);
     HIPC(hipMemcpyAsync(wd.p, w_grid, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
   }
-  // f^0 = dipoles, [n][3] -> [3][n]
-  std::vector<double> f0(3 * (size_t)n), f0t(3 * (size_t)n);
-  HIPC(hipMemcpyAsync(f0.data(), s->f0_d.p, sizeof(double) * f0.size(), hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
-  for (int i = 0; i < n; ++i)
-    for (int p = 0; p < 3; ++p) f0t[(size_t)p * n + i] = f0[(size_t)i * 3 + p];
+  // f^0 = dipoles, [3][n]
   double* buf = fv.as<double>();
-  HIPC(hipMemcpyAsync(buf, f0t.data(), sizeof(double) * f0t.size(), hipMemcpyHostToDevice, st));
+  cheb_start(s, n, buf);
   for (int k = 0; k < K; ++k) {
     const double* fc = buf + (size_t)(k % 3) * 3 * n;
     const double* fp = buf + (size_t)((k + 2) % 3) * 3 * n;
@@ -958,6 +972,60 @@ void chebyshev_spectrum(bse_system* s, int n_mom, double e_min, double e_max, in
   if (n_w > 0) HIPC(hipMemcpyAsync(sigma, sd.p, sizeof(double) * n_w, hipMemcpyDeviceToHost, st));
   if (residues)
     HIPC(hipMemcpyAsync(residues, mu.p, sizeof(double) * 3 * (size_t)n_mom, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (bounds) {
+    bounds[0] = e_min;
+    bounds[1] = e_max;
+  }
+}
+
+// Frequency-resolved exciton states (Eq. 8) on the device copy of A: the full
+// three-term recursion from the dipole start vectors with
+// F_q += g_m(omega_q) f^m at every step, then (optionally) the exciton
+// densities 2 sum_ia F_ia phi_i phi_a of every (omega, polarisation).
+void exciton_states(bse_system* s, int n_mom, double e_min, double e_max, int n_w, const double* w_list,
+                    double sig, double* f_out, double* dens_out, double* bounds) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_exciton_states: call bse_build_A first");
+  if (n_mom < 2 || n_w < 1 || n_w > 8 || !w_list || !f_out || !(sig > 0))
+    fail(BSE_ERR_ARG, "bse_exciton_states: bad arguments");
+  const int n = s->a_no * s->a_nc;
+  hipStream_t st = s->stream;
+  const double* A = s->A_d.as<double>();
+  cheb_interval(s, n, &e_min, &e_max, "bse_exciton_states");
+  const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
+  auto* t = s->timer.begin("exciton_states");
+  DBuf fv, g, F, wd;
+  fv.alloc(sizeof(double) * 9 * (size_t)n);
+  g.alloc(sizeof(double) * (size_t)n_w * n_mom);
+  F.alloc(sizeof(double) * 3 * (size_t)n_w * n);
+  wd.alloc(sizeof(double) * n_w);
+  HIPC(hipMemcpyAsync(wd.p, w_list, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
+  HIPC(launch_cheb_coef(wd.as<double>(), n_w, n_mom, 2 * n_mom, a, b, sig, g.as<double>(), st));
+  double* buf = fv.as<double>();
+  cheb_start(s, n, buf);
+  HIPC(launch_cheb_acc_init(buf, n, g.as<double>(), n_mom, n_w, F.as<double>(), st));
+  // buffer k % 3 holds f^k
+  for (int m = 0; m + 1 < n_mom; ++m) {
+    const double* fc = buf + (size_t)(m % 3) * 3 * n;
+    const double* fp = buf + (size_t)((m + 2) % 3) * 3 * n;
+    double* fn = buf + (size_t)((m + 1) % 3) * 3 * n;
+    HIPC(launch_cheb_step_acc(A, n, fc, fp, fn, a, b, m == 0 ? 1 : 0, g.as<double>(), n_mom, m + 1, n_w,
+                              F.as<double>(), st));
+  }
+  const size_t ng = s->ng;
+  DBuf dens;
+  if (dens_out) {
+    const int v0 = s->cfg.n_occ - s->a_no, c0 = s->cfg.n_occ;
+    dens.alloc(sizeof(double) * 3 * (size_t)n_w * ng);
+    HIPC(launch_exciton_density(s->phi64.as<double>(), v0, c0, s->a_no, s->a_nc, ng, F.as<double>(),
+                                3 * n_w, dens.as<double>(), st));
+  }
+  s->timer.end(t);
+  HIPC(hipMemcpyAsync(f_out, F.p, sizeof(double) * 3 * (size_t)n_w * n, hipMemcpyDeviceToHost, st));
+  if (dens_out)
+    HIPC(hipMemcpyAsync(dens_out, dens.p, sizeof(double) * 3 * (size_t)n_w * ng, hipMemcpyDeviceToHost,
+                        st));
   HIPC(hipStreamSynchronize(st));
   if (bounds) {
     bounds[0] = e_min;
@@ -1502,6 +1570,14 @@ bse_status bse_chebyshev_spectrum(bse_system* s, int32_t n_mom, double e_min, do
                                   double* sigma, double* residues, double* bounds) {
   API_BEGIN
   chebyshev_spectrum(s, n_mom, e_min, e_max, n_w, w_grid, sigma_broad, sigma, residues, bounds);
+  API_END
+}
+
+bse_status bse_exciton_states(bse_system* s, int32_t n_mom, double e_min, double e_max, int32_t n_w,
+                              const double* w_list, double sigma_broad, double* f_out, double* dens_out,
+                              double* bounds) {
+  API_BEGIN
+  exciton_states(s, n_mom, e_min, e_max, n_w, w_list, sigma_broad, f_out, dens_out, bounds);
   API_END
 }
 

@@ -56,6 +56,19 @@ hipError_t launch_cheb_step(const double* A, int n, const double* fc, const doub
 hipError_t launch_cheb_spectrum(const double* part, int K, int nblk, double* mu, int M, double* D,
                                 double a, double b, const double* w, int n_w, double sig,
                                 double* out, hipStream_t st);
+// frequency-resolved exciton states (Eq. 8): g[n_w][N] Chebyshev coefficients
+// of the broadened delta (Gauss-Chebyshev quadrature on M nodes); F[n_w][3][n]
+// = g[.][0] f0 at the start, then one recursion step per moment adding
+// g[.][m_next] f^{m_next}; exciton densities dens[n_out][ng] of F[n_out][n]
+hipError_t launch_cheb_coef(const double* w, int n_w, int N, int M, double a, double b, double sig,
+                            double* g, hipStream_t st);
+hipError_t launch_cheb_acc_init(const double* f0, int n, const double* g, int N, int n_w, double* F,
+                                hipStream_t st);
+hipError_t launch_cheb_step_acc(const double* A, int n, const double* fc, const double* fp, double* fn,
+                                double a, double b, int first, const double* g, int N, int m_next,
+                                int n_w, double* F, hipStream_t st);
+hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, int n_c, size_t ng,
+                                  const double* F, int n_out, double* dens, hipStream_t st);
 // out = w / sqrt(*bsq), bsq on the device
 hipError_t launch_scale_norm(const double* w, int n, const double* bsq, double* out, hipStream_t st);
 }  // namespace bse

@@ -350,6 +350,113 @@ __global__ void k_cheb_sigma(const double* __restrict__ D, int M, double a, doub
 }
 
 // ---------------------------------------------------------------------------
+// Frequency-resolved exciton states (Eq. 8): F_q = sum_{m < N} g_m(omega_q)
+// T_m(A~) f^0 for the three dipole start vectors, accumulated during the
+// full three-term recursion, and their exciton densities
+// 2 sum_ia F_ia phi_i phi_a on the grid.
+// ---------------------------------------------------------------------------
+// g[q][m] = (2 - delta_m0)/M sum_k G(a x_k + b - omega_q) cos(m th_k),
+// th_k = pi (k + 1/2)/M; the node Gaussians of a block's omega are staged in
+// LDS 256 nodes at a time
+__global__ void __launch_bounds__(256) k_cheb_coef(const double* __restrict__ w, int N, int M,
+                                                   double a, double b, double sig,
+                                                   double* __restrict__ g) {
+  __shared__ double gk[256], tk[256];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  const double om = w[q];
+  const double norm = 1.0 / (sig * sqrt(2.0 * M_PI));
+  double acc = 0;
+  for (int k0 = 0; k0 < M; k0 += 256) {
+    __syncthreads();
+    const int k = k0 + (int)threadIdx.x;
+    if (k < M) {
+      const double th = M_PI * (k + 0.5) / M;
+      const double z = (a * cos(th) + b - om) / sig;
+      gk[threadIdx.x] = norm * exp(-0.5 * z * z);
+      tk[threadIdx.x] = th;
+    }
+    __syncthreads();
+    const int kn = min(256, M - k0);
+    if (m < N)
+      for (int j = 0; j < kn; ++j) acc += gk[j] * cos(m * tk[j]);
+  }
+  if (m < N) g[(size_t)q * N + m] = (m == 0 ? 1.0 : 2.0) * acc / M;
+}
+
+// F[q][p][i] = g[q][0] f0[p][i]
+__global__ void k_cheb_acc_init(const double* __restrict__ f0, int n, const double* __restrict__ g,
+                                int N, int n_w, double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  for (int q = 0; q < n_w; ++q) F[(size_t)q * 3 * n + i] = g[(size_t)q * N] * f0[i];
+}
+
+// one recursion step (one wave per row), fn = f^{m_next}, and
+// F[q][p][row] += g[q][m_next] fn[p][row]
+__global__ void __launch_bounds__(256) k_cheb_step_acc(const double* __restrict__ A, int n,
+                                                       const double* __restrict__ fc,
+                                                       const double* __restrict__ fp,
+                                                       double* __restrict__ fn, double ia, double b,
+                                                       int first, const double* __restrict__ g, int N,
+                                                       int m_next, int n_w, double* __restrict__ F) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + w;
+  if (row >= n) return;
+  const double* ar = A + (size_t)row * n;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int j = lane; j < n; j += 64) {
+    const double v = ar[j];
+    s0 += v * fc[j];
+    s1 += v * fc[n + j];
+    s2 += v * fc[2 * n + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+    s2 += __shfl_down(s2, off, 64);
+  }
+  if (lane == 0) {
+    const double sp[3] = {s0, s1, s2};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double cur = fc[(size_t)p * n + row];
+      const double t = (sp[p] - b * cur) * ia;
+      const double nx = first ? t : 2.0 * t - fp[(size_t)p * n + row];
+      fn[(size_t)p * n + row] = nx;
+      for (int q = 0; q < n_w; ++q)
+        F[((size_t)q * 3 + p) * n + row] += g[(size_t)q * N + m_next] * nx;
+    }
+  }
+}
+
+// dens[k][r] = 2 sum_i phi_{v0+i}(r) sum_a F[k][i n_c + a] phi_{c0+a}(r) for
+// the (up to) 8 outputs k = 8 blockIdx.y + kk < n_out; one thread per point
+__global__ void __launch_bounds__(256) k_exciton_density(const double* __restrict__ phi, int v0, int c0,
+                                                         int n_o, int n_c, size_t ng,
+                                                         const double* __restrict__ F, int n_out,
+                                                         double* __restrict__ dens) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.y * 8, kn = min(8, n_out - k0);
+  if (r >= ng) return;
+  const int n = n_o * n_c;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < n_o; ++i) {
+    const double pv = phi[(size_t)(v0 + i) * ng + r];
+    for (int a = 0; a < n_c; ++a) {
+      const double t = pv * phi[(size_t)(c0 + a) * ng + r];
+      const double* fk = F + (size_t)k0 * n + i * n_c + a;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        if (kk < kn) acc[kk] += fk[(size_t)kk * n] * t;
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+    if (kk < kn) dens[(size_t)(k0 + kk) * ng + r] = 2.0 * acc[kk];
+}
+
+// ---------------------------------------------------------------------------
 // matrix-free A f in the mixed hole-grid representation (Eq. 6), FP64: f, Tf
 // and out are [n_o][ng] real fields of the valence window; W_ij comes from
 // the [n_ij][ng] stack of pairs i <= j in row order.
@@ -593,6 +700,31 @@ hipError_t launch_cheb_spectrum(const double* part, int K, int nblk, double* mu,
   if (n_w > 0)
     hipLaunchKernelGGL(k_cheb_sigma, dim3((n_w + 255) / 256), dim3(256), 0, st, D, M, a, b, w, n_w, sig,
                        out);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_coef(const double* w, int n_w, int N, int M, double a, double b, double sig,
+                            double* g, hipStream_t st) {
+  if (n_w <= 0 || N <= 0 || M <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cheb_coef, dim3((N + 255) / 256, n_w), dim3(256), 0, st, w, N, M, a, b, sig, g);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_acc_init(const double* f0, int n, const double* g, int N, int n_w, double* F,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_cheb_acc_init, dim3((3 * n + 255) / 256), dim3(256), 0, st, f0, n, g, N, n_w, F);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_step_acc(const double* A, int n, const double* fc, const double* fp, double* fn,
+                                double a, double b, int first, const double* g, int N, int m_next,
+                                int n_w, double* F, hipStream_t st) {
+  hipLaunchKernelGGL(k_cheb_step_acc, dim3(cheb_blocks(n)), dim3(256), 0, st, A, n, fc, fp, fn, 1.0 / a,
+                     b, first, g, N, m_next, n_w, F);
+  return hipGetLastError();
+}
+hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, int n_c, size_t ng,
+                                  const double* F, int n_out, double* dens, hipStream_t st) {
+  if (n_out <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_exciton_density, dim3((unsigned)((ng + 255) / 256), (n_out + 7) / 8), dim3(256), 0,
+                     st, phi, v0, c0, n_o, n_c, ng, F, n_out, dens);
   return hipGetLastError();
 }
 hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,

@@ -104,6 +104,49 @@ def test_tiny24_chebyshev_spectrum(tiny_a, precision):
     assert e.value.code == bse.BSE_ERR_ARG
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiny24_exciton_states(tiny_a, precision):
+    """Frequency-resolved exciton states (Eq. 8) and their densities
+    against the oracle on the oracle's A, dipoles and interval, at two
+    exciton energies, between two, and above the spectrum.  FP64: the
+    recursion's rounding; mixed: A agrees to ~1e-7 Ha, which moves states
+    broadened by 3 mHa by ~1e-7/3e-3 of their size."""
+    from paper_2205_06690_amd import bse
+    spec, sysd, A_o, f0 = tiny_a
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    with pytest.raises(bse.BseError) as e:
+        s.exciton_states(8, [0.1], 0.003)
+    assert e.value.code == bse.BSE_ERR_STATE
+    s.build_a(spec.n_o, spec.n_c)
+    lo, hi = obse.spectral_bounds(A_o)
+    a, b = obse.chebyshev_scale(lo, hi)
+    sig = 0.003
+    n_mom = int(6 * a / sig)
+    w = np.linalg.eigvalsh(A_o)
+    wl = np.array([w[0], 0.5 * (w[0] + w[1]), w[3], w[-1] + 0.004])
+    F_o = obse.chebyshev_states(A_o, f0, n_mom, a, b, wl, sig).transpose(0, 2, 1)   # [q][p][n]
+    F, dn, bo = s.exciton_states(n_mom, wl, sig, bounds=(lo, hi))
+    assert np.allclose(bo, [lo, hi])
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    v0 = spec.n_occ - spec.n_o
+    phv, phc = phi[v0:spec.n_occ], phi[spec.n_occ:spec.n_occ + spec.n_c]
+    dn_o = np.stack([[obse.exciton_density(phv, phc, F_o[q, p]) for p in range(3)]
+                     for q in range(len(wl))])
+    ef = np.abs(F - F_o).max() / np.abs(F_o).max()
+    ed = np.abs(dn - dn_o).max() / np.abs(dn_o).max()
+    say(f"exciton states prec {precision}: n_mom {n_mom}, states {ef:.2e}, densities {ed:.2e}")
+    if precision == 0:
+        assert ef < 1e-8 and ed < 1e-8
+    else:
+        assert ef < 1e-3 and ed < 1e-3
+    # without densities, and the argument checks
+    F2, dn2, _ = s.exciton_states(n_mom, wl, sig, bounds=(lo, hi), densities=False)
+    assert dn2 is None and np.array_equal(F2, F)
+    with pytest.raises(bse.BseError) as e:
+        s.exciton_states(n_mom, np.linspace(0, 1, 9), sig)
+    assert e.value.code == bse.BSE_ERR_ARG
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-3)])
 def test_tiny24_apply_a_mixed(precision, tol):
     """Matrix-free A f (Eq. 6) against the oracle on random virtual-space

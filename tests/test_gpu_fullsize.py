@@ -73,6 +73,10 @@ def test_mid64_bench_batch_w_and_a_block():
     occ = np.abs((Afr @ Po.T) * dvol).max() / np.abs(Afr).max()
     sym_l = np.sum(fr[1] * Afr[0]) * dvol
     sym_r = np.sum(Afr[1] * fr[0]) * dvol
+    # frequency-resolved exciton states (Eq. 8) at the four lowest excitons
+    wq = om[:4].copy()
+    Fq, dnq, _ = s.exciton_states(n_mom, wq, sig, bounds=bo)
+    sg_q, _, _ = s.chebyshev_spectrum(n_mom, wq, sig, bounds=bo)
     s.close()
     say(f"mid64: A f vs assembled A {ea:.2e}, occupied overlap {occ:.2e}, "
         f"symmetry {abs(sym_l - sym_r) / abs(sym_l):.2e}")
@@ -121,6 +125,30 @@ def test_mid64_bench_batch_w_and_a_block():
     el = np.abs(sg_c[low] - sg_l[low]).max() / np.abs(sg_l[low]).max()
     say(f"mid64: chebyshev vs lanczos below the 20th exciton - 6 sigma {el:.2e}")
     assert el < 1e-6
+    # exciton states: the broadened delta of this A applied to f0 (eigenpairs
+    # of the same A), <f0|f(w)> is the residue path's sigma(w)/w, and each
+    # density's dipole is 2 F.f0 with a vanishing charge
+    ev, X = np.linalg.eigh(A)
+    G = np.exp(-0.5 * ((ev[None, :] - wq[:, None]) / sig) ** 2) / (sig * np.sqrt(2 * np.pi))
+    F_ref = np.einsum("qk,nk,kp->qpn", G, X, X.T @ f0)
+    ef = np.abs(Fq - F_ref).max() / np.abs(F_ref).max()
+    es = np.abs(wq * np.einsum("np,qpn->q", f0, Fq) - sg_q).max() / np.abs(sg_q).max()
+    xs = grid.coords()
+    ed, eq = 0.0, 0.0
+    for q in range(len(wq)):
+        for p in range(3):
+            eq = max(eq, abs(np.sum(dnq[q, p]) * grid.dv) / np.abs(Fq[q, p]).sum())
+            for ax in range(3):
+                shp = [1, 1, 1]
+                shp[ax] = -1
+                mom = np.sum(dnq[q, p] * (xs[ax] - 0.5 * spec.n * spec.h).reshape(shp)) * grid.dv
+                ref = 2.0 * Fq[q, p] @ f0[:, ax]
+                ed = max(ed, abs(mom - ref) / np.abs(2.0 * Fq[q, p]).sum() / np.abs(f0).max())
+    say(f"mid64: exciton states vs eigenpairs {ef:.2e}, vs residue spectrum {es:.2e}, "
+        f"density dipole {ed:.2e}, charge {eq:.2e}")
+    assert ef < 1e-7
+    assert es < 1e-9
+    assert ed < 1e-9 and eq < 1e-9
 
 
 @pytest.mark.timeout(400)
