@@ -230,6 +230,39 @@ def chebyshev_residues_op(apply, f0_list, n_mom: int, a: float, b: float, inner)
     return R
 
 
+def chebyshev_states_op(apply, f0_list, n_mom: int, a: float, b: float, w_grid: np.ndarray,
+                        sigma: float, n_nodes: int | None = None) -> np.ndarray:
+    """Eq. 8 for a linear operator given by ``apply``: for each start vector
+    f0_p, sum_{n < n_mom} g_n(omega) T_n(A~) f0_p with A~ = (A - b)/a, by
+    the three-term recursion; [n_w, n_pol, *f0.shape]."""
+    g = chebyshev_coefficients(np.asarray(w_grid, dtype=float), n_mom, a, b, sigma, n_nodes)
+    out = np.zeros((g.shape[0], len(f0_list)) + np.shape(f0_list[0]))
+    for p, f0 in enumerate(f0_list):
+        f_prev = f0
+        out[:, p] = g[:, 0].reshape((-1,) + (1,) * f0.ndim) * f0
+        if n_mom == 1:
+            continue
+        f_cur = (apply(f0) - b * f0) / a
+        out[:, p] += g[:, 1].reshape((-1,) + (1,) * f0.ndim) * f_cur
+        for n in range(2, n_mom):
+            f_next = 2.0 * (apply(f_cur) - b * f_cur) / a - f_prev
+            out[:, p] += g[:, n].reshape((-1,) + (1,) * f0.ndim) * f_next
+            f_prev, f_cur = f_cur, f_next
+    return out
+
+
+def mixed_amplitudes(grid: Grid, phi_a: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Electron-hole amplitudes of a mixed-representation state:
+    f_ia = <phi_a|f_i> = h^3 sum_r phi_a(r) f_i(r); [n_o, n_a]."""
+    n_o, n_a = f.shape[0], phi_a.shape[0]
+    return (f.reshape(n_o, -1) @ phi_a.reshape(n_a, -1).T) * grid.dv
+
+
+def mixed_exciton_density(phi_v: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Exciton density of a mixed-representation state: 2 sum_i phi_i f_i."""
+    return 2.0 * np.sum(phi_v * f, axis=0)
+
+
 def mixed_dipole_start(grid: Grid, phi_occ: np.ndarray, n_o: int):
     """Start vectors of the mixed representation, one per axis:
     f0_j = Q (r_axis - box centre) phi_j for the valence window (the last

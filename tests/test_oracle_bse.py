@@ -246,6 +246,9 @@ def test_exciton_density_charge_and_dipole(gauss):
     dip = sum(F[i * nc + a] * _pair(Rv[i], Rc[a])[0] * (_pair(Rv[i], Rc[a])[1] - c)
               for i in range(len(Rv)) for a in range(nc))
     assert abs(np.sum(dn) * grid.dv - 2 * q) < 1e-9
+    # the mixed-representation density of f_i = sum_a F_ia phi_a is the same
+    f_mixed = np.tensordot(F.reshape(len(Rv), nc), phc, axes=(1, 0))
+    assert np.abs(bse.mixed_exciton_density(phv, f_mixed) - dn).max() < 1e-12 * np.abs(dn).max()
     xs = grid.coords()
     for ax in range(3):
         shp = [1, 1, 1]
@@ -339,6 +342,27 @@ def test_chebyshev_residues_operator_form_closed_form():
     th = np.arccos((w - b) / a)
     Rc = np.array([(np.cos(n * th)[:, None] * p).sum(axis=0) for n in range(120)])
     assert np.abs(R - Rc).max() < 1e-12 * np.abs(Rc).max()
+
+
+def test_chebyshev_states_operator_form_equals_matrix_form():
+    """The operator recursion of Eq. 8 with A applied as a product equals
+    the matrix form, itself pinned to the eigenpairs."""
+    A, f0 = _sym(16, 13)
+    a, b = bse.chebyshev_scale(*bse.spectral_bounds(A))
+    wg = np.array([0.3, 0.55, 0.8])
+    Fm = bse.chebyshev_states(A, f0, 300, a, b, wg, 0.03)               # [q, n, p]
+    Fo = bse.chebyshev_states_op(lambda x: A @ x, [f0[:, p] for p in range(3)], 300, a, b, wg, 0.03)
+    assert np.abs(Fo - Fm.transpose(0, 2, 1)).max() < 1e-12 * np.abs(Fm).max()
+
+
+def test_mixed_amplitudes_recover_conduction_coefficients(mixed_system):
+    """For f_i = sum_a c_ia phi_a over orthonormal eigenstates the
+    amplitudes <phi_a|f_i> are c_ia, and zero on the occupied orbitals."""
+    spec, grid, v, phi, eps, w = mixed_system
+    c = np.random.default_rng(14).standard_normal((2, 4))
+    f = np.tensordot(c, phi[6:10], axes=(1, 0))
+    assert np.abs(bse.mixed_amplitudes(grid, phi[6:10], f) - c).max() < 1e-9
+    assert np.abs(bse.mixed_amplitudes(grid, phi[:6], f)).max() < 1e-9
 
 
 def test_mixed_dipole_start_projects_to_eh_dipoles(mixed_system):
