@@ -194,6 +194,25 @@ bse_status bse_exciton_states(bse_system* sys, int32_t n_mom, double e_min, doub
                               int32_t n_w, const double* w_list, double sigma_broad,
                               double* f_out, double* dens_out, double* bounds);
 
+/* Frequency-resolved exciton states of the mixed representation (Eq. 8 with
+ * A applied matrix-free as in bse_apply_A_mixed, Eq. 6), the paper's route
+ * to exciton maps: for each frequency w_list[q] and each axis, the grid
+ * vectors f_j(r; w_q) = sum_{n < n_mom} g_n(w_q) T_n(A~) f0_j over the
+ * valence window of the last bse_build_A, from the start vectors
+ * f0_j = Q (r_axis - box centre) phi_j of bse_chebyshev_mixed, with A~, g_n
+ * and the interval [e_min, e_max] (required) as in bse_chebyshev_mixed.
+ * Outputs (host, caller-allocated): the electron-hole amplitudes
+ * f_ia = h^3 sum_r phi_a f_i on the n_a lowest virtual orbitals (a = n_occ
+ * .. n_occ + n_a - 1, any n_a up to the orbitals set, not only the n_c of
+ * A) in f_out[n_w][3][n_o][n_a]; the exciton densities 2 sum_i phi_i f_i in
+ * dens_out[n_w][3][nx*ny*nz] (nullable).  FP64 on the device; costs
+ * 3 (n_mom - 1) applications of A.  1 <= n_w <= 8; n_a = 0 requires
+ * dens_out.  Errors: BSE_ERR_STATE before bse_build_A; BSE_ERR_ARG on bad
+ * sizes, a missing interval or n_o * n_occ > 8192. */
+bse_status bse_exciton_states_mixed(bse_system* sys, int32_t n_mom, double e_min, double e_max,
+                                    int32_t n_w, const double* w_list, double sigma_broad, int32_t n_a,
+                                    double* f_out, double* dens_out);
+
 /* Uneven batch: the W-action for several systems at once (different grids,
  * orbital counts and pair counts, same device).  System k propagates
  * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and

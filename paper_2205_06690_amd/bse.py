@@ -32,7 +32,7 @@ EXPORTS = (
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
-    "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states",
+    "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
 )
 
 
@@ -80,6 +80,8 @@ def _load():
     lib.bse_apply_A_mixed.argtypes = [P, C.c_int32, dp, dp]
     lib.bse_exciton_states.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp, C.c_double,
                                        dp, dp, dp]
+    lib.bse_exciton_states_mixed.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
+                                             C.c_double, C.c_int32, dp, dp]
     lib.bse_chebyshev_mixed.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                         C.c_double, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
@@ -259,6 +261,20 @@ class System:
         _check(LIB.bse_exciton_states(self._h, n_mom, lo, hi, wl.size, _dptr(wl), sigma, _dptr(F),
                                       _dptr(dn) if densities else None, _dptr(bo)))
         return F, dn, bo
+
+    def exciton_states_mixed(self, n_mom: int, bounds, w_list, sigma: float = 0.08 / 27.211386245988,
+                             n_a: int = 0, densities: bool = True):
+        """Exciton states of the mixed representation (Eq. 8 with Eq. 6):
+        (amplitudes [n_w][3][n_o][n_a] or None, densities [n_w][3][nx, ny, nz]
+        or None); bounds = (e_min, e_max) of A on the virtual space."""
+        wl = np.ascontiguousarray(w_list, dtype=np.float64).reshape(-1)
+        n_o = getattr(self, "a_window", (1, 0))[0]
+        amp = np.empty((wl.size, 3, n_o, n_a)) if n_a > 0 else None
+        dn = np.empty((wl.size, 3, self.n, self.n, self.n)) if densities else None
+        _check(LIB.bse_exciton_states_mixed(self._h, n_mom, float(bounds[0]), float(bounds[1]), wl.size,
+                                            _dptr(wl), sigma, n_a, _dptr(amp) if amp is not None else None,
+                                            _dptr(dn) if dn is not None else None))
+        return amp, dn
 
     def chebyshev_spectrum(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
                            bounds=None):

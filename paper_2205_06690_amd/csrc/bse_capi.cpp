@@ -1033,6 +1033,75 @@ void exciton_states(bse_system* s, int n_mom, double e_min, double e_max, int n_
   }
 }
 
+// Frequency-resolved exciton states of the mixed representation (Eq. 8 with
+// the matrix-free A of Eq. 6), one polarisation at a time: the full
+// recursion on the grid vectors f_j(r) from the mixed dipole start with
+// F_q += g_m(omega_q) f^m at every step, then the electron-hole amplitudes
+// f_ia = h^3 sum_r phi_a f_i on the n_a lowest virtual orbitals and the
+// exciton densities 2 sum_i phi_i f_i.
+void exciton_states_mixed(bse_system* s, int n_mom, double e_min, double e_max, int n_w,
+                          const double* w_list, double sig, int n_a, double* f_out, double* dens_out) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_exciton_states_mixed: call bse_build_A first");
+  const int n_o = s->a_no, S = s->cfg.n_occ;
+  const int n_virt = s->n_orb - S;
+  if (n_mom < 2 || !(e_min < e_max) || n_w < 1 || n_w > 8 || !w_list || !(sig > 0) || n_a < 0 ||
+      n_a > n_virt || (n_a > 0 && !f_out) || (n_a == 0 && !dens_out))
+    fail(BSE_ERR_ARG, "bse_exciton_states_mixed: bad arguments");
+  if ((size_t)n_o * S * sizeof(double) > 64 * 1024)
+    fail(BSE_ERR_ARG, "bse_exciton_states_mixed: n_o * n_occ above 8192");
+  hipStream_t st = s->stream;
+  const size_t ng = s->ng, len = (size_t)n_o * ng;
+  const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
+  DBuf fv, af, part, g, F, wd, cq, pq, amp, pa, rho;
+  fv.alloc(sizeof(double) * 3 * len);               // [3 rotating vectors][n_o][ng]
+  af.alloc(sizeof(double) * len);
+  part.alloc(sizeof(double) * 6 * (size_t)mixed_cheb_blocks());
+  g.alloc(sizeof(double) * (size_t)n_w * n_mom);
+  F.alloc(sizeof(double) * (size_t)n_w * len);
+  wd.alloc(sizeof(double) * n_w);
+  cq.alloc(sizeof(double) * (size_t)n_o * S);
+  pq.alloc(sizeof(double) * std::max(gemm_part_elems(n_o, S, ng), gemm_part_elems(n_o, std::max(n_a, 1), ng)));
+  if (n_a > 0) amp.alloc(sizeof(double) * (size_t)n_o * n_a);
+  if (dens_out) rho.alloc(sizeof(double) * ng);
+  HIPC(hipMemcpyAsync(wd.p, w_list, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
+  HIPC(launch_cheb_coef(wd.as<double>(), n_w, n_mom, 2 * n_mom, a, b, sig, g.as<double>(), st));
+  double* buf = fv.as<double>();
+  auto vec = [&](int k) { return buf + (size_t)(k % 3) * len; };
+  const double* phv = s->phi64.as<double>() + (size_t)(S - n_o) * ng;
+  const double* pha = s->phi64.as<double>() + (size_t)S * ng;
+  auto* t = s->timer.begin("exciton_states_mixed");
+  for (int p = 0; p < 3; ++p) {
+    double* f0 = vec(0);
+    HIPC(launch_mixed_dipole(phv, n_o, s->n, s->cfg.h, p, f0, st));
+    HIPC(launch_gemm_f64(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st));
+    HIPC(launch_project_out(f0, n_o, s->phi64.as<double>(), S, cq.as<double>(), ng, st));
+    HIPC(launch_states_acc(F.as<double>(), f0, g.as<double>(), n_mom, 0, n_w, len, 1, st));
+    for (int m = 0; m + 1 < n_mom; ++m) {
+      apply_a_mixed_device(s, vec(m), af.as<double>());
+      HIPC(launch_mixed_cheb_update(af.as<double>(), vec(m), vec(m + 2), vec(m + 1), len, a, b,
+                                    m == 0 ? 1 : 0, s->dv, p, part.as<double>(), st));
+      HIPC(launch_states_acc(F.as<double>(), vec(m + 1), g.as<double>(), n_mom, m + 1, n_w, len, 0, st));
+    }
+    for (int q = 0; q < n_w; ++q) {
+      const double* Fq = F.as<double>() + (size_t)q * len;
+      if (n_a > 0) {
+        HIPC(launch_gemm_f64(Fq, n_o, pha, n_a, ng, s->dv, pq.as<double>(), amp.as<double>(), st));
+        HIPC(hipMemcpyAsync(f_out + ((size_t)q * 3 + p) * n_o * n_a, amp.p, sizeof(double) * n_o * n_a,
+                            hipMemcpyDeviceToHost, st));
+      }
+      if (dens_out) {
+        HIPC(launch_mixed_density(phv, Fq, n_o, ng, rho.as<double>(), st));
+        HIPC(hipMemcpyAsync(dens_out + ((size_t)q * 3 + p) * ng, rho.p, sizeof(double) * ng,
+                            hipMemcpyDeviceToHost, st));
+      }
+      HIPC(hipStreamSynchronize(st));   // amp and rho are reused
+    }
+  }
+  s->timer.end(t);
+  HIPC(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------------------
 // autotuner: x-tile width and plane-pass block size for this system's grid,
 // batch size and precision, timed on the system's own buffers; results are
@@ -1578,6 +1647,14 @@ bse_status bse_exciton_states(bse_system* s, int32_t n_mom, double e_min, double
                               double* bounds) {
   API_BEGIN
   exciton_states(s, n_mom, e_min, e_max, n_w, w_list, sigma_broad, f_out, dens_out, bounds);
+  API_END
+}
+
+bse_status bse_exciton_states_mixed(bse_system* s, int32_t n_mom, double e_min, double e_max,
+                                    int32_t n_w, const double* w_list, double sigma_broad, int32_t n_a,
+                                    double* f_out, double* dens_out) {
+  API_BEGIN
+  exciton_states_mixed(s, n_mom, e_min, e_max, n_w, w_list, sigma_broad, n_a, f_out, dens_out);
   API_END
 }
 

@@ -67,6 +67,9 @@ hipError_t launch_cheb_acc_init(const double* f0, int n, const double* g, int N,
 hipError_t launch_cheb_step_acc(const double* A, int n, const double* fc, const double* fp, double* fn,
                                 double a, double b, int first, const double* g, int N, int m_next,
                                 int n_w, double* F, hipStream_t st);
+// F[n_w][len] = / += g[.][m] f over grid vectors (mixed representation)
+hipError_t launch_states_acc(double* F, const double* f, const double* g, int N, int m, int n_w,
+                             size_t len, int init, hipStream_t st);
 hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, int n_c, size_t ng,
                                   const double* F, int n_out, double* dens, hipStream_t st);
 // out = w / sqrt(*bsq), bsq on the device

@@ -456,6 +456,21 @@ __global__ void __launch_bounds__(256) k_exciton_density(const double* __restric
     if (kk < kn) dens[(size_t)(k0 + kk) * ng + r] = 2.0 * acc[kk];
 }
 
+// F[q][i] = g[q][m] f[i] (init) or F[q][i] += g[q][m] f[i], i < len: the
+// Eq. 8 sum over grid vectors of the mixed representation
+__global__ void __launch_bounds__(256) k_states_acc(double* __restrict__ F, const double* __restrict__ f,
+                                                   const double* __restrict__ g, int N, int m, int n_w,
+                                                   size_t len, int init) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (size_t)gridDim.x * 256) {
+    const double v = f[i];
+    for (int q = 0; q < n_w; ++q) {
+      const double c = g[(size_t)q * N + m] * v;
+      double* d = F + (size_t)q * len + i;
+      *d = init ? c : *d + c;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // matrix-free A f in the mixed hole-grid representation (Eq. 6), FP64: f, Tf
 // and out are [n_o][ng] real fields of the valence window; W_ij comes from
@@ -718,6 +733,12 @@ hipError_t launch_cheb_step_acc(const double* A, int n, const double* fc, const 
                                 int n_w, double* F, hipStream_t st) {
   hipLaunchKernelGGL(k_cheb_step_acc, dim3(cheb_blocks(n)), dim3(256), 0, st, A, n, fc, fp, fn, 1.0 / a,
                      b, first, g, N, m_next, n_w, F);
+  return hipGetLastError();
+}
+hipError_t launch_states_acc(double* F, const double* f, const double* g, int N, int m, int n_w,
+                             size_t len, int init, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<size_t>((len + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_states_acc, dim3(blocks), dim3(256), 0, st, F, f, g, N, m, n_w, len, init);
   return hipGetLastError();
 }
 hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, int n_c, size_t ng,

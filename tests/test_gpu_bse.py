@@ -179,14 +179,11 @@ def test_tiny24_apply_a_mixed(precision, tol):
     assert e.value.code == bse.BSE_ERR_STATE
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
-def test_tiny24_chebyshev_mixed(precision, tol):
-    """The paper's algorithm: Chebyshev residues with A applied matrix-free
-    in the mixed representation, against the oracle's operator recursion
-    from the same dipole start vectors and interval (the oracle's extreme
-    eigenvalues of Q A-bar Q, widened by 2 %).  Mixed precision: the
-    library's W moves A f by ~3e-9 relative, which the recursion carries
-    about linearly in n."""
+@pytest.fixture(scope="module")
+def tiny_mixed():
+    """The oracle's mixed-representation operator on tiny24 (its own W_ij)
+    and an interval from its extreme eigenvalues on the virtual space,
+    widened by 2 %."""
     from scipy.sparse.linalg import LinearOperator, eigsh
     spec, sysd = system("tiny24")
     pairs = inputs.ij_pairs(spec)
@@ -211,6 +208,18 @@ def test_tiny24_chebyshev_mixed(precision, tol):
     lmax = eigsh(lin, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
     lmin = eigsh(lin, k=1, which="SA", return_eigenvectors=False, tol=1e-6)[0]
     lo, hi = lmin - 0.02 * (lmax - lmin), lmax + 0.02 * (lmax - lmin)
+    return spec, sysd, grid, phi, op, lo, hi
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
+def test_tiny24_chebyshev_mixed(tiny_mixed, precision, tol):
+    """The paper's algorithm: Chebyshev residues with A applied matrix-free
+    in the mixed representation, against the oracle's operator recursion
+    from the same dipole start vectors and interval.  Mixed precision: the
+    library's W moves A f by ~3e-9 relative, which the recursion carries
+    about linearly in n."""
+    spec, sysd, grid, phi, op, lo, hi = tiny_mixed
+    phio = phi[:spec.n_occ]
     a, b = obse.chebyshev_scale(lo, hi)
     n_mom = 200
     f0 = obse.mixed_dipole_start(grid, phio, spec.n_o)
@@ -226,3 +235,38 @@ def test_tiny24_chebyshev_mixed(precision, tol):
     say(f"chebyshev mixed prec {precision}: interval ({lo:.3f}, {hi:.3f}) Ha, residues {er:.2e}, "
         f"spectrum {es:.2e}")
     assert er < tol and es < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_tiny24_exciton_states_mixed(tiny_mixed, precision, tol):
+    """Exciton states of the mixed representation (Eq. 8 with Eq. 6) against
+    the oracle's operator form: amplitudes on every virtual orbital set
+    (the states range over the whole virtual space of the grid; the
+    amplitudes are their projections), and the densities 2 sum_i phi_i f_i."""
+    from paper_2205_06690_amd import bse
+    spec, sysd, grid, phi, op, lo, hi = tiny_mixed
+    phio = phi[:spec.n_occ]
+    n_virt = phi.shape[0] - spec.n_occ
+    n_a = min(n_virt, spec.n_c + 2)
+    a, b = obse.chebyshev_scale(lo, hi)
+    n_mom, sig = 120, 0.05 * (hi - lo)
+    wl = np.array([lo + 0.1 * (hi - lo), lo + 0.3 * (hi - lo), 0.5 * (lo + hi)])
+    f0 = obse.mixed_dipole_start(grid, phio, spec.n_o)
+    Fo = obse.chebyshev_states_op(op, f0, n_mom, a, b, wl, sig)          # [q, p, n_o, ...]
+    v0 = spec.n_occ - spec.n_o
+    amp_o = np.stack([[obse.mixed_amplitudes(grid, phi[spec.n_occ:spec.n_occ + n_a], Fo[q, p])
+                       for p in range(3)] for q in range(len(wl))])
+    dn_o = np.stack([[obse.mixed_exciton_density(phi[v0:spec.n_occ], Fo[q, p]) for p in range(3)]
+                     for q in range(len(wl))])
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    s.build_a(spec.n_o, spec.n_c)
+    amp, dn = s.exciton_states_mixed(n_mom, (lo, hi), wl, sig, n_a=n_a)
+    ea = np.abs(amp - amp_o).max() / np.abs(amp_o).max()
+    ed = np.abs(dn - dn_o).max() / np.abs(dn_o).max()
+    say(f"exciton states mixed prec {precision}: n_a {n_a}, amplitudes {ea:.2e}, densities {ed:.2e}")
+    assert ea < tol and ed < tol
+    amp2, dn2 = s.exciton_states_mixed(n_mom, (lo, hi), wl[:1], sig, n_a=0)
+    assert amp2 is None and np.allclose(dn2[0], dn[0], rtol=0, atol=1e-14 * np.abs(dn).max())
+    with pytest.raises(bse.BseError) as e:
+        s.exciton_states_mixed(n_mom, (lo, hi), wl, sig, n_a=n_virt + 1)
+    assert e.value.code == bse.BSE_ERR_ARG
