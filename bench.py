@@ -170,7 +170,7 @@ def bench_uneven(args):
 
 def bench_surrogate(args):
     """The learned screening surrogate: trained on 4096 pair densities of 20
-    mid-size molecules (seeds 100-119), judged on 512 held-out pairs of 3
+    mid-size molecules (seeds 100-119), evaluated on 512 held-out pairs of 3
     others (seeds 200-202) against the propagation that generated them."""
     import torch
     from paper_2205_06690_amd import bse, surrogate

@@ -256,7 +256,7 @@ void bse_destroy_system(bse_system* sys);
  * Screening surrogate: a Fourier neural operator that maps the scaled
  * source potential q_ij / s_ij (s_ij its RMS) plus molecule descriptor
  * channels to W^pol_ij / s_ij on the same grid.  It is trained on pairs that
- * bse_apply_W generates and is judged by them; it does not replace the
+ * bse_apply_W generates and its errors are measured on them; it does not replace the
  * propagation unless its prediction passes the caller's checks.
  *
  * Network: h0 = P x + p; for l < layers: z = W_l h + b_l + S_l h,

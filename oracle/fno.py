@@ -4,7 +4,7 @@ The surrogate maps the source potential of a pair density (scaled to unit
 RMS) together with two channels describing the molecule (ground-state
 density and V_ext) to the induced part W^pol of the screened interaction,
 in the same scaling.  The paper has no such network; it stands beside the
-TD-Hartree propagation, which generates its training data and judges it.
+TD-Hartree propagation, which generates its training data and checks its predictions.
 
 Network (a Fourier neural operator):
   h_0 = P x + p                                  (lift, per grid point)
