@@ -264,7 +264,7 @@ def main():
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(pairs would shard across GPUs with one all-gather of A; not built)",
               file=sys.stderr)
         sys.exit(2)
