@@ -160,6 +160,7 @@ struct bse_system {
   // surrogate descriptors and buffers
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
   DBuf mx_f, mx_tf, mx_out, mx_rho, mx_dv, mx_c, mx_part, mx_eps;  // matrix-free A f
+  int mx_eps_v0 = -1, mx_eps_n = 0;   // valence window whose eps mx_eps holds
   double n0_scale = 0, v_scale = 0;
 };
 
@@ -786,6 +787,17 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
 // kinetic term by the FFT pipeline with the k^2/2 multiplier, the Hartree
 // term from dn = 2 sum phi_i f_i, the exchange-like term from the cached
 // W_ij, then the occupied-space projection as a GEMM and an update.
+// C[n_o][S] = dv sum_r f_i phi_s: the streaming projection kernel for up to
+// 32 fields, the tiled FP64 GEMM beyond; part holds proj_scratch(n_o, S, ng)
+size_t proj_scratch(int n_o, int S, size_t ng) {
+  return n_o <= 32 ? proj_part_elems(n_o, S) : gemm_part_elems(n_o, S, ng);
+}
+void proj_coef(const double* f, int n_o, const double* phi, int S, size_t ng, double dv, double* part,
+               double* C, hipStream_t st) {
+  if (n_o <= 32) HIPC(launch_proj_coef(f, n_o, phi, S, ng, dv, part, C, st));
+  else HIPC(launch_gemm_f64(f, n_o, phi, S, ng, dv, part, C, st));
+}
+
 void apply_a_mixed_device(bse_system* s, const double* f_dev, double* af_dev) {
   const int n_o = s->a_no, S = s->cfg.n_occ;
   const size_t ng = s->ng;
@@ -795,15 +807,19 @@ void apply_a_mixed_device(bse_system* s, const double* f_dev, double* af_dev) {
   s->mx_rho.alloc(sizeof(double) * ng);
   s->mx_dv.alloc(sizeof(double) * ng);
   s->mx_c.alloc(sizeof(double) * (size_t)n_o * S);
-  s->mx_part.alloc(sizeof(double) * gemm_part_elems(n_o, S, ng));
+  s->mx_part.alloc(sizeof(double) * proj_scratch(n_o, S, ng));
   s->work64.alloc(sizeof(cplx<double>) * ng * (size_t)((n_o + 1) / 2));
   if (!s->vdev.p || s->vdev.bytes < sizeof(double) * ng) {
     s->vdev.alloc(sizeof(double) * ng);
     HIPC(hipMemcpy(s->vdev.p, s->vext.data(), sizeof(double) * ng, hipMemcpyHostToDevice));
   }
-  s->mx_eps.alloc(sizeof(double) * n_o);
-  HIPC(hipMemcpyAsync(s->mx_eps.p, s->eps.data() + (S - n_o), sizeof(double) * n_o,
-                      hipMemcpyHostToDevice, st));
+  if (s->mx_eps_v0 != S - n_o || s->mx_eps_n != n_o) {
+    HIPC(hipStreamSynchronize(st));   // earlier applications may still read mx_eps
+    s->mx_eps.alloc(sizeof(double) * n_o);
+    HIPC(hipMemcpy(s->mx_eps.p, s->eps.data() + (S - n_o), sizeof(double) * n_o, hipMemcpyHostToDevice));
+    s->mx_eps_v0 = S - n_o;
+    s->mx_eps_n = n_o;
+  }
   // kinetic term: T f_j for the n_o real fields (two per complex transform)
   PoisArgs<double> a{};
   a.rho = f_dev;
@@ -822,8 +838,8 @@ void apply_a_mixed_device(bse_system* s, const double* f_dev, double* af_dev) {
                             s->cfg.scissors, s->mx_dv.as<double>(), phv, s->wij.as<double>(), n_o, ng,
                             af_dev, st));
   // Q: coefficients on the occupied orbitals, then the update
-  HIPC(launch_gemm_f64(af_dev, n_o, s->phi64.as<double>(), S, ng, s->dv, s->mx_part.as<double>(),
-                       s->mx_c.as<double>(), st));
+  proj_coef(af_dev, n_o, s->phi64.as<double>(), S, ng, s->dv, s->mx_part.as<double>(), s->mx_c.as<double>(),
+            st);
   HIPC(launch_project_out(af_dev, n_o, s->phi64.as<double>(), S, s->mx_c.as<double>(), ng, st));
 }
 
@@ -869,7 +885,7 @@ void chebyshev_mixed(bse_system* s, int n_mom, double e_min, double e_max, int n
   mu.alloc(sizeof(double) * 3 * (size_t)n_mom);
   D.alloc(sizeof(double) * 3 * (size_t)M);
   cq.alloc(sizeof(double) * (size_t)n_o * S);
-  pq.alloc(sizeof(double) * gemm_part_elems(n_o, S, ng));
+  pq.alloc(sizeof(double) * proj_scratch(n_o, S, ng));
   if (n_w > 0) {
     wd.alloc(sizeof(double) * n_w);
     sd.alloc(sizeof(double) * n_w);
@@ -881,7 +897,7 @@ void chebyshev_mixed(bse_system* s, int n_mom, double e_min, double e_max, int n
   for (int p = 0; p < 3; ++p) {
     double* f0 = vec(p, 0);
     HIPC(launch_mixed_dipole(phv, n_o, s->n, s->cfg.h, p, f0, st));
-    HIPC(launch_gemm_f64(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st));
+    proj_coef(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st);
     HIPC(launch_project_out(f0, n_o, s->phi64.as<double>(), S, cq.as<double>(), ng, st));
   }
   for (int k = 0; k < K; ++k)
@@ -1061,7 +1077,7 @@ void exciton_states_mixed(bse_system* s, int n_mom, double e_min, double e_max, 
   F.alloc(sizeof(double) * (size_t)n_w * len);
   wd.alloc(sizeof(double) * n_w);
   cq.alloc(sizeof(double) * (size_t)n_o * S);
-  pq.alloc(sizeof(double) * std::max(gemm_part_elems(n_o, S, ng), gemm_part_elems(n_o, std::max(n_a, 1), ng)));
+  pq.alloc(sizeof(double) * std::max(proj_scratch(n_o, S, ng), proj_scratch(n_o, std::max(n_a, 1), ng)));
   if (n_a > 0) amp.alloc(sizeof(double) * (size_t)n_o * n_a);
   if (dens_out) rho.alloc(sizeof(double) * ng);
   HIPC(hipMemcpyAsync(wd.p, w_list, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
@@ -1074,7 +1090,7 @@ void exciton_states_mixed(bse_system* s, int n_mom, double e_min, double e_max, 
   for (int p = 0; p < 3; ++p) {
     double* f0 = vec(0);
     HIPC(launch_mixed_dipole(phv, n_o, s->n, s->cfg.h, p, f0, st));
-    HIPC(launch_gemm_f64(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st));
+    proj_coef(f0, n_o, s->phi64.as<double>(), S, ng, s->dv, pq.as<double>(), cq.as<double>(), st);
     HIPC(launch_project_out(f0, n_o, s->phi64.as<double>(), S, cq.as<double>(), ng, st));
     HIPC(launch_states_acc(F.as<double>(), f0, g.as<double>(), n_mom, 0, n_w, len, 1, st));
     for (int m = 0; m + 1 < n_mom; ++m) {
@@ -1086,7 +1102,7 @@ void exciton_states_mixed(bse_system* s, int n_mom, double e_min, double e_max, 
     for (int q = 0; q < n_w; ++q) {
       const double* Fq = F.as<double>() + (size_t)q * len;
       if (n_a > 0) {
-        HIPC(launch_gemm_f64(Fq, n_o, pha, n_a, ng, s->dv, pq.as<double>(), amp.as<double>(), st));
+        proj_coef(Fq, n_o, pha, n_a, ng, s->dv, pq.as<double>(), amp.as<double>(), st);
         HIPC(hipMemcpyAsync(f_out + ((size_t)q * 3 + p) * n_o * n_a, amp.p, sizeof(double) * n_o * n_a,
                             hipMemcpyDeviceToHost, st));
       }
@@ -1509,6 +1525,7 @@ bse_status bse_set_orbitals(bse_system* s, int32_t n_orb, const double* phi, con
   s->ready = false;
   s->n_orb = n_orb;
   s->eps.assign(eps, eps + n_orb);
+  s->mx_eps_v0 = -1;
   s->phi64.alloc(sizeof(double) * tot);
   HIPC(hipMemcpy(s->phi64.p, phi, sizeof(double) * tot, hipMemcpyHostToDevice));
   if (s->cfg.precision == BSE_MIXED) {

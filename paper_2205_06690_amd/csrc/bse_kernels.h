@@ -36,6 +36,11 @@ hipError_t launch_mixed_combine(const double* f, const double* tf, const double*
                                 const double* eps_v, double scissors, const double* dv,
                                 const double* phv, const double* wij, int n_o, size_t ng,
                                 double* out, hipStream_t st);
+// C[n_o][S] = dv sum_r f_i(r) phi_s(r) for n_o <= 32 fields (ng a multiple
+// of 32); part holds proj_part_elems(n_o, S) doubles
+size_t proj_part_elems(int n_o, int S);
+hipError_t launch_proj_coef(const double* f, int n_o, const double* phi, int S, size_t ng, double dv,
+                            double* part, double* C, hipStream_t st);
 hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
                               size_t ng, hipStream_t st);
 // mixed-representation Chebyshev: one step of polarisation p over len values

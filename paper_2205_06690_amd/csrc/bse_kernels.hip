@@ -506,6 +506,7 @@ __global__ void k_mixed_combine(const double* __restrict__ f, const double* __re
 }
 
 // out_j -= sum_s C[j][s] phi_s (the occupied-space projection), C staged in LDS
+template <int JB>
 __global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, int n_o,
                                                      const double* __restrict__ phi, int S,
                                                      const double* __restrict__ C, size_t ng) {
@@ -514,7 +515,7 @@ __global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, i
   __syncthreads();
   const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ng) return;
-  constexpr int JB = 8;
+  // JB fields per pass over phi: one pass for n_o <= JB
   for (int j0 = 0; j0 < n_o; j0 += JB) {
     double acc[JB];
 #pragma unroll
@@ -528,6 +529,68 @@ __global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, i
 #pragma unroll
     for (int q = 0; q < JB; ++q)
       if (j0 + q < n_o) out[(size_t)(j0 + q) * ng + r] -= acc[q];
+  }
+}
+
+// Coefficients of n_o fields on S orbitals, C[i][s] = dv sum_r f_i(r)
+// phi_s(r): block (x, y) owns the points [x PB, (x+1) PB) and the orbitals
+// [128 y, 128 y + 128); tiles of PJ_T points of phi (rows padded) and of
+// the fields are staged in LDS, each thread keeps the n_o sums of its
+// orbital in registers, and part[x][i][s] is reduced over x afterwards.
+constexpr int PJ_T = 32, PJ_S = 128, PJ_BLK = 1024;
+template <int NO>
+__global__ void __launch_bounds__(PJ_S) k_proj_coef(const double* __restrict__ f, int n_o,
+                                                    const double* __restrict__ phi, int S, size_t ng,
+                                                    size_t pb, double* __restrict__ part) {
+  __shared__ double lp[PJ_S][PJ_T + 1];
+  __shared__ double lf[NO][PJ_T];
+  const int t = threadIdx.x, s0 = blockIdx.y * PJ_S, s = s0 + t;
+  const size_t r0 = (size_t)blockIdx.x * pb, r1 = min(ng, r0 + pb);
+  double acc[NO];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) acc[i] = 0;
+  for (size_t rb = r0; rb < r1; rb += PJ_T) {
+    __syncthreads();
+    for (int e = t; e < PJ_S * PJ_T; e += PJ_S) {
+      const int row = e / PJ_T, c = e % PJ_T;
+      lp[row][c] = (s0 + row < S) ? phi[(size_t)(s0 + row) * ng + rb + c] : 0.0;
+    }
+    for (int e = t; e < NO * PJ_T; e += PJ_S) {
+      const int i = e / PJ_T, c = e % PJ_T;
+      lf[i][c] = (i < n_o) ? f[(size_t)i * ng + rb + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < PJ_T; ++c) {
+      const double v = lp[t][c];
+#pragma unroll
+      for (int i = 0; i < NO; ++i) acc[i] += v * lf[i][c];
+    }
+  }
+  if (s < S) {
+    double* out = part + (size_t)blockIdx.x * n_o * S;
+#pragma unroll
+    for (int i = 0; i < NO; ++i)
+      if (i < n_o) out[(size_t)i * S + s] = acc[i];
+  }
+}
+
+// C[k] = dv sum_x part[x][k] in eight slices of x added in a fixed order
+__global__ void __launch_bounds__(256) k_proj_reduce(const double* __restrict__ part, int nx, int MN,
+                                                     double dv, double* __restrict__ C) {
+  __shared__ double red[8][32];
+  const int o = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int k = blockIdx.x * 32 + o;
+  double acc = 0;
+  if (k < MN)
+    for (int x = j; x < nx; x += 8) acc += part[(size_t)x * MN + k];
+  red[j][o] = acc;
+  __syncthreads();
+  if (j == 0 && k < MN) {
+    double sum = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += red[q][o];
+    C[k] = sum * dv;
   }
 }
 
@@ -676,9 +739,32 @@ hipError_t launch_mixed_combine(const double* f, const double* tf, const double*
 hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
                               size_t ng, hipStream_t st) {
   const size_t sm = sizeof(double) * (size_t)n_o * S;
-  if (sm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_project_out, dim3((unsigned)((ng + 255) / 256)), dim3(256), sm, st, out, n_o, phi,
-                     S, C, ng);
+  if (sm > 64 * 1024 || n_o < 1) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((ng + 255) / 256)), b(256);
+  if (n_o <= 8)
+    hipLaunchKernelGGL(k_project_out<8>, g, b, sm, st, out, n_o, phi, S, C, ng);
+  else if (n_o <= 16)
+    hipLaunchKernelGGL(k_project_out<16>, g, b, sm, st, out, n_o, phi, S, C, ng);
+  else
+    hipLaunchKernelGGL(k_project_out<32>, g, b, sm, st, out, n_o, phi, S, C, ng);
+  return hipGetLastError();
+}
+size_t proj_part_elems(int n_o, int S) { return (size_t)PJ_BLK * n_o * S; }
+hipError_t launch_proj_coef(const double* f, int n_o, const double* phi, int S, size_t ng, double dv,
+                            double* part, double* C, hipStream_t st) {
+  if (n_o < 1 || n_o > 32 || S < 1 || ng % PJ_T) return hipErrorInvalidValue;
+  // PJ_BLK point ranges, each a multiple of the tile
+  const size_t pb = ((ng + PJ_BLK - 1) / PJ_BLK + PJ_T - 1) / PJ_T * PJ_T;
+  const int nx = (int)((ng + pb - 1) / pb);
+  const dim3 g(nx, (S + PJ_S - 1) / PJ_S), b(PJ_S);
+  if (n_o <= 8)
+    hipLaunchKernelGGL(k_proj_coef<8>, g, b, 0, st, f, n_o, phi, S, ng, pb, part);
+  else if (n_o <= 16)
+    hipLaunchKernelGGL(k_proj_coef<16>, g, b, 0, st, f, n_o, phi, S, ng, pb, part);
+  else
+    hipLaunchKernelGGL(k_proj_coef<32>, g, b, 0, st, f, n_o, phi, S, ng, pb, part);
+  const int MN = n_o * S;
+  hipLaunchKernelGGL(k_proj_reduce, dim3((MN + 31) / 32), dim3(256), 0, st, part, nx, MN, dv, C);
   return hipGetLastError();
 }
 int mixed_cheb_blocks() { return 256; }
