@@ -506,90 +506,139 @@ __global__ void k_mixed_combine(const double* __restrict__ f, const double* __re
 }
 
 // out_j -= sum_s C[j][s] phi_s (the occupied-space projection), C staged in LDS
+// out_j -= sum_s C[j][s] phi_s: the coefficients of PO_SC orbitals at a time
+// sit in LDS transposed, cs[s][JB], so that each orbital's JB coefficients
+// are read as double2; JB fields per pass over phi (one pass for n_o <= JB)
+constexpr int PO_LDS = 4096;                     // doubles of coefficients in LDS
 template <int JB>
 __global__ void __launch_bounds__(256) k_project_out(double* __restrict__ out, int n_o,
                                                      const double* __restrict__ phi, int S,
                                                      const double* __restrict__ C, size_t ng) {
-  extern __shared__ double cs[];
-  for (int i = threadIdx.x; i < n_o * S; i += blockDim.x) cs[i] = C[i];
-  __syncthreads();
+  constexpr int SC = PO_LDS / JB;                // orbitals per staged chunk
+  __shared__ __attribute__((aligned(16))) double cs[PO_LDS];
   const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= ng) return;
-  // JB fields per pass over phi: one pass for n_o <= JB
+  const bool live = r < ng;
   for (int j0 = 0; j0 < n_o; j0 += JB) {
     double acc[JB];
 #pragma unroll
     for (int q = 0; q < JB; ++q) acc[q] = 0;
-    for (int s = 0; s < S; ++s) {
-      const double p = phi[(size_t)s * ng + r];
+    for (int c0 = 0; c0 < S; c0 += SC) {
+      const int cn = min(SC, S - c0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < cn * JB; e += blockDim.x) {
+        const int sI = e / JB, q = e % JB;
+        cs[e] = (j0 + q < n_o) ? C[(size_t)(j0 + q) * S + c0 + sI] : 0.0;
+      }
+      __syncthreads();
+      if (!live) continue;
+#pragma unroll 2
+      for (int sI = 0; sI < cn; ++sI) {
+        const double p = phi[(size_t)(c0 + sI) * ng + r];
+        const double2* c2 = reinterpret_cast<const double2*>(cs + (size_t)sI * JB);
+#pragma unroll
+        for (int q = 0; q < JB / 2; ++q) {
+          const double2 c = c2[q];
+          acc[2 * q] += c.x * p;
+          acc[2 * q + 1] += c.y * p;
+        }
+      }
+    }
+    if (live)
 #pragma unroll
       for (int q = 0; q < JB; ++q)
-        if (j0 + q < n_o) acc[q] += cs[(j0 + q) * S + s] * p;
-    }
-#pragma unroll
-    for (int q = 0; q < JB; ++q)
-      if (j0 + q < n_o) out[(size_t)(j0 + q) * ng + r] -= acc[q];
+        if (j0 + q < n_o) out[(size_t)(j0 + q) * ng + r] -= acc[q];
   }
 }
 
 // Coefficients of n_o fields on S orbitals, C[i][s] = dv sum_r f_i(r)
-// phi_s(r): block (x, y) owns the points [x PB, (x+1) PB) and the orbitals
+// phi_s(r): block (x, y) owns the points [x pb, (x+1) pb) and the orbitals
 // [128 y, 128 y + 128); tiles of PJ_T points of phi (rows padded) and of
-// the fields are staged in LDS, each thread keeps the n_o sums of its
-// orbital in registers, and part[x][i][s] is reduced over x afterwards.
-constexpr int PJ_T = 32, PJ_S = 128, PJ_BLK = 1024;
+// the fields are staged in LDS, the next tile's loads in flight during the
+// current one; thread t keeps the n_o sums of orbital t % 128 over half of
+// each tile's points (t / 128), the halves are added at the end, and
+// part[x][i][s] is reduced over x afterwards.
+constexpr int PJ_T = 32, PJ_S = 128, PJ_BLK = 512;
 template <int NO>
-__global__ void __launch_bounds__(PJ_S) k_proj_coef(const double* __restrict__ f, int n_o,
-                                                    const double* __restrict__ phi, int S, size_t ng,
-                                                    size_t pb, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_proj_coef(const double* __restrict__ f, int n_o,
+                                                   const double* __restrict__ phi, int S, size_t ng,
+                                                   size_t pb, double* __restrict__ part) {
+  constexpr int NL = PJ_S * PJ_T / 256;          // phi values per thread and tile
+  constexpr int NF = (NO * PJ_T + 255) / 256;    // field values per thread and tile
   __shared__ double lp[PJ_S][PJ_T + 1];
   __shared__ double lf[NO][PJ_T];
-  const int t = threadIdx.x, s0 = blockIdx.y * PJ_S, s = s0 + t;
+  const int t = threadIdx.x, so = t % PJ_S, h = t / PJ_S;
+  const int s0 = blockIdx.y * PJ_S, s = s0 + so;
   const size_t r0 = (size_t)blockIdx.x * pb, r1 = min(ng, r0 + pb);
+  double rp[NL], rf[NF];
+  auto load = [&](size_t rb) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = t + 256 * k, row = e / PJ_T, c = e % PJ_T;
+      const int sr = min(s0 + row, S - 1);      // rows past S: in-range data, never used
+      rp[k] = phi[(size_t)sr * ng + rb + c];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int e = t + 256 * k, i = min(e / PJ_T, n_o - 1), c = e % PJ_T;
+      rf[k] = f[(size_t)i * ng + rb + c];
+    }
+  };
   double acc[NO];
 #pragma unroll
   for (int i = 0; i < NO; ++i) acc[i] = 0;
+  if (r0 < r1) load(r0);
   for (size_t rb = r0; rb < r1; rb += PJ_T) {
     __syncthreads();
-    for (int e = t; e < PJ_S * PJ_T; e += PJ_S) {
-      const int row = e / PJ_T, c = e % PJ_T;
-      lp[row][c] = (s0 + row < S) ? phi[(size_t)(s0 + row) * ng + rb + c] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = t + 256 * k;
+      lp[e / PJ_T][e % PJ_T] = rp[k];
     }
-    for (int e = t; e < NO * PJ_T; e += PJ_S) {
-      const int i = e / PJ_T, c = e % PJ_T;
-      lf[i][c] = (i < n_o) ? f[(size_t)i * ng + rb + c] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int e = t + 256 * k;
+      if (e < NO * PJ_T) lf[e / PJ_T][e % PJ_T] = (e / PJ_T < n_o) ? rf[k] : 0.0;
     }
     __syncthreads();
+    if (rb + PJ_T < r1) load(rb + PJ_T);
 #pragma unroll 4
-    for (int c = 0; c < PJ_T; ++c) {
-      const double v = lp[t][c];
+    for (int c = h * (PJ_T / 2); c < (h + 1) * (PJ_T / 2); ++c) {
+      const double v = lp[so][c];
 #pragma unroll
       for (int i = 0; i < NO; ++i) acc[i] += v * lf[i][c];
     }
   }
-  if (s < S) {
+  // second half's sums into the first's (fixed order), through LDS
+  __syncthreads();
+  double* red = &lp[0][0];                        // PJ_S * NO <= PJ_S * (PJ_T + 1)
+  if (h == 1)
+#pragma unroll
+    for (int i = 0; i < NO; ++i) red[i * PJ_S + so] = acc[i];
+  __syncthreads();
+  if (h == 0 && s < S) {
     double* out = part + (size_t)blockIdx.x * n_o * S;
 #pragma unroll
     for (int i = 0; i < NO; ++i)
-      if (i < n_o) out[(size_t)i * S + s] = acc[i];
+      if (i < n_o) out[(size_t)i * S + s] = acc[i] + red[i * PJ_S + so];
   }
 }
 
-// C[k] = dv sum_x part[x][k] in eight slices of x added in a fixed order
+// C[k] = dv sum_x part[x][k]: a block sums 8 outputs in 32 slices of x
+// (slice j: x = j, j + 32, ...) and adds the slices in order
 __global__ void __launch_bounds__(256) k_proj_reduce(const double* __restrict__ part, int nx, int MN,
                                                      double dv, double* __restrict__ C) {
-  __shared__ double red[8][32];
-  const int o = threadIdx.x & 31, j = threadIdx.x >> 5;
-  const int k = blockIdx.x * 32 + o;
+  __shared__ double red[32][8];
+  const int o = threadIdx.x & 7, j = threadIdx.x >> 3;
+  const int k = blockIdx.x * 8 + o;
   double acc = 0;
   if (k < MN)
-    for (int x = j; x < nx; x += 8) acc += part[(size_t)x * MN + k];
+    for (int x = j; x < nx; x += 32) acc += part[(size_t)x * MN + k];
   red[j][o] = acc;
   __syncthreads();
   if (j == 0 && k < MN) {
     double sum = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sum += red[q][o];
+    for (int q = 0; q < 32; ++q) sum += red[q][o];
     C[k] = sum * dv;
   }
 }
@@ -738,15 +787,14 @@ hipError_t launch_mixed_combine(const double* f, const double* tf, const double*
 }
 hipError_t launch_project_out(double* out, int n_o, const double* phi, int S, const double* C,
                               size_t ng, hipStream_t st) {
-  const size_t sm = sizeof(double) * (size_t)n_o * S;
-  if (sm > 64 * 1024 || n_o < 1) return hipErrorInvalidValue;
+  if (n_o < 1 || S < 1) return hipErrorInvalidValue;
   const dim3 g((unsigned)((ng + 255) / 256)), b(256);
   if (n_o <= 8)
-    hipLaunchKernelGGL(k_project_out<8>, g, b, sm, st, out, n_o, phi, S, C, ng);
+    hipLaunchKernelGGL(k_project_out<8>, g, b, 0, st, out, n_o, phi, S, C, ng);
   else if (n_o <= 16)
-    hipLaunchKernelGGL(k_project_out<16>, g, b, sm, st, out, n_o, phi, S, C, ng);
+    hipLaunchKernelGGL(k_project_out<16>, g, b, 0, st, out, n_o, phi, S, C, ng);
   else
-    hipLaunchKernelGGL(k_project_out<32>, g, b, sm, st, out, n_o, phi, S, C, ng);
+    hipLaunchKernelGGL(k_project_out<32>, g, b, 0, st, out, n_o, phi, S, C, ng);
   return hipGetLastError();
 }
 size_t proj_part_elems(int n_o, int S) { return (size_t)PJ_BLK * n_o * S; }
@@ -756,7 +804,7 @@ hipError_t launch_proj_coef(const double* f, int n_o, const double* phi, int S, 
   // PJ_BLK point ranges, each a multiple of the tile
   const size_t pb = ((ng + PJ_BLK - 1) / PJ_BLK + PJ_T - 1) / PJ_T * PJ_T;
   const int nx = (int)((ng + pb - 1) / pb);
-  const dim3 g(nx, (S + PJ_S - 1) / PJ_S), b(PJ_S);
+  const dim3 g(nx, (S + PJ_S - 1) / PJ_S), b(256);
   if (n_o <= 8)
     hipLaunchKernelGGL(k_proj_coef<8>, g, b, 0, st, f, n_o, phi, S, ng, pb, part);
   else if (n_o <= 16)
@@ -764,7 +812,7 @@ hipError_t launch_proj_coef(const double* f, int n_o, const double* phi, int S, 
   else
     hipLaunchKernelGGL(k_proj_coef<32>, g, b, 0, st, f, n_o, phi, S, ng, pb, part);
   const int MN = n_o * S;
-  hipLaunchKernelGGL(k_proj_reduce, dim3((MN + 31) / 32), dim3(256), 0, st, part, nx, MN, dv, C);
+  hipLaunchKernelGGL(k_proj_reduce, dim3((MN + 7) / 8), dim3(256), 0, st, part, nx, MN, dv, C);
   return hipGetLastError();
 }
 int mixed_cheb_blocks() { return 256; }
