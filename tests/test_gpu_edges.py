@@ -1,0 +1,73 @@
+"""Edge cases of the GPU path on a small system: an empty pair list, pair
+order and repeated pairs, a batch of exactly max_batch pairs, the 1 x 1
+Tamm-Dancoff matrix, and the shortest Chebyshev recursion (two moments)
+for the residues and the frequency-resolved states."""
+import numpy as np
+import pytest
+
+from paper_2205_06690_amd import inputs
+from oracle import bse as obse
+from oracle.grid import Grid
+from gpu_util import say, small_spec, oracle_w, gpu_system, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    spec = small_spec()
+    return spec, inputs.make_system(spec)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_empty_repeated_and_reversed_pairs(small, precision):
+    """No pairs: no work and no error.  rho_ij = rho_ji, so reversed and
+    repeated pairs give the same W up to rounding, and a batch of exactly
+    max_batch pairs equals the same pairs run one by one.  Not bit for bit:
+    the Coulomb solves pack two densities into one complex transform, whose
+    butterflies round each density against its partner, and in mixed
+    precision the cleaning GEMM's point chunks follow the batch size."""
+    spec, sysd = small
+    s = gpu_system(spec, sysd, precision, max_batch=3)
+    w0 = s.apply_w(np.zeros((0, 2), dtype=np.int32))
+    assert w0.shape == (0, spec.ng)
+    pairs = np.array([[4, 5], [5, 4], [4, 5]], dtype=np.int32)
+    w = s.apply_w(pairs)
+    single = np.concatenate([s.apply_w(pairs[k:k + 1]) for k in range(3)])
+    e_rep = max(rel(w[1:2], w[:1]).max(), rel(w[2:3], w[:1]).max())
+    e_bat = rel(w, single).max()
+    say(f"edges prec {precision}: repeated/reversed {e_rep:.2e}, batch vs single {e_bat:.2e}")
+    bound = 1e-12 if precision == 0 else 1e-6
+    assert e_rep < bound and e_bat < bound
+    w_o, _ = oracle_w(spec, sysd, pairs[:1])
+    tol = 1e-10 if precision == 0 else 1e-3
+    assert rel(w[:1], w_o.reshape(1, -1)).max() < tol
+
+
+def test_one_by_one_a_and_two_moments(small):
+    """n_o = n_c = 1: A is the scalar (e_a - e_i) + 2 (ia|ia) - (aa|W|ii);
+    two moments: R_0 = |f0|^2, R_1 = f0 . A~ f0, and the states
+    g_0 f0 + g_1 A~ f0, against the oracle on its own A."""
+    spec, sysd = small
+    s = gpu_system(spec, sysd, 0, max_batch=3)
+    A = s.build_a(1, 1)
+    grid = Grid(spec.shape, spec.h)
+    phi = sysd["phi"].reshape((-1,) + spec.shape)
+    i, a_ = spec.n_occ - 1, spec.n_occ
+    w_o, _ = oracle_w(spec, sysd, np.array([[i, i]], dtype=np.int32))
+    wf = w_o.reshape((1, 1) + spec.shape)
+    A_o = obse.build_a(grid, phi[i:i + 1], phi[a_:a_ + 1], sysd["eps"][i:i + 1], sysd["eps"][a_:a_ + 1], wf)
+    say(f"1x1 A: gpu {A[0, 0]:.12f} oracle {A_o[0, 0]:.12f}")
+    assert A.shape == (1, 1) and abs(A[0, 0] - A_o[0, 0]) < 1e-10
+    f0 = obse.dipoles(grid, phi[i:i + 1], phi[a_:a_ + 1])
+    lo, hi = A_o[0, 0] - 0.1, A_o[0, 0] + 0.1
+    a, b = obse.chebyshev_scale(lo, hi)
+    _, R, _ = s.chebyshev_spectrum(2, None, bounds=(lo, hi))
+    R_o = obse.chebyshev_residues(A_o, f0, 2, a, b)
+    assert np.allclose(R, R_o.T, rtol=1e-10, atol=1e-14)
+    wl = np.array([A_o[0, 0] - 0.01, A_o[0, 0]])
+    F, dn, _ = s.exciton_states(2, wl, 0.02, bounds=(lo, hi))
+    F_o = obse.chebyshev_states(A_o, f0, 2, a, b, wl, 0.02).transpose(0, 2, 1)
+    assert np.allclose(F, F_o, rtol=1e-10, atol=1e-14)
+    dn_o = obse.exciton_density(phi[i:i + 1], phi[a_:a_ + 1], F_o[1, 0])
+    assert np.abs(dn[1, 0] - dn_o).max() < 1e-10 * np.abs(dn_o).max()
