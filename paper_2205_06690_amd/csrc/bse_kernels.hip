@@ -653,7 +653,33 @@ __global__ void __launch_bounds__(256) k_mixed_cheb_update(const double* __restr
                                                            double ia, double b, int first, double dv,
                                                            int p, double* __restrict__ part) {
   double c0 = 0, c1 = 0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (size_t)gridDim.x * 256) {
+  // four values per thread and iteration (double2 accesses), scalar tail
+  const size_t len4 = len & ~(size_t)3;
+  for (size_t i = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4; i < len4; i += (size_t)gridDim.x * 256 * 4) {
+    const double2 a0 = *reinterpret_cast<const double2*>(af + i);
+    const double2 a1 = *reinterpret_cast<const double2*>(af + i + 2);
+    const double2 u0 = *reinterpret_cast<const double2*>(fc + i);
+    const double2 u1 = *reinterpret_cast<const double2*>(fc + i + 2);
+    double2 p0 = make_double2(0.0, 0.0), p1 = p0;
+    if (!first) {
+      p0 = *reinterpret_cast<const double2*>(fp + i);
+      p1 = *reinterpret_cast<const double2*>(fp + i + 2);
+    }
+    const double cv[4] = {u0.x, u0.y, u1.x, u1.y};
+    const double av[4] = {a0.x, a0.y, a1.x, a1.y};
+    const double pv[4] = {p0.x, p0.y, p1.x, p1.y};
+    double nv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = (av[q] - b * cv[q]) * ia;
+      nv[q] = first ? t : 2.0 * t - pv[q];
+      c0 += cv[q] * cv[q];
+      c1 += nv[q] * cv[q];
+    }
+    *reinterpret_cast<double2*>(fn + i) = make_double2(nv[0], nv[1]);
+    *reinterpret_cast<double2*>(fn + i + 2) = make_double2(nv[2], nv[3]);
+  }
+  for (size_t i = len4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (size_t)gridDim.x * 256) {
     const double cur = fc[i];
     const double t = (af[i] - b * cur) * ia;
     const double nx = first ? t : 2.0 * t - fp[i];
