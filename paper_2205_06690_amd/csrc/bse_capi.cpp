@@ -153,6 +153,7 @@ struct bse_system {
   DBuf A_d;       // [(n_o n_c)^2] FP64
   DBuf f0_d;      // [n_o n_c][3] dipoles
   DBuf lz_V, lz_w, lz_c, lz_s;  // Lanczos basis and scratch
+  DBuf ba_pq, ba_X, ba_Dm, ba_part, ba_rho64, ba_v64, ba_cpart, ba_ev, ba_ec, ba_s[4];  // bse_build_A scratch
   Timer timer;
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
@@ -507,10 +508,24 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
   // 1. W_ij for the valence pairs (kept on the device)
   s->wij.alloc(sizeof(double) * ng * n_ij);
   apply_w_device(s, n_ij, pij.data(), s->wij.as<double>(), nullptr, nullptr);
-  DBuf pq;
+  // scratch kept by the system across calls (grow-only), so repeated
+  // builds allocate nothing
+  DBuf& pq = s->ba_pq;
   pq.alloc(sizeof(int) * 2 * (size_t)std::max(std::max(n_ia, n_ab), n_ij));
   const bool fp64 = s->cfg.precision == BSE_FP64;
-  DBuf X, Dm, part, rho64, v64, cpart;
+  DBuf &X = s->ba_X, &Dm = s->ba_Dm, &part = s->ba_part, &rho64 = s->ba_rho64, &v64 = s->ba_v64,
+       &cpart = s->ba_cpart;
+  // the buffers shared by the exchange and direct terms get their largest
+  // size first, so that none is reallocated while kernels still use it
+  if (fp64) {
+    s->ba_s[0].alloc(sizeof(double) * ng * n_ab);
+  } else {
+    s->ba_s[0].alloc(sizeof(unsigned short) * ng * std::max(n_ia, n_ab));
+    s->ba_s[1].alloc(sizeof(unsigned short) * ng * std::max(n_ia, n_ab));
+    s->ba_s[2].alloc(sizeof(unsigned short) * ng * std::max(n_ia, n_ij));
+    s->ba_s[3].alloc(sizeof(unsigned short) * ng * std::max(n_ia, n_ij));
+    cpart.alloc(sizeof(float) * std::max(contract_part_floats(n_ia, n_ia, ng), contract_part_floats(n_ab, n_ij, ng)));
+  }
   X.alloc(sizeof(double) * (size_t)n_ia * n_ia);
   Dm.alloc(sizeof(double) * (size_t)n_ab * n_ij);
   const size_t pe = std::max(gemm_part_elems(n_ia, n_ia, ng), gemm_part_elems(n_ab, n_ij, ng));
@@ -531,7 +546,7 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
                          part.as<double>(), X.as<double>(), st));
   } else {
     // operands split once from FP64 into bf16 pairs for the matrix cores
-    DBuf rh, rl, vh, vl;
+    DBuf &rh = s->ba_s[0], &rl = s->ba_s[1], &vh = s->ba_s[2], &vl = s->ba_s[3];
     rh.alloc(sizeof(unsigned short) * ng * n_ia);
     rl.alloc(sizeof(unsigned short) * ng * n_ia);
     vh.alloc(sizeof(unsigned short) * ng * n_ia);
@@ -543,22 +558,18 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     HIPC(launch_contract_x3(rh.as<unsigned short>(), rl.as<unsigned short>(), n_ia, vh.as<unsigned short>(),
                             vl.as<unsigned short>(), n_ia, ng, s->dv, cpart.as<float>(), X.as<double>(), st));
     s->timer.end(t);
-    HIPC(hipStreamSynchronize(st));   // the split operands are freed at the end of this scope
   }
-  // 3. direct (ab|W|ij) over a <= b and i <= j
-  HIPC(hipStreamSynchronize(st));
+  // 3. direct (ab|W|ij) over a <= b and i <= j (pq is rewritten in stream order)
   HIPC(hipMemcpyAsync(pq.p, pab.data(), sizeof(int) * 2 * n_ab, hipMemcpyHostToDevice, st));
   if (fp64) {
-    DBuf rab;
+    DBuf& rab = s->ba_s[0];
     rab.alloc(sizeof(double) * ng * n_ab);
     HIPC(launch_products<double>(s->phi64.as<double>(), pq.as<int>(), n_ab, ng, rab.as<double>(), st));
     HIPC(launch_gemm_f64(rab.as<double>(), n_ab, s->wij.as<double>(), n_ij, ng, s->dv,
                          part.as<double>(), Dm.as<double>(), st));
     HIPC(hipStreamSynchronize(st));
   } else {
-    rho64.release();
-    v64.release();
-    DBuf abh, abl, wh, wl;
+    DBuf &abh = s->ba_s[0], &abl = s->ba_s[1], &wh = s->ba_s[2], &wl = s->ba_s[3];
     abh.alloc(sizeof(unsigned short) * ng * n_ab);
     abl.alloc(sizeof(unsigned short) * ng * n_ab);
     wh.alloc(sizeof(unsigned short) * ng * n_ij);
@@ -571,10 +582,9 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     HIPC(launch_contract_x3(abh.as<unsigned short>(), abl.as<unsigned short>(), n_ab, wh.as<unsigned short>(),
                             wl.as<unsigned short>(), n_ij, ng, s->dv, cpart.as<float>(), Dm.as<double>(), st));
     s->timer.end(t);
-    HIPC(hipStreamSynchronize(st));
   }
   // 4. assemble
-  DBuf ev, ec;
+  DBuf &ev = s->ba_ev, &ec = s->ba_ec;
   ev.alloc(sizeof(double) * n_o);
   ec.alloc(sizeof(double) * n_c);
   HIPC(hipMemcpyAsync(ev.p, s->eps.data() + v0, sizeof(double) * n_o, hipMemcpyHostToDevice, st));
