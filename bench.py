@@ -319,7 +319,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    S.set_timing(True)
+    # events only around the propagation passes and the contractions (the
+    # roofline kernels): each event pair costs a few microseconds of stream time
+    S.set_timing(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

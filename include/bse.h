@@ -245,7 +245,11 @@ bse_status bse_generate_signs(uint64_t seed, int32_t n_stoch, int32_t n_occ, int
  * number of kernels timed (0 unless timing was enabled). */
 int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, double* avg_ms,
                          int32_t* calls);
-/* Enable per-kernel HIP-event timing (adds synchronisation-free events). */
+/* Per-kernel HIP-event timing (synchronisation-free events around the timed
+ * launches, each pair costing a few microseconds of stream time): enable = 0
+ * off; 1 the propagation passes (prop_x, prop_yz) and the grid contractions
+ * (gemm_exchange, gemm_direct) only; 2 every timed section (also cleaning,
+ * Poisson, exciton states).  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
 const char* bse_last_error(void);

@@ -310,8 +310,10 @@ class System:
         LIB.bse_tuned_shape(self._h, C.byref(tc), C.byref(nt))
         return tc.value, nt.value
 
-    def set_timing(self, on: bool = True):
-        _check(LIB.bse_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, on=True):
+        """False/0 off; 1 the propagation passes and contractions; True/2 all."""
+        level = 2 if on is True else (0 if on is False else int(on))
+        _check(LIB.bse_set_timing(self._h, level))
 
     def kernel_times(self):
         cap = 32

@@ -76,11 +76,18 @@ struct Timer {
     size_t used = 0;
   };
   bool on = false;
+  int level = 0;   // 1: the propagation passes and the contractions; 2: every timed section
   std::map<std::string, Rec> recs;
   std::vector<std::string> order;
   hipStream_t st = nullptr;
-  std::pair<hipEvent_t, hipEvent_t>* begin(const char* name) {
-    if (!on) return nullptr;
+  std::pair<hipEvent_t, hipEvent_t>* begin(const char* name, int lvl = 2) {
+    auto* p = slot(name, lvl);
+    if (p) HIPC(hipEventRecord(p->first, st));
+    return p;
+  }
+  // the event pair of a timed section whose launch records the events itself
+  std::pair<hipEvent_t, hipEvent_t>* slot(const char* name, int lvl = 2) {
+    if (!on || lvl > level) return nullptr;
     auto it = recs.find(name);
     if (it == recs.end()) {
       order.push_back(name);
@@ -93,9 +100,7 @@ struct Timer {
       HIPC(hipEventCreate(&b));
       r.ev.push_back({a, b});
     }
-    auto* p = &r.ev[r.used++];
-    HIPC(hipEventRecord(p->first, st));
-    return p;
+    return &r.ev[r.used++];
   }
   void end(std::pair<hipEvent_t, hipEvent_t>* p) {
     if (p) HIPC(hipEventRecord(p->second, st));
@@ -378,9 +383,9 @@ void propagate_batch(bse_system* s, int B) {
     px.dt = (T)s->cfg.dt;
     px.L = L;
     px.mode = half ? PX_HALF : PX_FULL;
-    auto* t1 = s->timer.begin("prop_x");
-    HIPC(launch_prop_x<T>(s->n, px, B, st, s->tune_tc));
-    s->timer.end(t1);
+    auto* t1 = s->timer.slot("prop_x", 1);
+    const LaunchEvents e1{t1 ? t1->first : nullptr, t1 ? t1->second : nullptr};
+    HIPC(launch_prop_x<T>(s->n, px, B, st, s->tune_tc, t1 ? &e1 : nullptr));
     PropYZArgs<T> pz{};
     pz.d = s->d.as<C>();
     pz.H = hnext;
@@ -389,9 +394,9 @@ void propagate_batch(bse_system* s, int B) {
     pz.dens = s->dens.as<T>();
     pz.L = L;
     pz.density = 1;
-    auto* t2 = s->timer.begin("prop_yz");
-    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt));
-    s->timer.end(t2);
+    auto* t2 = s->timer.slot("prop_yz", 1);
+    const LaunchEvents e2{t2 ? t2->first : nullptr, t2 ? t2->second : nullptr};
+    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt, t2 ? &e2 : nullptr));
     const bool do_clean = M > 0 && ((n + 1) % M == 0);
     const double wn = s->wts[n + 1];
     if (!do_clean) {
@@ -554,7 +559,7 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     HIPC(launch_split64(rho64.as<double>(), ng * n_ia, rh.as<unsigned short>(), rl.as<unsigned short>(), st));
     HIPC(launch_split64(v64.as<double>(), ng * n_ia, vh.as<unsigned short>(), vl.as<unsigned short>(), st));
     cpart.alloc(sizeof(float) * contract_part_floats(n_ia, n_ia, ng));
-    auto* t = s->timer.begin("gemm_exchange");
+    auto* t = s->timer.begin("gemm_exchange", 1);
     HIPC(launch_contract_x3(rh.as<unsigned short>(), rl.as<unsigned short>(), n_ia, vh.as<unsigned short>(),
                             vl.as<unsigned short>(), n_ia, ng, s->dv, cpart.as<float>(), X.as<double>(), st));
     s->timer.end(t);
@@ -578,7 +583,7 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
                                abl.as<unsigned short>(), st));
     HIPC(launch_split64(s->wij.as<double>(), ng * n_ij, wh.as<unsigned short>(), wl.as<unsigned short>(), st));
     cpart.alloc(sizeof(float) * contract_part_floats(n_ab, n_ij, ng));
-    auto* t = s->timer.begin("gemm_direct");
+    auto* t = s->timer.begin("gemm_direct", 1);
     HIPC(launch_contract_x3(abh.as<unsigned short>(), abl.as<unsigned short>(), n_ab, wh.as<unsigned short>(),
                             wl.as<unsigned short>(), n_ij, ng, s->dv, cpart.as<float>(), Dm.as<double>(), st));
     s->timer.end(t);
@@ -1602,8 +1607,10 @@ bse_status bse_apply_W(bse_system* s, int32_t n_pairs, const int32_t* pq, double
 bse_status bse_set_timing(bse_system* s, int32_t enable) {
   API_BEGIN
   if (!s) fail(BSE_ERR_ARG, "null system");
+  if (enable < 0 || enable > 2) fail(BSE_ERR_ARG, "bse_set_timing: level 0, 1 or 2");
   HIPC(hipStreamSynchronize(s->stream));
   s->timer.on = enable != 0;
+  s->timer.level = enable;
   s->timer.reset();
   API_END
 }

@@ -74,9 +74,17 @@ template <typename T> struct CleanArgs {
 
 template <typename T> bool grid_supported(int n);
 template <typename T> void configure_kernels(int n);
-// tc: x-tile width (16, 32, 64; 0 = default); nt: plane-pass block size (256, 512; 0 = default)
-template <typename T> hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc = 0);
-template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt = 0);
+// start/stop events recorded by the kernel's own dispatch (timing without
+// separate event packets on the stream)
+struct LaunchEvents {
+  hipEvent_t start, stop;
+};
+// tc: x-tile width (16, 32, 64; 0 = default); nt: plane-pass block size (256, 512; 0 = default);
+// ev: nullable timing events
+template <typename T> hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc = 0,
+                                               const LaunchEvents* ev = nullptr);
+template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt = 0,
+                                                const LaunchEvents* ev = nullptr);
 template <typename T> hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_stoch_orbitals(const double* phi, const signed char* xi, int L, int n_occ,

@@ -9,6 +9,8 @@
 // factors by prop_yz on whole contiguous y-z planes.  The Coulomb solve is a
 // full 3-D transform: forward y-z planes, x-lines with the 4 pi/k^2
 // multiplier between the forward and inverse halves, inverse y-z planes.
+#include <hip/hip_ext.h>
+
 #include "fft_lines.h"
 #include "prop_kernels.h"
 #include "clean_mfma.h"
@@ -833,44 +835,52 @@ template <int N, typename T> constexpr size_t yz_lds() {
 
 template <int N, typename T>
 struct Launch {
+  // plain launch, or one that records ev's events in its own dispatch
+  template <typename K, typename A>
+  static void go(K kern, dim3 grid, dim3 block, size_t sm, hipStream_t st, const LaunchEvents* ev, const A& a) {
+    if (ev)
+      hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)sm, st, ev->start, ev->stop, 0, a);
+    else
+      hipLaunchKernelGGL(kern, grid, block, sm, st, a);
+  }
   template <int TC>
-  static hipError_t prop_x_tc(const PropXArgs<T>& a, int F, hipStream_t st) {
+  static hipError_t prop_x_tc(const PropXArgs<T>& a, int F, hipStream_t st, const LaunchEvents* ev) {
     if constexpr (!x_valid<N, TC>()) {
       return hipErrorInvalidValue;
     } else {
       dim3 grid(F, N * N / TC);
       size_t sm = x_lds<N, TC, T>();
       if (a.mode == PX_ETA0)
-        hipLaunchKernelGGL((k_prop_x<N, TC, T, true>), grid, dim3(256), sm, st, a);
+        go(k_prop_x<N, TC, T, true>, grid, dim3(256), sm, st, ev, a);
       else
-        hipLaunchKernelGGL((k_prop_x<N, TC, T, false>), grid, dim3(256), sm, st, a);
+        go(k_prop_x<N, TC, T, false>, grid, dim3(256), sm, st, ev, a);
       return hipGetLastError();
     }
   }
   // F: fields (unperturbed set) or pairs (perturbed set); tc 0 = default
-  static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st, int tc) {
+  static hipError_t prop_x(const PropXArgs<T>& a, int F, hipStream_t st, int tc, const LaunchEvents* ev) {
     if (tc == 0) tc = x_tc<N>();
     switch (tc) {
-      case 16: return prop_x_tc<16>(a, F, st);
-      case 32: return prop_x_tc<32>(a, F, st);
-      case 64: return prop_x_tc<64>(a, F, st);
+      case 16: return prop_x_tc<16>(a, F, st, ev);
+      case 32: return prop_x_tc<32>(a, F, st, ev);
+      case 64: return prop_x_tc<64>(a, F, st, ev);
       default: return hipErrorInvalidValue;
     }
   }
   template <int NT>
-  static hipError_t prop_yz_nt(const PropYZArgs<T>& a, int nb, hipStream_t st) {
+  static hipError_t prop_yz_nt(const PropYZArgs<T>& a, int nb, hipStream_t st, const LaunchEvents* ev) {
     size_t sm = yz_lds<N, T>();
     if (a.density)
-      hipLaunchKernelGGL((k_prop_yz<N, T, NT, true>), dim3(N, nb), dim3(NT), sm, st, a);
+      go(k_prop_yz<N, T, NT, true>, dim3(N, nb), dim3(NT), sm, st, ev, a);
     else
-      hipLaunchKernelGGL((k_prop_yz<N, T, NT, false>), dim3(N, nb), dim3(NT), sm, st, a);
+      go(k_prop_yz<N, T, NT, false>, dim3(N, nb), dim3(NT), sm, st, ev, a);
     return hipGetLastError();
   }
-  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt) {
+  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt, const LaunchEvents* ev) {
     if (nt == 0) nt = yz_threads<N>();
     switch (nt) {
-      case 256: return prop_yz_nt<256>(a, nb, st);
-      case 512: return prop_yz_nt<512>(a, nb, st);
+      case 256: return prop_yz_nt<256>(a, nb, st, ev);
+      case 512: return prop_yz_nt<512>(a, nb, st, ev);
       default: return hipErrorInvalidValue;
     }
   }
@@ -947,12 +957,13 @@ bool grid_supported(int n) {
   }
 
 template <typename T>
-hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc) {
-  BSE_DISPATCH_N(n, T, prop_x(a, F, st, tc));
+hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc, const LaunchEvents* ev) {
+  BSE_DISPATCH_N(n, T, prop_x(a, F, st, tc, ev));
 }
 template <typename T>
-hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt) {
-  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st, nt));
+hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt,
+                          const LaunchEvents* ev) {
+  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st, nt, ev));
 }
 template <typename T>
 hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st) {
@@ -1078,8 +1089,10 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
 }
 
 #define BSE_INST(T)                                                                            \
-  template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t, int);       \
-  template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t, int);     \
+  template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t, int,        \
+                                       const LaunchEvents*);                                     \
+  template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t, int,      \
+                                        const LaunchEvents*);                                    \
   template hipError_t launch_poisson<T>(int, const PoisArgs<T>&, hipStream_t);                 \
   template void configure_kernels<T>(int);                                                     \
   template bool grid_supported<T>(int);                                                        \
