@@ -252,6 +252,14 @@ int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, doubl
  * Poisson, exciton states).  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
+/* Kernel schedule of bse_spectrum's Lanczos iteration (the arithmetic and
+ * the convergence checks are the same either way; results agree to
+ * rounding).  0 (default): for n_o n_c <= 1024 every step up to the next
+ * convergence check runs in one single-workgroup launch with its vectors
+ * in LDS; larger A take path 1.  1: one chip-wide launch per operation of
+ * every step.  Errors: BSE_ERR_ARG for other values. */
+bse_status bse_set_lanczos_path(bse_system* sys, int32_t path);
+
 const char* bse_last_error(void);
 const char* bse_version(void);
 void bse_destroy_system(bse_system* sys);

@@ -26,7 +26,8 @@ BSE_FP64, BSE_MIXED = 0, 1
 EXPORTS = (
     "bse_create_system", "bse_set_orbitals", "bse_set_signs", "bse_apply_W",
     "bse_apply_W_device", "bse_build_A", "bse_spectrum", "bse_set_stream",
-    "bse_generate_signs", "bse_kernel_times", "bse_set_timing", "bse_last_error",
+    "bse_generate_signs", "bse_kernel_times", "bse_set_timing", "bse_set_lanczos_path",
+    "bse_last_error",
     "bse_version", "bse_destroy_system", "bse_apply_W_batch", "bse_autotune",
     "bse_tuned_shape", "bse_fno_create", "bse_fno_num_params", "bse_fno_set_params",
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
@@ -89,6 +90,7 @@ def _load():
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
     lib.bse_kernel_times.restype = C.c_int32
     lib.bse_set_timing.argtypes = [P, C.c_int32]
+    lib.bse_set_lanczos_path.argtypes = [P, C.c_int32]
     lib.bse_apply_W_batch.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
                                       C.c_int32]
     lib.bse_autotune.argtypes = [P, C.c_int32, C.c_char_p]
@@ -314,6 +316,11 @@ class System:
         """False/0 off; 1 the propagation passes and contractions; True/2 all."""
         level = 2 if on is True else (0 if on is False else int(on))
         _check(LIB.bse_set_timing(self._h, level))
+
+    def set_lanczos_path(self, path):
+        """0: single-workgroup launches up to each convergence check where A
+        fits (n <= 1024); 1: a chip-wide launch per operation."""
+        _check(LIB.bse_set_lanczos_path(self._h, int(path)))
 
     def kernel_times(self):
         cap = 32

@@ -160,6 +160,7 @@ struct bse_system {
   DBuf lz_V, lz_w, lz_c, lz_s;  // Lanczos basis and scratch
   DBuf ba_pq, ba_X, ba_Dm, ba_part, ba_rho64, ba_v64, ba_cpart, ba_ev, ba_ec, ba_s[4];  // bse_build_A scratch
   Timer timer;
+  int lz_path = 0;   // 0 fused launches where A fits, 1 a launch per operation
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
   hipStream_t own_stream = nullptr;
@@ -611,20 +612,34 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
 // symmetric tridiagonal eigenpairs (host, FP64): Sturm-count bisection for
 // the k lowest eigenvalues, inverse iteration for their vectors
 // ---------------------------------------------------------------------------
-int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int m, double x) {
-  int cnt = 0;
-  double q = a[0] - x;
-  if (q < 0) ++cnt;
-  for (int i = 1; i < m; ++i) {
-    const double qq = (std::fabs(q) < 1e-300) ? 1e-300 : q;
-    q = a[i] - x - b[i - 1] * b[i - 1] / qq;
-    if (q < 0) ++cnt;
+// Sturm counts (eigenvalues of T below x) at nx points at once: the points'
+// recurrences are independent, so interleaving them keeps the divider busy.
+void sturm_counts(const std::vector<double>& a, const std::vector<double>& b2, int m, const double* x, int nx,
+                  int* cnt) {
+  constexpr int XB = 32;
+  for (int x0 = 0; x0 < nx; x0 += XB) {
+    const int nb = std::min(XB, nx - x0);
+    double q[XB];
+    int c[XB];
+    for (int j = 0; j < nb; ++j) {
+      q[j] = a[0] - x[x0 + j];
+      c[j] = q[j] < 0;
+    }
+    for (int i = 1; i < m; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const double qq = (std::fabs(q[j]) < 1e-300) ? 1e-300 : q[j];
+        q[j] = a[i] - x[x0 + j] - b2[i - 1] / qq;
+        c[j] += q[j] < 0;
+      }
+    for (int j = 0; j < nb; ++j) cnt[x0 + j] = c[j];
   }
-  return cnt;
 }
 
+// The k lowest eigenpairs of the symmetric tridiagonal T (diagonal a,
+// off-diagonal b): bisection on Sturm counts until each bracket is below
+// tol relative to its magnitude, then inverse iteration.
 void tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, int m, int k,
-                    std::vector<double>& theta, std::vector<std::vector<double>>& vecs) {
+                    std::vector<double>& theta, std::vector<std::vector<double>>& vecs, double tol = 1e-15) {
   double lo = a[0], hi = a[0];
   for (int i = 0; i < m; ++i) {
     const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
@@ -632,15 +647,27 @@ void tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, 
     hi = std::max(hi, a[i] + r);
   }
   const double span = std::max(hi - lo, 1e-30);
-  theta.assign(k, 0.0);
-  for (int j = 0; j < k; ++j) {
-    double l = lo - 1e-12 * span, h = hi + 1e-12 * span;
-    for (int it = 0; it < 200 && h - l > 1e-15 * std::max(1.0, std::fabs(l) + std::fabs(h)); ++it) {
-      const double mid = 0.5 * (l + h);
-      if (sturm_count(a, b, m, mid) > j) h = mid; else l = mid;
+  std::vector<double> b2(std::max(m - 1, 1));
+  for (int i = 0; i + 1 < m; ++i) b2[i] = b[i] * b[i];
+  // bisection of the k lowest eigenvalues, all brackets advanced together
+  std::vector<double> l(k, lo - 1e-12 * span), h(k, hi + 1e-12 * span), mid(k);
+  std::vector<int> act(k), cnt(k);
+  for (int it = 0; it < 200; ++it) {
+    int na = 0;
+    for (int j = 0; j < k; ++j)
+      if (h[j] - l[j] > tol * std::max(1.0, std::fabs(l[j]) + std::fabs(h[j]))) {
+        act[na] = j;
+        mid[na++] = 0.5 * (l[j] + h[j]);
+      }
+    if (!na) break;
+    sturm_counts(a, b2, m, mid.data(), na, cnt.data());
+    for (int q = 0; q < na; ++q) {
+      const int j = act[q];
+      if (cnt[q] > j) h[j] = mid[q]; else l[j] = mid[q];
     }
-    theta[j] = 0.5 * (l + h);
   }
+  theta.assign(k, 0.0);
+  for (int j = 0; j < k; ++j) theta[j] = 0.5 * (l[j] + h[j]);
   vecs.assign(k, std::vector<double>(m, 0.0));
   uint64_t seed = 977;
   for (int j = 0; j < k; ++j) {
@@ -729,15 +756,23 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
   std::vector<double> theta;
   std::vector<std::vector<double>> svec;
   int m = 0, done = 0;
+  const bool fused = s->lz_path == 0 && n <= lanczos_fused_max();
   for (int k = 0; k < n && !m; ++k) {
-    HIPC(launch_gemv(s->A_d.as<double>(), n, V + (size_t)k * n, w, st));
-    // two passes of classical Gram-Schmidt against the whole basis
-    HIPC(launch_reorth(V, n, k + 1, c, w, st, al_d + k));
-    HIPC(launch_reorth(V, n, k + 1, c, w, st));
-    HIPC(launch_dot(w, w, n, bq_d + k, st));
-    if (k + 1 < n) HIPC(launch_scale_norm(w, n, bq_d + k, V + (size_t)(k + 1) * n, st));
     const int mk = k + 1;
-    if (!(mk >= n_exc && ((mk - n_exc) % 10 == 0 || mk == n))) continue;
+    const bool check = mk >= n_exc && ((mk - n_exc) % 10 == 0 || mk == n);
+    if (fused) {
+      // every iteration up to the next convergence check in one launch
+      if (!check) continue;
+      HIPC(launch_lanczos_steps(s->A_d.as<double>(), n, V, done, mk, al_d, bq_d, st));
+    } else {
+      HIPC(launch_gemv(s->A_d.as<double>(), n, V + (size_t)k * n, w, st));
+      // two passes of classical Gram-Schmidt against the whole basis
+      HIPC(launch_reorth(V, n, k + 1, c, w, st, al_d + k));
+      HIPC(launch_reorth(V, n, k + 1, c, w, st));
+      HIPC(launch_dot(w, w, n, bq_d + k, st));
+      if (k + 1 < n) HIPC(launch_scale_norm(w, n, bq_d + k, V + (size_t)(k + 1) * n, st));
+      if (!check) continue;
+    }
     HIPC(hipMemcpyAsync(al.data() + done, al_d + done, sizeof(double) * (mk - done),
                         hipMemcpyDeviceToHost, st));
     HIPC(hipMemcpyAsync(bq.data() + done, bq_d + done, sizeof(double) * (mk - done),
@@ -762,12 +797,17 @@ void spectrum(bse_system* s, int n_exc, double* omega, double* dip2, int n_w, co
       if (q + 1 < mk) beta.push_back(b_q);
     }
     if (mm < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
-    tridiag_lowest(alpha, beta, mm, std::min(n_exc, mm), theta, svec);
+    // the convergence test takes Ritz values to 1e-9 (the last components of
+    // their vectors barely depend on that); the final ones are resolved fully
+    tridiag_lowest(alpha, beta, mm, std::min(n_exc, mm), theta, svec, 1e-9);
     const double b_last = std::sqrt(std::max(bq[mm - 1], 0.0));
     bool conv = true;
     for (int j = 0; j < (int)theta.size() && conv; ++j)
       if (b_last * std::fabs(svec[j][mm - 1]) > 1e-10 * std::max(anorm, 1.0)) conv = false;
-    if (conv || breakdown || mk == n) m = mm;
+    if (conv || breakdown || mk == n) {
+      m = mm;
+      tridiag_lowest(alpha, beta, mm, std::min(n_exc, mm), theta, svec);
+    }
   }
   if (m == 0 || (int)theta.size() < n_exc) fail(BSE_ERR_NUMERIC, "Lanczos subspace smaller than n_exc");
   // Ritz vectors (all at once) and dipole strengths
@@ -1612,6 +1652,14 @@ bse_status bse_set_timing(bse_system* s, int32_t enable) {
   s->timer.on = enable != 0;
   s->timer.level = enable;
   s->timer.reset();
+  API_END
+}
+
+bse_status bse_set_lanczos_path(bse_system* s, int32_t path) {
+  API_BEGIN
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (path < 0 || path > 1) fail(BSE_ERR_ARG, "bse_set_lanczos_path: path 0 or 1");
+  s->lz_path = path;
   API_END
 }
 

@@ -21,6 +21,11 @@ hipError_t launch_dipoles(const double* phi, const int* pq, int K, int n, double
                           hipStream_t st);
 hipError_t launch_gemv(const double* A, int n, const double* v, double* y, hipStream_t st);
 // w -= V^T-projection onto the first m basis vectors (c = V w); c[m-1] also to *last
+// Lanczos iterations k0 .. k1-1 in one launch for n <= lanczos_fused_max():
+// basis V[n+1][n] (v_k0 set), al[k] = alpha_k, bq[k] = |w_k|^2
+int lanczos_fused_max();
+hipError_t launch_lanczos_steps(const double* A, int n, double* V, int k0, int k1, double* al, double* bq,
+                                hipStream_t st);
 hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,
                          double* last = nullptr);
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);

@@ -190,6 +190,93 @@ __global__ void __launch_bounds__(256) k_vt_w(const double* __restrict__ V, int 
   }
 }
 
+// Lanczos iterations k0 .. k1-1 in one workgroup (n <= LZ_T, so the vectors
+// live in LDS): w = A v_k, two passes of classical Gram-Schmidt against
+// v_0 .. v_k (alpha_k = the first pass's coefficient on v_k), bq[k] = |w|^2
+// and v_{k+1} = w / |w|; the steps of the launch-per-operation path in one
+// launch.  One CU is latency bound here, so every sum is split so that many
+// independent loads are in flight: A v reads columns (A is symmetric) and
+// V^T c reads V's rows, both coalesced, each thread summing every P-th term
+// of one element (P = LZ_T / n parts, added through LDS); the dot products
+// V w take LZ_R rows per wave at a time.
+constexpr int LZ_T = 1024, LZ_R = 4;
+__global__ void __launch_bounds__(LZ_T) k_lanczos_steps(const double* __restrict__ A, int n,
+                                                       double* __restrict__ V, int k0, int k1,
+                                                       double* __restrict__ al, double* __restrict__ bq) {
+  extern __shared__ double lz[];
+  double* v = lz;                // [n]
+  double* w = lz + n;            // [n]
+  double* c = lz + 2 * n;        // [n]
+  double* part = lz + 3 * n;     // [P][n]
+  __shared__ double red[LZ_T / 64];
+  constexpr int NW = LZ_T / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int P = LZ_T / n, i = tid % n, p = tid / n;
+  for (int k = k0; k < k1; ++k) {
+    if (tid < n) v[tid] = V[(size_t)k * n + tid];
+    __syncthreads();
+    if (p < P) {
+      double t = 0;
+#pragma unroll 8
+      for (int j = p; j < n; j += P) t += A[(size_t)j * n + i] * v[j];
+      part[p * n + i] = t;
+    }
+    __syncthreads();
+    if (tid < n) {
+      double t = 0;
+      for (int q = 0; q < P; ++q) t += part[q * n + tid];
+      w[tid] = t;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j0 = LZ_R * wv; j0 <= k; j0 += LZ_R * NW) {
+        double t[LZ_R];
+#pragma unroll
+        for (int q = 0; q < LZ_R; ++q) t[q] = 0;
+        const int nj = min(LZ_R, k + 1 - j0);
+        for (int e = lane; e < n; e += 64) {
+          const double we = w[e];
+#pragma unroll
+          for (int q = 0; q < LZ_R; ++q)
+            if (q < nj) t[q] += V[(size_t)(j0 + q) * n + e] * we;
+        }
+#pragma unroll
+        for (int q = 0; q < LZ_R; ++q)
+          for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
+        if (lane == 0)
+          for (int q = 0; q < nj; ++q) {
+            c[j0 + q] = t[q];
+            if (pass == 0 && j0 + q == k) al[k] = t[q];
+          }
+      }
+      __syncthreads();
+      if (p < P) {
+        double t = 0;
+#pragma unroll 8
+        for (int j = p; j <= k; j += P) t += c[j] * V[(size_t)j * n + i];
+        part[p * n + i] = t;
+      }
+      __syncthreads();
+      if (tid < n) {
+        double t = 0;
+        for (int q = 0; q < P; ++q) t += part[q * n + tid];
+        w[tid] -= t;
+      }
+      __syncthreads();
+    }
+    double t = tid < n ? w[tid] * w[tid] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+    if (lane == 0) red[wv] = t;
+    __syncthreads();
+    double b2 = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) b2 += red[q];
+    if (tid == 0) bq[k] = b2;
+    if (k + 1 < n && tid < n) V[(size_t)(k + 1) * n + tid] = w[tid] * (b2 > 0.0 ? 1.0 / sqrt(b2) : 0.0);
+    __syncthreads();   // v_{k+1} in global memory before the next iteration reads it
+  }
+}
+
 // w[i] -= sum_k c[k] V[k][i]
 __global__ void k_w_minus_vc(const double* __restrict__ V, int n, int m,
                              const double* __restrict__ c, double* __restrict__ w) {
@@ -906,6 +993,17 @@ hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, in
   if (n_out <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_exciton_density, dim3((unsigned)((ng + 255) / 256), (n_out + 7) / 8), dim3(256), 0,
                      st, phi, v0, c0, n_o, n_c, ng, F, n_out, dens);
+  return hipGetLastError();
+}
+// one workgroup holds one element of every vector per thread; beyond that,
+// and where one CU's share of bandwidth no longer beats the launch cost,
+// the chip-wide kernels of the other path take over
+int lanczos_fused_max() { return LZ_T; }
+hipError_t launch_lanczos_steps(const double* A, int n, double* V, int k0, int k1, double* al, double* bq,
+                                hipStream_t st) {
+  if (n < 1 || n > lanczos_fused_max() || k0 < 0 || k1 > n || k0 >= k1) return hipErrorInvalidValue;
+  const size_t sm = sizeof(double) * (3 * (size_t)n + (size_t)(LZ_T / n) * n);
+  hipLaunchKernelGGL(k_lanczos_steps, dim3(1), dim3(LZ_T), sm, st, A, n, V, k0, k1, al, bq);
   return hipGetLastError();
 }
 hipError_t launch_reorth(const double* V, int n, int m, double* c, double* w, hipStream_t st,

@@ -48,6 +48,12 @@ def test_tiny24_build_a_and_excitons(tiny_a, precision, tol_a, tol_w):
     # Lanczos on the device equals a dense eigensolve of the same matrix
     w_dense = np.linalg.eigvalsh(A)[:n_exc]
     assert np.abs(om - w_dense).max() < 1e-10
+    # the launch-per-operation schedule of the same iteration
+    s.set_lanczos_path(1)
+    om1, d21 = s.spectrum(n_exc)
+    s.set_lanczos_path(0)
+    assert np.abs(om1 - om).max() < 1e-12
+    assert np.allclose(d21, d2, rtol=1e-9, atol=1e-14)
     # absorption on a grid (Eq. 7 with Gaussian deltas)
     wg = np.linspace(om.min() - 0.05, om.max() + 0.05, 200)
     om2, d22, sg = s.spectrum(n_exc, wg, 0.003)
@@ -63,6 +69,9 @@ def test_build_a_symmetric_and_errors(tiny_a):
     assert e.value.code == bse.BSE_ERR_STATE
     with pytest.raises(bse.BseError) as e:
         s.build_a(spec.n_o, 100)
+    assert e.value.code == bse.BSE_ERR_ARG
+    with pytest.raises(bse.BseError) as e:
+        s.set_lanczos_path(2)
     assert e.value.code == bse.BSE_ERR_ARG
     A = s.build_a(spec.n_o, spec.n_c)
     assert np.array_equal(A, A.T)

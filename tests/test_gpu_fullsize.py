@@ -41,6 +41,15 @@ def test_mid64_bench_batch_w_and_a_block():
     # Chebyshev spectrum (Eqs. 7-8) of this A: properties at full size
     sig = 0.08 / inputs.HARTREE_EV
     om, d2 = s.spectrum(20)
+    # single-workgroup Lanczos launches (n = 200) against the launch-per-
+    # operation schedule and a dense eigensolve of the same A
+    s.set_lanczos_path(1)
+    om1, d21 = s.spectrum(20)
+    s.set_lanczos_path(0)
+    e_dense = np.abs(om - np.linalg.eigvalsh(A)[:20]).max()
+    say(f"mid64: Lanczos vs dense {e_dense:.2e}, paths {np.abs(om1 - om).max():.2e}")
+    assert e_dense < 1e-9 and np.abs(om1 - om).max() < 1e-12
+    assert np.allclose(d21, d2, rtol=1e-8, atol=1e-14)
     wg = np.linspace(om[0] - 10 * sig, om[-1] + 0.1, 2000)
     _, _, bo = s.chebyshev_spectrum(2, None)                # the Gershgorin interval
     # the Gaussian's Chebyshev coefficients fall as exp(-(n sig / a)^2 / 2):
