@@ -77,6 +77,8 @@ class SystemSpec:
     depth: tuple = (1.0, 3.0)
     width: tuple = (0.8, 1.5)
     sign_seed: Optional[int] = None  # None => seed
+    mol_n: Optional[int] = None      # draw the wells as in a box of mol_n points and centre
+                                     # that box in this one (the same molecule in several boxes)
 
     @property
     def ng(self) -> int:
@@ -111,6 +113,8 @@ class SystemSpec:
     def potential_key(self) -> str:
         """Hash of the fields that fix V_ext (and so the orbitals)."""
         d = {k: getattr(self, k) for k in ("n", "h", "n_wells", "seed", "layout", "depth", "width")}
+        if self.mol_n is not None:
+            d["mol_n"] = self.mol_n
         return hashlib.sha1(json.dumps(d, sort_keys=True).encode()).hexdigest()[:16]
 
 
@@ -126,6 +130,13 @@ CONFIGS = {
                            n_c=40, n_stoch=10, dt=0.05, n_steps=600,
                            layout="ring_sphere"),
 }
+
+
+def box_series(spec: SystemSpec, sizes):
+    """The molecule of ``spec`` in cubic boxes of ``sizes`` points per axis
+    (same spacing, wells at the same place relative to the box centre): the
+    several-box runs of the W(k->0) correction (Results section)."""
+    return [dataclasses.replace(spec, n=int(m), mol_n=spec.n) for m in sizes]
 
 
 def uneven_batch_specs(n_systems: int = 32):
@@ -160,6 +171,12 @@ def well_params(spec: SystemSpec):
     k = spec.n_wells
     U = rng.uniform(spec.depth[0], spec.depth[1], size=k)
     w = rng.uniform(spec.width[0], spec.width[1], size=k)
+    if spec.mol_n is not None:
+        # the molecule of the mol_n box, moved to the centre of this one
+        if spec.mol_n > spec.n:
+            raise ValueError("mol_n must not exceed n")
+        U, w, R = well_params(dataclasses.replace(spec, n=spec.mol_n, mol_n=None))
+        return U, w, R + 0.5 * (spec.n - spec.mol_n) * spec.h
     box = spec.box
     if spec.layout == "uniform":
         R = rng.uniform(0.2, 0.8, size=(k, 3)) * box
