@@ -213,6 +213,31 @@ bse_status bse_exciton_states_mixed(bse_system* sys, int32_t n_mom, double e_min
                                     int32_t n_w, const double* w_list, double sigma_broad, int32_t n_a,
                                     double* f_out, double* dens_out);
 
+/* Finite-box W(k->0) correction (Results section: the scissors of Eq. 1 is
+ * shifted down by W(k->0) = eps_eff^-1 v_bndry, eps_eff^-1 fitted so that
+ * the spectra of runs in several box sizes overlap).
+ *
+ * bse_boundary_potential: v_bndry of this system's box, the mean of the
+ * Kohn-Sham potential V_ext + v_H[n] (n = 2 sum_{s < n_occ} phi_s^2, v_H
+ * the periodic Coulomb potential without its k = 0 term) over the grid
+ * points with a zero index along some axis (the three faces through the
+ * origin corner; 3 n^2 - 3 n + 1 points), minus its mean over the cell.
+ * FP64 on the device; *v_bndry (host) receives it.  Errors: BSE_ERR_STATE
+ * before bse_set_orbitals; BSE_ERR_ARG for a null output. */
+bse_status bse_boundary_potential(bse_system* sys, double* v_bndry);
+
+/* bse_fit_box_correction: least-squares fit over n_box >= 2 boxes of the
+ * n_exc >= 1 lowest excitation energies omega[n_box][n_exc] (host, Hartree,
+ * e.g. from bse_spectrum of each box) to omega[b][m] = c[m] + eps_inv *
+ * v_bndry[b] (a scissors moves every excitation by the same amount, so
+ * spectra corrected by -W(k->0) overlap when these do).  Outputs (host):
+ * *eps_inv; c[n_exc] (nullable); w_k0[n_box] = eps_inv * v_bndry[b], the
+ * W(k->0) to subtract from each box's scissors.  Host arithmetic only.
+ * Errors: BSE_ERR_ARG for bad sizes, null required pointers, non-finite
+ * inputs, or boundary potentials that all agree to 1e-12 relative. */
+bse_status bse_fit_box_correction(int32_t n_box, int32_t n_exc, const double* omega,
+                                  const double* v_bndry, double* eps_inv, double* c, double* w_k0);
+
 /* Uneven batch: the W-action for several systems at once (different grids,
  * orbital counts and pair counts, same device).  System k propagates
  * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and

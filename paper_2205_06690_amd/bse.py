@@ -34,6 +34,7 @@ EXPORTS = (
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
+    "bse_boundary_potential", "bse_fit_box_correction",
 )
 
 
@@ -85,6 +86,8 @@ def _load():
                                              C.c_double, C.c_int32, dp, dp]
     lib.bse_chebyshev_mixed.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                         C.c_double, dp, dp]
+    lib.bse_boundary_potential.argtypes = [P, dp]
+    lib.bse_fit_box_correction.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
     lib.bse_set_stream.argtypes = [P, P]
     lib.bse_generate_signs.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
     lib.bse_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_char_p), dp, ip]
@@ -148,6 +151,23 @@ def apply_w_batch(systems, pair_lists, w_dev_ptrs, use_graph: bool = True):
     pq_ptrs = (C.POINTER(C.c_int32) * n)(*[_iptr(p) for p in pqs])
     w_ptrs = (C.c_void_p * n)(*[C.c_void_p(p) for p in w_dev_ptrs])
     _check(LIB.bse_apply_W_batch(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, 1 if use_graph else 0))
+
+
+def fit_box_correction(omega, v_bndry):
+    """Inverse-dielectric fit of the W(k->0) correction over several boxes
+    (bse_fit_box_correction): omega[n_box][n_exc] lowest excitation
+    energies, v_bndry[n_box] boundary potentials -> (eps_inv, c[n_exc],
+    w_k0[n_box])."""
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    v = np.ascontiguousarray(v_bndry, dtype=np.float64)
+    if om.ndim != 2 or v.shape != (om.shape[0],):
+        raise ValueError("omega must be [n_box][n_exc] and v_bndry [n_box]")
+    e = C.c_double()
+    c = np.empty(om.shape[1])
+    wk = np.empty(om.shape[0])
+    _check(LIB.bse_fit_box_correction(om.shape[0], om.shape[1], _dptr(om), _dptr(v), C.byref(e),
+                                      _dptr(c), _dptr(wk)))
+    return e.value, c, wk
 
 
 def generate_signs(seed: int, n_stoch: int, n_occ: int) -> np.ndarray:
@@ -316,6 +336,12 @@ class System:
         """False/0 off; 1 the propagation passes and contractions; True/2 all."""
         level = 2 if on is True else (0 if on is False else int(on))
         _check(LIB.bse_set_timing(self._h, level))
+
+    def boundary_potential(self) -> float:
+        """v_bndry of this box (bse_boundary_potential)."""
+        v = C.c_double()
+        _check(LIB.bse_boundary_potential(self._h, C.byref(v)))
+        return v.value
 
     def set_lanczos_path(self, path):
         """0: single-workgroup launches up to each convergence check where A

@@ -168,6 +168,7 @@ struct bse_system {
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
   DBuf mx_f, mx_tf, mx_out, mx_rho, mx_dv, mx_c, mx_part, mx_eps;  // matrix-free A f
   int mx_eps_v0 = -1, mx_eps_n = 0;   // valence window whose eps mx_eps holds
+  DBuf bnd_n, bnd_v, bnd_part;   // boundary potential: density, v_H, block sums
   double n0_scale = 0, v_scale = 0;
 };
 
@@ -1343,6 +1344,69 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
 }
 
 // ---------------------------------------------------------------------------
+// finite-box W(k->0) correction (Results section): boundary potential of one
+// box on the device, and the inverse-dielectric fit over several boxes
+// ---------------------------------------------------------------------------
+double boundary_potential(bse_system* s) {
+  check_ready(s);
+  const size_t ng = s->ng;
+  hipStream_t st = s->stream;
+  if (!s->vdev.p || s->vdev.bytes < sizeof(double) * ng) {
+    s->vdev.alloc(sizeof(double) * ng);
+    HIPC(hipMemcpy(s->vdev.p, s->vext.data(), sizeof(double) * ng, hipMemcpyHostToDevice));
+  }
+  s->bnd_n.alloc(sizeof(double) * ng);
+  s->bnd_v.alloc(sizeof(double) * ng);
+  s->bnd_part.alloc(sizeof(double) * (boundary_part_elems(s->n) + 1));
+  // n = 2 sum_{s < N_occ} phi_s^2, v_H = v[n] (k = 0 term removed)
+  HIPC(launch_ground_density(s->phi64.as<double>(), s->cfg.n_occ, ng, s->bnd_n.as<double>(), st));
+  poisson64(s, s->bnd_n.as<double>(), 1, s->bnd_v.as<double>(), nullptr, 0.0);
+  double* part = s->bnd_part.as<double>();
+  double* out = part + boundary_part_elems(s->n);
+  HIPC(launch_boundary_average(s->vdev.as<double>(), s->bnd_v.as<double>(), s->n, part, out, st));
+  double v = 0;
+  HIPC(hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  return v;
+}
+
+// Least squares of omega[b][m] = c_m + e v[b]: with box means removed,
+// e = sum_bm (omega_bm - mean_b omega_bm)(v_b - mean v) / (n_exc sum_b (v_b - mean v)^2).
+void fit_box_correction(int n_box, int n_exc, const double* omega, const double* v, double* eps_inv,
+                        double* c, double* w_k0) {
+  if (n_box < 2 || n_exc < 1 || !omega || !v || !eps_inv || !w_k0)
+    fail(BSE_ERR_ARG, "bse_fit_box_correction: need n_box >= 2, n_exc >= 1 and non-null buffers");
+  for (int i = 0; i < n_box * n_exc; ++i)
+    if (!std::isfinite(omega[i])) fail(BSE_ERR_ARG, "bse_fit_box_correction: non-finite omega");
+  double vm = 0, vmax = 0;
+  for (int b = 0; b < n_box; ++b) {
+    if (!std::isfinite(v[b])) fail(BSE_ERR_ARG, "bse_fit_box_correction: non-finite v_bndry");
+    vm += v[b];
+    vmax = std::max(vmax, std::fabs(v[b]));
+  }
+  vm /= n_box;
+  double spread = 0, den = 0;
+  for (int b = 0; b < n_box; ++b) {
+    spread = std::max(spread, std::fabs(v[b] - vm));
+    den += (v[b] - vm) * (v[b] - vm);
+  }
+  if (!(spread > 1e-12 * std::max(vmax, 1e-300)))
+    fail(BSE_ERR_ARG, "bse_fit_box_correction: the boxes' boundary potentials coincide");
+  std::vector<double> om_mean(n_exc, 0.0);
+  for (int b = 0; b < n_box; ++b)
+    for (int m = 0; m < n_exc; ++m) om_mean[m] += omega[(size_t)b * n_exc + m];
+  for (int m = 0; m < n_exc; ++m) om_mean[m] /= n_box;
+  double num = 0;
+  for (int b = 0; b < n_box; ++b)
+    for (int m = 0; m < n_exc; ++m) num += (omega[(size_t)b * n_exc + m] - om_mean[m]) * (v[b] - vm);
+  const double e = num / (n_exc * den);
+  *eps_inv = e;
+  if (c)
+    for (int m = 0; m < n_exc; ++m) c[m] = om_mean[m] - e * vm;
+  for (int b = 0; b < n_box; ++b) w_k0[b] = e * v[b];
+}
+
+// ---------------------------------------------------------------------------
 // surrogate samples and surrogate W-action
 // ---------------------------------------------------------------------------
 void surrogate_descriptors(bse_system* s) {
@@ -1699,6 +1763,20 @@ bse_status bse_spectrum(bse_system* s, int32_t n_exc, double* omega, double* dip
                         const double* w_grid, double sigma_broad, double* sigma) {
   API_BEGIN
   spectrum(s, n_exc, omega, dip2, n_w, w_grid, sigma_broad, sigma);
+  API_END
+}
+
+bse_status bse_boundary_potential(bse_system* s, double* v_bndry) {
+  API_BEGIN
+  if (!v_bndry) fail(BSE_ERR_ARG, "bse_boundary_potential: null output");
+  *v_bndry = boundary_potential(s);
+  API_END
+}
+
+bse_status bse_fit_box_correction(int32_t n_box, int32_t n_exc, const double* omega, const double* v_bndry,
+                                  double* eps_inv, double* c, double* w_k0) {
+  API_BEGIN
+  fit_box_correction(n_box, n_exc, omega, v_bndry, eps_inv, c, w_k0);
   API_END
 }
 

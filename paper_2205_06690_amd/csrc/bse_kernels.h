@@ -88,6 +88,11 @@ hipError_t launch_scale_norm(const double* w, int n, const double* bsq, double* 
 
 namespace bse {
 hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double* n0, hipStream_t st);
+// v_bndry = mean of vext + vh over the zero-index faces minus the cell mean,
+// into out[0] (device); part holds boundary_part_elems(n) doubles
+size_t boundary_part_elems(int n);
+hipError_t launch_boundary_average(const double* vext, const double* vh, int n, double* part, double* out,
+                                   hipStream_t st);
 hipError_t launch_row_dots(const double* a, const double* c, const double* d, int B, size_t ng,
                            double* out, hipStream_t st);
 hipError_t launch_features(const double* q, const double* scale, const double* n0, double n0s,

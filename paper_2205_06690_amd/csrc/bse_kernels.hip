@@ -1108,6 +1108,79 @@ __global__ void k_assemble_w(const double* __restrict__ q, const double* __restr
   w[i] = q[i] + p;
 }
 
+// ---------------------------------------------------------------------------
+// Boundary potential of the finite-box W(k->0) correction (Results
+// section): v_bndry = mean of V = V_ext + v_H over the points with a zero
+// index (the three faces through the origin corner; the far faces are
+// their periodic images) minus its mean over the cell.  Each block sums a
+// fixed range of BND_T * BND_PER points; the block sums are added in block
+// order by one block, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int BND_T = 256, BND_PER = 16;
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  const double t = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(BND_T) k_boundary_partial(const double* __restrict__ vext,
+                                                            const double* __restrict__ vh, int n,
+                                                            double* __restrict__ part) {
+  __shared__ double red[BND_T / 64];
+  const size_t ng = (size_t)n * n * n;
+  const size_t r0 = (size_t)blockIdx.x * BND_T * BND_PER;
+  double all = 0, bnd = 0;
+  for (int q = 0; q < BND_PER; ++q) {
+    const size_t r = r0 + (size_t)q * BND_T + threadIdx.x;
+    if (r < ng) {
+      const double v = vext[r] + vh[r];
+      const int k = (int)(r % n), j = (int)((r / n) % n), i = (int)(r / ((size_t)n * n));
+      all += v;
+      if (i == 0 || j == 0 || k == 0) bnd += v;
+    }
+  }
+  all = block_sum_256(all, red);
+  bnd = block_sum_256(bnd, red);
+  if (threadIdx.x == 0) {
+    part[2 * (size_t)blockIdx.x] = all;
+    part[2 * (size_t)blockIdx.x + 1] = bnd;
+  }
+}
+
+__global__ void __launch_bounds__(BND_T) k_boundary_final(const double* __restrict__ part, int nblk, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double red[BND_T / 64];
+  double all = 0, bnd = 0;
+  for (int b = threadIdx.x; b < nblk; b += BND_T) {
+    all += part[2 * (size_t)b];
+    bnd += part[2 * (size_t)b + 1];
+  }
+  all = block_sum_256(all, red);
+  bnd = block_sum_256(bnd, red);
+  if (threadIdx.x == 0) {
+    const double nb = 3.0 * n * n - 3.0 * n + 1.0, ng = (double)n * n * n;
+    out[0] = bnd / nb - all / ng;
+  }
+}
+
+size_t boundary_part_elems(int n) {
+  const size_t ng = (size_t)n * n * n;
+  return 2 * ((ng + (size_t)BND_T * BND_PER - 1) / ((size_t)BND_T * BND_PER));
+}
+
+hipError_t launch_boundary_average(const double* vext, const double* vh, int n, double* part, double* out,
+                                   hipStream_t st) {
+  if (n < 1) return hipErrorInvalidValue;
+  const int nblk = (int)(boundary_part_elems(n) / 2);
+  hipLaunchKernelGGL(k_boundary_partial, dim3(nblk), dim3(BND_T), 0, st, vext, vh, n, part);
+  hipLaunchKernelGGL(k_boundary_final, dim3(1), dim3(BND_T), 0, st, part, nblk, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double* n0, hipStream_t st) {
   hipLaunchKernelGGL(k_ground_density, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, phi, n_occ,
                      ng, n0);
