@@ -51,14 +51,42 @@ _PROP_SOURCES = ("paper_2205_06690_amd/csrc/prop_kernels.hip",
                  "paper_2205_06690_amd/csrc/fft_lines.h")
 
 
-def _sources_sha256() -> str:
+def _sources_sha256(files=None) -> str:
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in _PROP_SOURCES:
+    for f in (_PROP_SOURCES if files is None else files):
         with open(os.path.join(here, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+_CONTRACT_SOURCES = ("paper_2205_06690_amd/csrc/contract_mfma.hip",
+                     "paper_2205_06690_amd/csrc/contract_mfma.h",
+                     "paper_2205_06690_amd/csrc/mfma_tiles.h")
+
+
+def _mfma_record(kernel: str, workload: str):
+    """Counter-measured matrix-core utilisation of a contraction kernel
+    (SQ_VALU_MFMA_BUSY_CYCLES over SIMDs x cycles) from the record in
+    profiles/, or None when there is none or the sources changed since."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    d = os.path.join(here, "profiles")
+    if not os.path.isdir(d):
+        return None
+    sha = _sources_sha256(_CONTRACT_SOURCES)
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(d, name)) as fh:
+            for line in fh:
+                if not line.startswith("mfma-record: "):
+                    continue
+                rec = json.loads(line[len("mfma-record: "):])
+                if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                        and rec.get("sources_sha256") == sha):
+                    return rec
+    return None
 
 
 def _traffic_bytes(kernel: str, workload: str):
@@ -440,8 +468,10 @@ def main():
                                  float(np.sum((cor - cor.mean(0)) ** 2))],
             "ms": round(t_series * 1e3, 1), "note": "system setup, A, excitons, v_bndry of 3 boxes + fit"}
 
-    # the grid contractions (Eq. 1) on the BF16 matrix cores: issued flops of
-    # the three-term split over the measured launch times
+    # the grid contractions (Eq. 1) on the BF16 matrix cores: the issued flops
+    # of the three-term split (3 x 2MNK) over the GEMM kernel's own launch
+    # time (the FP64 chunk reduction is timed apart), and the counter-measured
+    # matrix-core busy fraction of the same kernel from profiles/
     contraction = None
     if prec == bse.BSE_MIXED and "gemm_exchange" in kt and "gemm_direct" in kt:
         n_ia = spec.n_o * spec.n_c
@@ -453,11 +483,14 @@ def main():
         contraction = {"bound": "mfma", "kernel": "k_contract_x3 (exchange + direct)",
                        "achieved": round(tf, 1), "peak": PEAK_BF16_TFS, "unit": "TFLOP/s",
                        "frac": round(tf / PEAK_BF16_TFS, 4),
-                       "flops_issued": fl_x + fl_d, "ms": round(ms_x + ms_d, 4),
-                       "exchange": {"M": n_ia, "N": n_ia, "K": spec.ng, "ms": round(ms_x, 4),
-                                    "tflops": round(fl_x / (ms_x * 1e-3) / 1e12, 1)},
-                       "direct": {"M": n_ab, "N": B, "K": spec.ng, "ms": round(ms_d, 4),
-                                  "tflops": round(fl_d / (ms_d * 1e-3) / 1e12, 1)}}
+                       "flops_issued": fl_x + fl_d, "ms": round(ms_x + ms_d, 4)}
+        for name, M_, N_, fl, ms in (("exchange", n_ia, n_ia, fl_x, ms_x), ("direct", n_ab, B, fl_d, ms_d)):
+            e = {"M": M_, "N": N_, "K": spec.ng, "ms": round(ms, 4),
+                 "tflops": round(fl / (ms * 1e-3) / 1e12, 1),
+                 "reduce_ms": round(kt.get("reduce_" + name, [float("nan")])[0], 4)}
+            rec = _mfma_record(name, args.config)
+            e["mfma_busy_frac"] = None if rec is None else rec["mfma_busy_frac"]
+            contraction[name] = e
 
     out = {
         "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",

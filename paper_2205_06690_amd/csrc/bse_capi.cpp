@@ -561,10 +561,13 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     HIPC(launch_split64(rho64.as<double>(), ng * n_ia, rh.as<unsigned short>(), rl.as<unsigned short>(), st));
     HIPC(launch_split64(v64.as<double>(), ng * n_ia, vh.as<unsigned short>(), vl.as<unsigned short>(), st));
     cpart.alloc(sizeof(float) * contract_part_floats(n_ia, n_ia, ng));
-    auto* t = s->timer.begin("gemm_exchange", 1);
+    auto* t = s->timer.slot("gemm_exchange", 1);
+    auto* tr = s->timer.slot("reduce_exchange", 1);
+    const LaunchEvents e{t ? t->first : nullptr, t ? t->second : nullptr};
+    const LaunchEvents er{tr ? tr->first : nullptr, tr ? tr->second : nullptr};
     HIPC(launch_contract_x3(rh.as<unsigned short>(), rl.as<unsigned short>(), n_ia, vh.as<unsigned short>(),
-                            vl.as<unsigned short>(), n_ia, ng, s->dv, cpart.as<float>(), X.as<double>(), st));
-    s->timer.end(t);
+                            vl.as<unsigned short>(), n_ia, ng, s->dv, cpart.as<float>(), X.as<double>(), st,
+                            t ? &e : nullptr, tr ? &er : nullptr));
   }
   // 3. direct (ab|W|ij) over a <= b and i <= j (pq is rewritten in stream order)
   HIPC(hipMemcpyAsync(pq.p, pab.data(), sizeof(int) * 2 * n_ab, hipMemcpyHostToDevice, st));
@@ -585,10 +588,13 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
                                abl.as<unsigned short>(), st));
     HIPC(launch_split64(s->wij.as<double>(), ng * n_ij, wh.as<unsigned short>(), wl.as<unsigned short>(), st));
     cpart.alloc(sizeof(float) * contract_part_floats(n_ab, n_ij, ng));
-    auto* t = s->timer.begin("gemm_direct", 1);
+    auto* t = s->timer.slot("gemm_direct", 1);
+    auto* tr = s->timer.slot("reduce_direct", 1);
+    const LaunchEvents e{t ? t->first : nullptr, t ? t->second : nullptr};
+    const LaunchEvents er{tr ? tr->first : nullptr, tr ? tr->second : nullptr};
     HIPC(launch_contract_x3(abh.as<unsigned short>(), abl.as<unsigned short>(), n_ab, wh.as<unsigned short>(),
-                            wl.as<unsigned short>(), n_ij, ng, s->dv, cpart.as<float>(), Dm.as<double>(), st));
-    s->timer.end(t);
+                            wl.as<unsigned short>(), n_ij, ng, s->dv, cpart.as<float>(), Dm.as<double>(), st,
+                            t ? &e : nullptr, tr ? &er : nullptr));
   }
   // 4. assemble
   DBuf &ev = s->ba_ev, &ec = s->ba_ec;

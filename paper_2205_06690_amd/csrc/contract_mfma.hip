@@ -10,6 +10,7 @@
 // LDS 64 points at a time with the next stage's loads in flight; FP32 sums
 // per tile and chunk, FP64 sums over chunks.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "contract_mfma.h"
 #include "mfma_tiles.h"
@@ -196,7 +197,8 @@ hipError_t launch_products_split(const double* phi, const int* pq, int K, size_t
 
 hipError_t launch_contract_x3(const unsigned short* ah, const unsigned short* al, int M,
                               const unsigned short* bh, const unsigned short* bl, int N, size_t K,
-                              double scale, float* part, double* C, hipStream_t st) {
+                              double scale, float* part, double* C, hipStream_t st,
+                              const LaunchEvents* ev, const LaunchEvents* ev_reduce) {
   if (M <= 0 || N <= 0 || K % CK_STAGE != 0) return hipErrorInvalidValue;
   size_t chunk;
   int nchunk;
@@ -205,11 +207,20 @@ hipError_t launch_contract_x3(const unsigned short* ah, const unsigned short* al
   const unsigned ntile = (unsigned)ntm * ntn * nchunk;
   (void)hipFuncSetAttribute((const void*)k_contract_x3<CK_STAGE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)contract_lds<CK_STAGE>());
-  hipLaunchKernelGGL(k_contract_x3<CK_STAGE>, dim3(round8u(ntile)), dim3(256), contract_lds<CK_STAGE>(), st,
-                     ah, al, M, bh, bl, N, K, chunk, ntm, ntn, ntile, 1, part);
+  if (ev)
+    hipExtLaunchKernelGGL(k_contract_x3<CK_STAGE>, dim3(round8u(ntile)), dim3(256),
+                          (uint32_t)contract_lds<CK_STAGE>(), st, ev->start, ev->stop, 0, ah, al, M, bh, bl,
+                          N, K, chunk, ntm, ntn, ntile, 1, part);
+  else
+    hipLaunchKernelGGL(k_contract_x3<CK_STAGE>, dim3(round8u(ntile)), dim3(256), contract_lds<CK_STAGE>(),
+                       st, ah, al, M, bh, bl, N, K, chunk, ntm, ntn, ntile, 1, part);
   const size_t MN = (size_t)M * N;
-  hipLaunchKernelGGL(k_contract_reduce, dim3((unsigned)((MN + 31) / 32)), dim3(256), 0, st, part,
-                     nchunk, MN, scale, C);
+  const dim3 gr((unsigned)((MN + 31) / 32));
+  if (ev_reduce)
+    hipExtLaunchKernelGGL(k_contract_reduce, gr, dim3(256), 0, st, ev_reduce->start, ev_reduce->stop, 0, part,
+                          nchunk, MN, scale, C);
+  else
+    hipLaunchKernelGGL(k_contract_reduce, gr, dim3(256), 0, st, part, nchunk, MN, scale, C);
   return hipGetLastError();
 }
 
