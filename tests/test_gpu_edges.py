@@ -1,7 +1,8 @@
 """Edge cases of the GPU path on a small system: an empty pair list, pair
 order and repeated pairs, a batch of exactly max_batch pairs, the 1 x 1
-Tamm-Dancoff matrix, and the shortest Chebyshev recursion (two moments)
-for the residues and the frequency-resolved states."""
+Tamm-Dancoff matrix, the shortest Chebyshev recursion (two moments) for
+the residues and the frequency-resolved states, and the Lanczos either
+side of its single-workgroup size limit."""
 import numpy as np
 import pytest
 
@@ -71,3 +72,28 @@ def test_one_by_one_a_and_two_moments(small):
     assert np.allclose(F, F_o, rtol=1e-10, atol=1e-14)
     dn_o = obse.exciton_density(phi[i:i + 1], phi[a_:a_ + 1], F_o[1, 0])
     assert np.abs(dn[1, 0] - dn_o).max() < 1e-10 * np.abs(dn_o).max()
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("n_o,n_c", [(32, 32), (25, 41)])
+def test_lanczos_at_the_single_workgroup_limit(n_o, n_c):
+    """A of 1024 rows (the largest the single-workgroup Lanczos takes, one
+    element per thread) and of 1025 (one past it: the launch-per-operation
+    schedule): both schedules give the lowest excitons of a dense
+    eigensolve of the same A."""
+    spec = small_spec(n=16, h=0.6, wells=5, seed=7, n_occ=n_o, n_o=n_o, n_c=n_c, n_steps=20, n_stoch=4)
+    sysd = inputs.make_system(spec)
+    s = gpu_system(spec, sysd, 0, max_batch=64)
+    A = s.build_a(n_o, n_c)
+    assert A.shape == (n_o * n_c, n_o * n_c) and np.array_equal(A, A.T)
+    n_exc = 10
+    w_dense = np.linalg.eigvalsh(A)[:n_exc]
+    om0, d0 = s.spectrum(n_exc)
+    s.set_lanczos_path(1)
+    om1, d1 = s.spectrum(n_exc)
+    s.set_lanczos_path(0)
+    scale = max(1.0, np.abs(w_dense).max())
+    say(f"n = {n_o * n_c}: Lanczos vs dense {np.abs(om0 - w_dense).max():.2e} / {np.abs(om1 - w_dense).max():.2e}")
+    assert np.abs(om0 - w_dense).max() < 1e-9 * scale
+    assert np.abs(om1 - w_dense).max() < 1e-9 * scale
+    assert np.allclose(d0, d1, rtol=1e-6, atol=1e-12)
