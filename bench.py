@@ -129,6 +129,49 @@ def cpu_baseline(spec, sysd, pair, steps_sample: int):
     return w.reshape(1, -1), wp.reshape(1, -1), per_solve, t
 
 
+_PAR_CHILD = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from paper_2205_06690_amd import inputs
+from oracle.grid import Grid
+from oracle import tdh
+spec = inputs.CONFIGS[sys.argv[2]]
+pair, steps = (int(sys.argv[3]), int(sys.argv[4])), int(sys.argv[5])
+sysd = inputs.make_system(spec)
+grid = Grid(spec.shape, spec.h)
+phi = sysd["phi"].reshape((-1,) + spec.shape)
+eta0 = tdh.stochastic_orbitals(phi[:spec.n_occ], sysd["xi"])
+t0 = time.perf_counter()
+tdh.apply_w(grid, sysd["v_ext"], phi, spec.n_occ, [pair], eta0, dt=spec.dt, n_steps=steps,
+            gamma=spec.gamma_eff, clean_every=spec.clean_every)
+print(json.dumps({"seconds": time.perf_counter() - t0}))
+"""
+
+
+def cpu_parallel_baseline(config: str, spec, pairs, steps: int, procs: int):
+    """The embarrassingly parallel form of the oracle: ``procs`` one-thread
+    processes at once, each on its own pair for ``steps`` time steps (child
+    processes that never touch the GPU).  Returns pair solves/s of the full
+    propagation over all processes and the per-process seconds."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, BSE_ORACLE_THREADS="1", OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    ch = []
+    for k in range(procs):
+        i, j = (int(x) for x in pairs[k % len(pairs)])
+        ch.append(subprocess.Popen([sys.executable, "-c", _PAR_CHILD, here, config, str(i), str(j), str(steps)],
+                                   env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+    secs = []
+    for c in ch:
+        out, err = c.communicate()
+        if c.returncode != 0:
+            raise RuntimeError(f"oracle child failed: {err[-500:]}")
+        secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
+    per_solve = max(secs) * spec.n_steps / steps
+    return procs / per_solve, secs
+
+
 def bench_uneven(args):
     """The uneven batch: 32 synthetic molecules on {32,48,64}^3 grids with
     10-80 wells, N_occ 10-100 and 16-200 pair densities each, L = 10,
@@ -275,6 +318,8 @@ def main():
     ap.add_argument("--config", default="mid64")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-par-steps", type=int, default=10,
+                    help="steps per process of the one-process-per-core oracle sample (0 = skip)")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps of the CPU sample (0: 200 at 64^3, 40 at 112^3)")
     ap.add_argument("--n-systems", type=int, default=32)
@@ -536,6 +581,16 @@ def main():
             "cores": os.cpu_count(), "kind": "oracle",
             "sample": f"1 pair x {args.cpu_steps} of {spec.n_steps} steps "
                       f"({t_cpu:.1f}s), scaled linearly to the full propagation"}
+        # the same oracle as one one-thread process per core, each on its own
+        # pair (the embarrassingly parallel form), on a shorter sample
+        if args.cpu_par_steps > 0:
+            procs = os.cpu_count() or 1
+            rate, secs = cpu_parallel_baseline(args.config, spec, pairs, args.cpu_par_steps, procs)
+            out["cpu_baseline"]["parallel"] = {
+                "value": round(rate, 6), "unit": "pair solves/s", "processes": procs,
+                "threads_per_process": 1,
+                "sample": f"{procs} pairs at once x {args.cpu_par_steps} of {spec.n_steps} steps "
+                          f"(slowest {max(secs):.1f}s), scaled linearly"}
         out["parity_sample"] = {"pair": list(pair), "steps": args.cpu_steps,
                                 "rel_err_W": rel_w, "rel_err_Wpol": rel_wp}
     print(json.dumps(out), flush=True)

@@ -19,7 +19,8 @@ import numpy as np
 
 try:
     import scipy.fft as _sfft
-    _W = os.cpu_count() or 1
+    # FFT threads: BSE_ORACLE_THREADS if set (one-core runs), else every core
+    _W = int(os.environ.get("BSE_ORACLE_THREADS", "0")) or os.cpu_count() or 1
 
     def fftn(x):
         return _sfft.fftn(x, axes=(-3, -2, -1), workers=_W)
