@@ -39,8 +39,10 @@ def _alg_bytes(kernel: str, B: int, L: int, ng: int, cbytes: int) -> float:
     rbytes = cbytes // 2
     if kernel == "prop_x":
         return 2.0 * F * ng * cbytes + L * ng * cbytes + B * ng * rbytes
-    if kernel == "prop_yz":
+    if kernel in ("prop_yz", "prop_y"):
         return 2.0 * F * ng * cbytes + L * ng * cbytes + B * ng * rbytes
+    if kernel == "prop_z":
+        return 2.0 * F * ng * cbytes
     return float("nan")
 
 
@@ -409,7 +411,8 @@ def main():
           file=sys.stderr, flush=True)
 
     cbytes = 8 if prec == bse.BSE_MIXED else 16
-    dom = max(("prop_x", "prop_yz"), key=lambda k: kt.get(k, (0.0, 0))[0] * kt.get(k, (0.0, 0))[1])
+    dom = max(("prop_x", "prop_yz", "prop_z", "prop_y"),
+              key=lambda k: kt.get(k, (0.0, 0))[0] * kt.get(k, (0.0, 0))[1])
     avg_ms = kt[dom][0]
     alg = _alg_bytes(dom, B, spec.n_stoch, spec.ng, cbytes)
     achieved = alg / (avg_ms * 1e-3) / 1e9

@@ -279,7 +279,7 @@ bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
 /* Kernel schedule of bse_spectrum's Lanczos iteration (the arithmetic and
  * the convergence checks are the same either way; results agree to
- * rounding).  0 (default): for n_o n_c <= 1024 every step up to the next
+ * rounding).  0 (default): for n_o n_c <= 384 every step up to the next
  * convergence check runs in one single-workgroup launch with its vectors
  * in LDS; larger A take path 1.  1: one chip-wide launch per operation of
  * every step.  Errors: BSE_ERR_ARG for other values. */

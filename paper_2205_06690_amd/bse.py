@@ -345,7 +345,7 @@ class System:
 
     def set_lanczos_path(self, path):
         """0: single-workgroup launches up to each convergence check where A
-        fits (n <= 1024); 1: a chip-wide launch per operation."""
+        pays (n <= 384); 1: a chip-wide launch per operation."""
         _check(LIB.bse_set_lanczos_path(self._h, int(path)))
 
     def kernel_times(self):

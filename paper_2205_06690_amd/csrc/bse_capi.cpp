@@ -396,9 +396,12 @@ void propagate_batch(bse_system* s, int B) {
     pz.dens = s->dens.as<T>();
     pz.L = L;
     pz.density = 1;
-    auto* t2 = s->timer.slot("prop_yz", 1);
+    const bool split = prop_yz_split<T>(s->n);
+    auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
+    auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
     const LaunchEvents e2{t2 ? t2->first : nullptr, t2 ? t2->second : nullptr};
-    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt, t2 ? &e2 : nullptr));
+    const LaunchEvents e3{t3 ? t3->first : nullptr, t3 ? t3->second : nullptr};
+    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt, t2 ? &e2 : nullptr, t3 ? &e3 : nullptr));
     const bool do_clean = M > 0 && ((n + 1) % M == 0);
     const double wn = s->wts[n + 1];
     if (!do_clean) {

@@ -995,10 +995,12 @@ hipError_t launch_exciton_density(const double* phi, int v0, int c0, int n_o, in
                      st, phi, v0, c0, n_o, n_c, ng, F, n_out, dens);
   return hipGetLastError();
 }
-// one workgroup holds one element of every vector per thread; beyond that,
-// and where one CU's share of bandwidth no longer beats the launch cost,
-// the chip-wide kernels of the other path take over
-int lanczos_fused_max() { return LZ_T; }
+// One CU streams A once per step (about 4.6e-4 n^2 us measured: 18 us at
+// n = 200, 290 us at n = 800) where the chip-wide path pays about 70 us of
+// launches per step: the single workgroup wins up to n ~ 390.
+constexpr int LZ_MAX = 384;
+static_assert(LZ_MAX <= LZ_T, "one element of every vector per thread");
+int lanczos_fused_max() { return LZ_MAX; }
 hipError_t launch_lanczos_steps(const double* A, int n, double* V, int k0, int k1, double* al, double* bq,
                                 hipStream_t st) {
   if (n < 1 || n > lanczos_fused_max() || k0 < 0 || k1 > n || k0 >= k1) return hipErrorInvalidValue;

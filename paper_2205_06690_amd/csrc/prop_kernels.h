@@ -83,8 +83,13 @@ struct LaunchEvents {
 // ev: nullable timing events
 template <typename T> hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, int tc = 0,
                                                const LaunchEvents* ev = nullptr);
+// grids whose y-z plane would leave one block per CU (prop_yz_split) run the
+// y and z factors as a z-line and a y-line pass: ev then times the z pass
+// and ev2 the y pass; otherwise ev times the plane pass and ev2 is unused
 template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt = 0,
-                                                const LaunchEvents* ev = nullptr);
+                                                const LaunchEvents* ev = nullptr,
+                                                const LaunchEvents* ev2 = nullptr);
+template <typename T> bool prop_yz_split(int n);
 template <typename T> hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_stoch_orbitals(const double* phi, const signed char* xi, int L, int n_occ,

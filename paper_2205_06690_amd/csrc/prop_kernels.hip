@@ -300,6 +300,118 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// The y and z factors as two line passes, for grids whose y-z plane would
+// leave one block per compute unit (112^3 in FP32: 101 KB of LDS, and the
+// lone block's barriers idle the CU): a z-line pass over tiles of PZ_TL
+// contiguous lines, then a y-line pass over tiles of PY_TZ z columns of one
+// x plane, which also forms the induced density of a pair's L orbitals.
+// One more HBM pass, in exchange for several small blocks per CU.
+// ---------------------------------------------------------------------------
+constexpr int PZ_TL = 32, PY_TZ = 16, PY_ES = PY_TZ + 1, PY_NT = 128;
+
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_prop_z(PropYZArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int TL = PZ_TL, S = N + 1, E = TL * N;
+  const size_t ng = (size_t)N * N * N;
+  const int tid = threadIdx.x;
+  C* d = a.d + (size_t)blockIdx.y * ng + (size_t)blockIdx.x * E;
+  C* tws = s + TL * S;
+  stage_tables<N>(tws, a.tw, a.kph, tid, 256);
+  for (int e = tid; e < E; e += 256) s[(e / N) * S + e % N] = d[e];
+  __syncthreads();
+  const C* kp = tws + N;
+  auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
+  // z lines: line = (x, y) row (stride S), elements contiguous
+  stageA_fwd<N>(s, TL, S, 1, tws, tid, 256, true);
+  __syncthreads();
+  stageB<N, 2>(s, TL, S, 1, tws, tid, 256, true, mul);
+  __syncthreads();
+  stageC_inv<N>(s, TL, S, 1, tid, 256, true);
+  __syncthreads();
+  for (int e = tid; e < E; e += 256) d[e] = s[(e / N) * S + e % N];
+}
+
+// y lines of one tile: line = z column c (stride 1), element y at y * PY_ES
+template <int N, typename T>
+__device__ __forceinline__ void kinetic_y_tile(cplx<T>* s, const cplx<T>* __restrict__ tw,
+                                               const cplx<T>* __restrict__ kp, int tid) {
+  using C = cplx<T>;
+  auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
+  stageA_fwd<N>(s, PY_TZ, 1, PY_ES, tw, tid, PY_NT, true);
+  __syncthreads();
+  stageB<N, 2>(s, PY_TZ, 1, PY_ES, tw, tid, PY_NT, true, mul);
+  __syncthreads();
+  stageC_inv<N>(s, PY_TZ, 1, PY_ES, tid, PY_NT, true);
+  __syncthreads();
+}
+
+// grid (fields or pairs, tiles): the pairs of one tile run together and
+// share its unperturbed-orbital tiles in L2
+template <int N, typename T, bool DENS>
+__global__ void __launch_bounds__(PY_NT) k_prop_y(PropYZArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  constexpr int TZ = PY_TZ, E = N * TZ, PER = E / PY_NT;
+  static_assert(N % TZ == 0 && E % PY_NT == 0, "tiles must divide the grid");
+  const size_t ng = (size_t)N * N * N;
+  const int tid = threadIdx.x, b = blockIdx.x, tile = blockIdx.y;
+  const int x = tile / (N / TZ), z0 = (tile % (N / TZ)) * TZ;
+  const size_t off = (size_t)x * N * N + z0;
+  C* tws = s + N * PY_ES;
+  stage_tables<N>(tws, a.tw, a.kph, tid, PY_NT);
+  // element e of the tile: y = e / TZ, column c = e % TZ
+  auto gi = [](int e) { return (size_t)(e / TZ) * N + (e % TZ); };
+  auto li = [](int e) { return (e / TZ) * PY_ES + (e % TZ); };
+  if (!DENS) {
+    C* d = a.d + (size_t)b * ng + off;
+    for (int e = tid; e < E; e += PY_NT) s[li(e)] = d[gi(e)];
+    __syncthreads();
+    kinetic_y_tile<N, T>(s, tws, tws + N, tid);
+    for (int e = tid; e < E; e += PY_NT) d[gi(e)] = s[li(e)];
+    return;
+  }
+  T acc[PER];
+  C dn[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    acc[i] = 0;
+    dn[i] = a.d[((size_t)b * a.L) * ng + off + gi(tid + i * PY_NT)];
+  }
+  for (int l = 0; l < a.L; ++l) {
+    C* d = a.d + ((size_t)b * a.L + l) * ng + off;
+    const C* __restrict__ h = a.H + (size_t)l * ng + off;
+    C hc[PER];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) s[li(tid + i * PY_NT)] = dn[i];
+    __syncthreads();
+    // the next orbital's tile and this orbital's unperturbed tile load
+    // during the transform
+    if (l + 1 < a.L) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) dn[i] = d[ng + gi(tid + i * PY_NT)];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) hc[i] = h[gi(tid + i * PY_NT)];
+    kinetic_y_tile<N, T>(s, tws, tws + N, tid);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * PY_NT;
+      const C v = s[li(e)];
+      d[gi(e)] = v;
+      acc[i] += hc[i].x * v.x + hc[i].y * v.y;
+    }
+  }
+  T* dn_out = a.dens + (size_t)b * ng + off;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) dn_out[gi(tid + i * PY_NT)] = (T)4 * acc[i];
+}
+
+// ---------------------------------------------------------------------------
 // Coulomb potential v[rho] of real densities, two packed per complex field
 // (the 4 pi/k^2 kernel is real and even, so re and im stay independent).
 // ---------------------------------------------------------------------------
@@ -876,7 +988,28 @@ struct Launch {
       go(k_prop_yz<N, T, NT, false>, dim3(N, nb), dim3(NT), sm, st, ev, a);
     return hipGetLastError();
   }
-  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt, const LaunchEvents* ev) {
+  static constexpr bool yz_split() { return yz_lds<N, T>() > 80 * 1024; }
+  // the two line passes: ev times the z pass, ev2 the y pass
+  static hipError_t prop_zy(const PropYZArgs<T>& a, int nb, hipStream_t st, const LaunchEvents* ev,
+                            const LaunchEvents* ev2) {
+    if constexpr (N % PY_TZ == 0 && (N * N) % PZ_TL == 0 && (N * PY_TZ) % PY_NT == 0) {
+      const int F = a.density ? nb * a.L : nb;
+      const size_t smz = sizeof(cplx<T>) * ((size_t)PZ_TL * (N + 1) + 2 * N);
+      const size_t smy = sizeof(cplx<T>) * ((size_t)N * PY_ES + 2 * N);
+      go(k_prop_z<N, T>, dim3(N * N / PZ_TL, F), dim3(256), smz, st, ev, a);
+      const dim3 gy(nb, N * (N / PY_TZ));
+      if (a.density)
+        go(k_prop_y<N, T, true>, gy, dim3(PY_NT), smy, st, ev2, a);
+      else
+        go(k_prop_y<N, T, false>, gy, dim3(PY_NT), smy, st, ev2, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt, const LaunchEvents* ev,
+                            const LaunchEvents* ev2) {
+    if constexpr (yz_split()) return prop_zy(a, nb, st, ev, ev2);
     if (nt == 0) nt = yz_threads<N>();
     switch (nt) {
       case 256: return prop_yz_nt<256>(a, nb, st, ev);
@@ -890,8 +1023,9 @@ struct Launch {
     const int M = (a.B + 1) / 2;
     const size_t smp = yz_lds<N, T>();
     const size_t smx = x_lds<N, TC, T>();
-    if constexpr (yz_lds<N, T>() > 160 * 1024) {
-      // the plane does not fit: separate z-line and y-line passes
+    if constexpr (yz_lds<N, T>() > 80 * 1024) {
+      // the plane does not fit, or would leave one block per CU: separate
+      // z-line and y-line passes
       static_assert(N % PL_TL == 0, "line tiles must divide the grid");
       const size_t smz = sizeof(cplx<T>) * ((size_t)PL_TL * (N + 1) + N);
       const size_t smy = sizeof(cplx<T>) * ((size_t)PL_TL * N + N);
@@ -962,8 +1096,20 @@ hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int F, hipStream_t st, in
 }
 template <typename T>
 hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt,
-                          const LaunchEvents* ev) {
-  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st, nt, ev));
+                          const LaunchEvents* ev, const LaunchEvents* ev2) {
+  BSE_DISPATCH_N(n, T, prop_yz(a, nb, st, nt, ev, ev2));
+}
+template <typename T>
+bool prop_yz_split(int n) {
+  switch (n) {
+    case 16: return Launch<16, T>::yz_split();
+    case 24: return Launch<24, T>::yz_split();
+    case 32: return Launch<32, T>::yz_split();
+    case 48: return Launch<48, T>::yz_split();
+    case 64: return Launch<64, T>::yz_split();
+    case 112: return Launch<112, T>::yz_split();
+    default: return false;
+  }
 }
 template <typename T>
 hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st) {
@@ -1092,7 +1238,8 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
   template hipError_t launch_prop_x<T>(int, const PropXArgs<T>&, int, hipStream_t, int,        \
                                        const LaunchEvents*);                                     \
   template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t, int,      \
-                                        const LaunchEvents*);                                    \
+                                        const LaunchEvents*, const LaunchEvents*);               \
+  template bool prop_yz_split<T>(int);                                                         \
   template hipError_t launch_poisson<T>(int, const PoisArgs<T>&, hipStream_t);                 \
   template void configure_kernels<T>(int);                                                     \
   template bool grid_supported<T>(int);                                                        \

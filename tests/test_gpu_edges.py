@@ -75,12 +75,12 @@ def test_one_by_one_a_and_two_moments(small):
 
 
 @pytest.mark.timeout(400)
-@pytest.mark.parametrize("n_o,n_c", [(32, 32), (25, 41)])
+@pytest.mark.parametrize("n_o,n_c", [(12, 32), (11, 35), (32, 32)])
 def test_lanczos_at_the_single_workgroup_limit(n_o, n_c):
-    """A of 1024 rows (the largest the single-workgroup Lanczos takes, one
-    element per thread) and of 1025 (one past it: the launch-per-operation
-    schedule): both schedules give the lowest excitons of a dense
-    eigensolve of the same A."""
+    """A of 384 rows (the largest the single-workgroup Lanczos takes), of
+    385 (one past it: the launch-per-operation schedule) and of 1024: both
+    schedules give the lowest excitons of a dense eigensolve of the same
+    A."""
     spec = small_spec(n=16, h=0.6, wells=5, seed=7, n_occ=n_o, n_o=n_o, n_c=n_c, n_steps=20, n_stoch=4)
     sysd = inputs.make_system(spec)
     s = gpu_system(spec, sysd, 0, max_batch=64)
