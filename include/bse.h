@@ -18,8 +18,8 @@
  * Conventions
  *   - Grid: cubic n x n x n, spacing h (bohr), periodic, row-major with z
  *     fastest; grid point (i,j,k) sits at (i h, j h, k h).  Integrals are
- *     sums times h^3.  Supported n: 16, 24, 32, 48, 64 and 112 (FP64 mode:
- *     up to 64).
+ *     sums times h^3.  Supported n: 16, 24, 32, 48, 64 and 112, in both
+ *     precisions.
  *   - Orbitals: real, sum_r |phi|^2 h^3 = 1, ascending eps; orbitals
  *     0..n_occ-1 are occupied.  Units: Hartree atomic units.
  *   - The Coulomb kernel is periodic, 4 pi/|k|^2 with k = 0 removed.

@@ -1050,6 +1050,7 @@ struct Launch {
     }
   }
   template <int NT> static void conf_yz() {
+    if constexpr (yz_lds<N, T>() > 160 * 1024) return;   // the plane kernels never run
     const int smp = (int)yz_lds<N, T>();
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     (void)hipFuncSetAttribute((const void*)k_prop_yz<N, T, NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
@@ -1064,19 +1065,30 @@ struct Launch {
     conf_x<64>();
     conf_yz<256>();
     conf_yz<512>();
-    (void)hipFuncSetAttribute((const void*)k_poisson_yz_fwd<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
-    (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    if constexpr (yz_lds<N, T>() <= 160 * 1024) {
+      (void)hipFuncSetAttribute((const void*)k_poisson_yz_fwd<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+      (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
+    }
     (void)hipFuncSetAttribute((const void*)k_poisson_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
   }
 };
 
+// a grid is supported when its line transforms are instantiated and its y-z
+// step fits: the plane pass needs the padded plane in LDS, the line passes
+// (taken where the plane would leave one block per CU) only their tiles
 template <typename T>
 bool grid_supported(int n) {
-  if (sizeof(cplx<T>) * ((size_t)n * (n + 1) + 2 * (size_t)n) > 160 * 1024) return false;
+  bool split;
   switch (n) {
-    case 16: case 24: case 32: case 48: case 64: case 112: return true;
+    case 16: split = Launch<16, T>::yz_split(); break;
+    case 24: split = Launch<24, T>::yz_split(); break;
+    case 32: split = Launch<32, T>::yz_split(); break;
+    case 48: split = Launch<48, T>::yz_split(); break;
+    case 64: split = Launch<64, T>::yz_split(); break;
+    case 112: split = Launch<112, T>::yz_split(); break;
     default: return false;
   }
+  return split || sizeof(cplx<T>) * ((size_t)n * (n + 1) + 2 * (size_t)n) <= 160 * 1024;
 }
 
 #define BSE_DISPATCH_N(n, T, CALL)                \
@@ -1123,7 +1135,7 @@ void configure_kernels(int n) {
     case 32: Launch<32, T>::configure(); break;
     case 48: Launch<48, T>::configure(); break;
     case 64: Launch<64, T>::configure(); break;
-    case 112: if (sizeof(T) == 4) Launch<112, float>::configure(); break;
+    case 112: Launch<112, T>::configure(); break;
     default: break;
   }
 }

@@ -8,7 +8,8 @@ outputs that the FP64 oracle computes one by one.
   diagonal, Eq. 1).
 * paper112 (112^3, N_occ = 260): a 16-pair batch over 60 steps (the oracle
   cost of the full 600 steps is out of reach here), one pair checked over
-  the whole grid.
+  the whole grid, in mixed precision and in FP64; mixed against FP64 on
+  all 16 pairs.
 Bars: 1e-3 relative on W; for A, the direct-term error that a 1e-3 error
 on W allows, measured against the block's direct term."""
 import dataclasses
@@ -179,3 +180,14 @@ def test_paper112_batch_sampled_pair():
     say(f"paper112: rel W {rw:.3e}  rel Wpol {rwp:.3e}")
     assert rw < 1e-3
     assert rwp < 1e-2
+    # the same batch in FP64 on the same GPU (the y and z factors in line
+    # passes): equal to the oracle, and the mixed form against it pair by pair
+    say("paper112: FP64 batch")
+    s64 = gpu_system(spec, sysd, bse.BSE_FP64, max_batch=len(pairs))
+    w64, wp64 = s64.apply_w(pairs, want_wpol=True)
+    s64.close()
+    r64 = float(rel(w64[k], w_o.reshape(-1)))
+    rmix = float(rel(w, w64).max())
+    say(f"paper112: FP64 rel W {r64:.3e}; mixed vs FP64, worst of 16 pairs {rmix:.3e}")
+    assert r64 < 1e-10
+    assert rmix < 1e-3
