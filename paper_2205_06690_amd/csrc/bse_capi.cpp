@@ -151,6 +151,7 @@ struct bse_system {
   // batch workspace
   int cap_b = 0;
   DBuf d, u, dens, wpol, q, rho64, work, work64, part, part32, gpart, coef, coefE, E, pq_d, flags;
+  DBuf pscale;    // [B][3] row sums of q, then [B] per-pair scales of the packed Poisson solves
   int nchunk = 0;
   // A / spectrum state
   int a_no = 0, a_nc = 0;
@@ -263,6 +264,7 @@ void ensure_batch(bse_system* s, int B) {
   s->pq_d.alloc(sizeof(int) * 2 * B);
   s->flags.alloc(sizeof(int) * B);
   s->work64.alloc(sizeof(cplx<double>) * ng * (size_t)((B + 1) / 2));
+  s->pscale.alloc(sizeof(double) * 4 * (size_t)B);
   s->cap_b = B;
 }
 
@@ -320,6 +322,7 @@ void poissonT(bse_system* s, int B, double* acc, double wn) {
   a.out = s->u.as<T>();
   a.acc = acc;
   a.wn = wn;
+  a.pscale = s->pscale.as<double>() + 3 * (size_t)B;
   auto* t = s->timer.begin("poisson");
   HIPC(launch_poisson<T>(s->n, a, s->stream));
   s->timer.end(t);
@@ -341,6 +344,12 @@ void propagate_batch(bse_system* s, int B) {
   hipStream_t st = s->stream;
   HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, ng, s->rho64.as<double>(), st));
   poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0);
+  // per-pair scales for the packed Poisson solves of the induced densities:
+  // the RMS of q_b (the response is linear in it), so that a pair whose
+  // source is orders of magnitude weaker than its partner's is not buried
+  // in the partner's rounding
+  HIPC(launch_row_dots(s->q.as<double>(), nullptr, nullptr, B, ng, s->pscale.as<double>(), st));
+  HIPC(launch_rms_scales(s->pscale.as<double>(), B, ng, s->pscale.as<double>() + 3 * (size_t)B, st));
   HIPC(launch_fill_zero(s->wpol.p, sizeof(double) * ng * B, st));
   HIPC(launch_fill_zero(s->u.p, sizeof(T) * ng * B, st));
   HIPC(launch_kick<T>(s->q.as<double>(), s->eta0.as<double>(), L, F, ng, s->d.as<C>(), st));

@@ -93,6 +93,8 @@ hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double
 size_t boundary_part_elems(int n);
 hipError_t launch_boundary_average(const double* vext, const double* vh, int n, double* part, double* out,
                                    hipStream_t st);
+// scale[b] = RMS of row b from launch_row_dots' sums (1 for a zero row)
+hipError_t launch_rms_scales(const double* dots, int B, size_t ng, double* scale, hipStream_t st);
 hipError_t launch_row_dots(const double* a, const double* c, const double* d, int B, size_t ng,
                            double* out, hipStream_t st);
 hipError_t launch_features(const double* q, const double* scale, const double* n0, double n0s,

@@ -1188,6 +1188,17 @@ hipError_t launch_ground_density(const double* phi, int n_occ, size_t ng, double
                      ng, n0);
   return hipGetLastError();
 }
+// scale[b] = sqrt(dots[b][0] / ng) (the RMS of a row), 1 for a zero row
+__global__ void k_rms_scales(const double* __restrict__ dots, int B, size_t ng, double* __restrict__ scale) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double r = sqrt(dots[(size_t)b * 3] / (double)ng);
+  scale[b] = r > 0.0 ? r : 1.0;
+}
+hipError_t launch_rms_scales(const double* dots, int B, size_t ng, double* scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_rms_scales, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, dots, B, ng, scale);
+  return hipGetLastError();
+}
 hipError_t launch_row_dots(const double* a, const double* c, const double* d, int B, size_t ng,
                            double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_row_dots, dim3(B), dim3(256), 0, st, a, c, d, ng, out);

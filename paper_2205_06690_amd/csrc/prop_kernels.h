@@ -44,6 +44,9 @@ template <typename T> struct PoisArgs {
   double* acc;         // nullable [B][ng]: acc += wn * v[rho]
   double wn;
   int kinetic;         // 1: multiplier vscale k^2/2 (the kinetic operator) instead of vscale/k^2
+  const double* pscale;  // nullable [B]: density b enters its packed transform as rho_b / pscale[b]
+                         // and its potential leaves times pscale[b], so that two packed
+                         // densities of very different size keep their own relative rounding
 };
 
 template <typename T> struct CleanArgs {

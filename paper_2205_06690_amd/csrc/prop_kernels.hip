@@ -429,7 +429,9 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
   const T* r1 = (b1 < a.B) ? a.rho + (size_t)b1 * ng + (size_t)x * P : nullptr;
   C* tw = s + N * S;
   stage_tables<N, C>(tw, a.tw, nullptr, tid, NT);
-  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
+  const T i0 = a.pscale ? (T)(1.0 / a.pscale[b0]) : (T)1;
+  const T i1 = (a.pscale && r1) ? (T)(1.0 / a.pscale[b1]) : (T)1;
+  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = cmk<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0);
   __syncthreads();
   NoMul nm;
   stageA_fwd<N>(s, N, S, 1, tw, tid, NT, true);
@@ -511,8 +513,10 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_inv(PoisArgs<T> a) {
   const size_t o0 = (size_t)b0 * ng + (size_t)x * P;
   const size_t o1 = (size_t)b1 * ng + (size_t)x * P;
   const bool has1 = b1 < a.B;
+  const double c0 = a.pscale ? a.pscale[b0] : 1.0, c1 = (a.pscale && has1) ? a.pscale[b1] : 1.0;
   for (int e = tid; e < P; e += NT) {
-    const C v = s[plane_idx<N>(e)];
+    C v = s[plane_idx<N>(e)];
+    if (a.pscale) v = cmk<C>((T)(c0 * v.x), (T)(c1 * v.y));
     if (a.out) {
       a.out[o0 + e] = v.x;
       if (has1) a.out[o1 + e] = v.y;
@@ -554,7 +558,10 @@ __global__ void __launch_bounds__(256) k_poisson_z(PoisArgs<T> a, int dir) {
   if (dir == 0) {
     const T* r0 = a.rho + (size_t)b0 * ng + base;
     const T* r1 = has1 ? a.rho + (size_t)b1 * ng + base : nullptr;
-    for (int e = tid; e < E; e += 256) s[(e / N) * S + e % N] = cmk<C>(r0[e], r1 ? r1[e] : (T)0);
+    const T i0 = a.pscale ? (T)(1.0 / a.pscale[b0]) : (T)1;
+    const T i1 = (a.pscale && has1) ? (T)(1.0 / a.pscale[b1]) : (T)1;
+    for (int e = tid; e < E; e += 256)
+      s[(e / N) * S + e % N] = cmk<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0);
     __syncthreads();
     stageA_fwd<N>(s, TL, S, 1, tw, tid, 256, true);
     __syncthreads();
@@ -572,8 +579,10 @@ __global__ void __launch_bounds__(256) k_poisson_z(PoisArgs<T> a, int dir) {
   stageC_inv<N>(s, TL, S, 1, tid, 256, true);
   __syncthreads();
   const size_t o0 = (size_t)b0 * ng + base, o1 = (size_t)b1 * ng + base;
+  const double c0 = a.pscale ? a.pscale[b0] : 1.0, c1 = (a.pscale && has1) ? a.pscale[b1] : 1.0;
   for (int e = tid; e < E; e += 256) {
-    const C v = s[(e / N) * S + e % N];
+    C v = s[(e / N) * S + e % N];
+    if (a.pscale) v = cmk<C>((T)(c0 * v.x), (T)(c1 * v.y));
     if (a.out) {
       a.out[o0 + e] = v.x;
       if (has1) a.out[o1 + e] = v.y;

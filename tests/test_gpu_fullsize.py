@@ -191,3 +191,15 @@ def test_paper112_batch_sampled_pair():
     say(f"paper112: FP64 rel W {r64:.3e}; mixed vs FP64, worst of 16 pairs {rmix:.3e}")
     assert r64 < 1e-10
     assert rmix < 1e-3
+    # a pair whose source is 2e5 times weaker than the pair it shares a
+    # packed Poisson transform with (orbitals on the ring and in the sphere)
+    # keeps its own accuracy: 3e-3 before the per-pair scaling, 1e-5 after
+    weak = np.array([[252, 259], [240, 240]], dtype=np.int32)
+    res = []
+    for prec in (bse.BSE_MIXED, bse.BSE_FP64):
+        sw = gpu_system(spec, sysd, prec, max_batch=2)
+        res.append(sw.apply_w(weak)[0])
+        sw.close()
+    rweak = rel(res[0], res[1])
+    say(f"paper112: weak pair packed with a strong one, mixed vs FP64 {rweak}")
+    assert rweak.max() < 1e-4
