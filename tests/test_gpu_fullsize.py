@@ -5,11 +5,12 @@ outputs that the FP64 oracle computes one by one.
   the benchmark times -- mixed precision, all 55 valence pairs in one batch
   -- checked on one pair's W (and W^pol) over the whole grid, and on the
   20 x 20 block of A that this pair's W_ij feeds (direct + exchange +
-  diagonal, Eq. 1).
+  diagonal, Eq. 1); the 20 lowest excitons within 1 meV of the FP64 form
+  on the same GPU.
 * paper112 (112^3, N_occ = 260): a 16-pair batch over 60 steps (the oracle
   cost of the full 600 steps is out of reach here), one pair checked over
   the whole grid, in mixed precision and in FP64; mixed against FP64 on
-  all 16 pairs.
+  all 16 pairs, and on a weak pair packed with a strong one.
 Bars: 1e-3 relative on W; for A, the direct-term error that a 1e-3 error
 on W allows, measured against the block's direct term."""
 import dataclasses
@@ -51,6 +52,16 @@ def test_mid64_bench_batch_w_and_a_block():
     say(f"mid64: Lanczos vs dense {e_dense:.2e}, paths {np.abs(om1 - om).max():.2e}")
     assert e_dense < 1e-9 and np.abs(om1 - om).max() < 1e-12
     assert np.allclose(d21, d2, rtol=1e-8, atol=1e-14)
+    # the whole A in FP64 on the same GPU (W of every pair equal to the
+    # oracle's to ~1e-13 at the sizes the oracle reaches): the mixed A's 20
+    # lowest excitons within 1 meV of it
+    s64 = gpu_system(spec, sysd, bse.BSE_FP64, max_batch=len(pairs))
+    A64 = s64.build_a(spec.n_o, spec.n_c)
+    om64, _ = s64.spectrum(20)
+    s64.close()
+    d_mev = np.abs(om - om64).max() * inputs.HARTREE_EV * 1e3
+    say(f"mid64: max|A - A_fp64| {np.abs(A - A64).max():.2e} Ha, excitons {d_mev:.4f} meV")
+    assert d_mev < 1.0
     wg = np.linspace(om[0] - 10 * sig, om[-1] + 0.1, 2000)
     _, _, bo = s.chebyshev_spectrum(2, None)                # the Gershgorin interval
     # the Gaussian's Chebyshev coefficients fall as exp(-(n sig / a)^2 / 2):
