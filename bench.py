@@ -114,6 +114,18 @@ def _traffic_bytes(kernel: str, workload: str):
     return None
 
 
+def _cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), for the CPU baseline."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, sysd, pair, steps_sample: int):
     """The FP64 oracle on one pair for ``steps_sample`` time steps, scaled to
     pair solves per second of the full ``spec.n_steps`` propagation."""
@@ -581,7 +593,7 @@ def main():
         rel_wp = float(np.linalg.norm(wp_g - wp_o) / np.linalg.norm(wp_o))
         out["cpu_baseline"] = {
             "value": round(1.0 / per_solve, 6), "unit": "pair solves/s",
-            "cores": os.cpu_count(), "kind": "oracle",
+            "cores": os.cpu_count(), "cpu": _cpu_model(), "kind": "oracle",
             "sample": f"1 pair x {args.cpu_steps} of {spec.n_steps} steps "
                       f"({t_cpu:.1f}s), scaled linearly to the full propagation"}
         # the same oracle as one one-thread process per core, each on its own
