@@ -273,7 +273,8 @@ def bench_surrogate(args):
                   bf16_weights=True, seed=0)
     t1 = time.perf_counter()
     hist = surrogate.train(net, x_tr, t_tr, epochs=args.epochs, batch=args.sur_batch, lr=args.lr,
-                           lr_end=args.lr * 0.01, log=log, time_limit=args.train_seconds)
+                           lr_end=args.lr * 0.01, log=log, time_limit=args.train_seconds,
+                           augment=not args.no_augment)
     t_train = time.perf_counter() - t1
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -308,7 +309,8 @@ def bench_surrogate(args):
                                f"targets from {args.sur_steps}-step propagation (L=10, dt=0.05); network: "
                                f"4 Fourier layers, width 32, modes kx,ky in [-{args.modes},{args.modes}), "
                                f"kz in [0,{args.modes}), BF16 weights, FP32 accumulation",
-                   "params": net.n_params, "epochs_run": len(hist), "batch": args.sur_batch},
+                   "params": net.n_params, "epochs_run": len(hist), "batch": args.sur_batch,
+                   "augment": "cube symmetries" if not args.no_augment else None},
         "train_loss": [round(v, 6) for v in hist],
         "heldout_rel_err_Wpol": {"median": float(np.median(rel_wpol)), "p90": float(np.quantile(rel_wpol, 0.9))},
         "heldout_rel_err_W": {"median": float(np.median(rel_w)), "p90": float(np.quantile(rel_w, 0.9)),
@@ -344,6 +346,8 @@ def main():
     ap.add_argument("--modes", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--no-augment", action="store_true",
+                    help="train the surrogate without the cube-symmetry augmentation")
     ap.add_argument("--train-seconds", type=float, default=420.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev, mixed, box)")

@@ -69,10 +69,19 @@ def generate(specs, limit: Optional[int] = None, log=print):
     return torch.cat(xs), torch.cat(ts), torch.cat(ss)
 
 
+def _cube_symmetry(rng):
+    """A random element of the cube's symmetry group: an axis permutation and
+    a set of axes to reverse.  On the periodic cubic grid the kinetic and
+    Coulomb operators commute with both, so a molecule mapped by one of them
+    has the mapped response: 48 molecules per training molecule."""
+    return tuple(int(a) for a in rng.permutation(3)), tuple(int(a) for a in np.nonzero(rng.integers(0, 2, 3))[0])
+
+
 def train(net: "bse.Fno", x, t, epochs: int, batch: int, lr: float, lr_end: float,
-          seed: int = 0, log=print, time_limit: Optional[float] = None):
+          seed: int = 0, log=print, time_limit: Optional[float] = None, augment: bool = True):
     """Adam with a cosine learning-rate decay; returns the per-epoch mean
-    training loss."""
+    training loss.  With augment, each batch goes through a random symmetry
+    of the cube (fields [batch][channel][x][y][z], targets [batch][x][y][z])."""
     import torch
     rng = np.random.default_rng(seed)
     n = x.shape[0]
@@ -85,8 +94,17 @@ def train(net: "bse.Fno", x, t, epochs: int, batch: int, lr: float, lr_end: floa
         losses = []
         for j in range(n // batch):
             idx = torch.from_numpy(perm[j * batch:(j + 1) * batch]).cuda()
-            xb = x.index_select(0, idx).contiguous()
-            tb = t.index_select(0, idx).contiguous()
+            xb = x.index_select(0, idx)
+            tb = t.index_select(0, idx)
+            if augment:
+                perm_ax, flips = _cube_symmetry(rng)
+                xb = xb.permute(0, 1, *(2 + a for a in perm_ax))
+                tb = tb.permute(0, *(1 + a for a in perm_ax))
+                if flips:
+                    xb = xb.flip([2 + a for a in flips])
+                    tb = tb.flip([1 + a for a in flips])
+            xb = xb.contiguous()
+            tb = tb.contiguous()
             a = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * k / max(steps, 1)))
             losses.append(net.train_step(batch, xb.data_ptr(), tb.data_ptr(), a))
             k += 1

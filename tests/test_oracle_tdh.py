@@ -201,3 +201,23 @@ def test_unperturbed_kick_has_no_density():
     q = grid.poisson(phi[0] * phi[3])[None]
     wp = tdh.w_pol(grid, v, phi[:4], eta, q, dt=0.05, n_steps=0, gamma=1.0, clean_every=10)
     assert np.abs(wp).max() == 0.0
+
+
+@pytest.mark.parametrize("perm,flips", [((1, 2, 0), (0,)), ((0, 2, 1), (1, 2)), ((2, 1, 0), ())])
+def test_response_commutes_with_cube_symmetries(sys4, perm, flips):
+    """An axis permutation or reversal of the periodic cubic grid maps the
+    system (V_ext, orbitals, source) onto one with the mapped response:
+    W^pol of the mapped system equals the mapped W^pol (the surrogate's
+    training data are augmented by exactly these maps)."""
+    grid, v, phi, eps = sys4
+    n_occ = 4
+    q = grid.poisson(phi[1] * phi[2])
+
+    def g(f):                                   # the map on the last three axes
+        lead = f.ndim - 3
+        f = np.transpose(f, tuple(range(lead)) + tuple(lead + a for a in perm))
+        return np.flip(f, axis=tuple(lead + a for a in flips)) if flips else f
+
+    wp, _, _ = _run(grid, v, phi, n_occ, q, 0.05, 2.0, clean_every=10)
+    wp_g, _, _ = _run(grid, g(v).copy(), g(phi).copy(), n_occ, g(q).copy(), 0.05, 2.0, clean_every=10)
+    assert _rel(wp_g, g(wp)) < 1e-12
