@@ -97,12 +97,18 @@ def train(net: "bse.Fno", x, t, epochs: int, batch: int, lr: float, lr_end: floa
             xb = x.index_select(0, idx)
             tb = t.index_select(0, idx)
             if augment:
+                # samples hold their grid flattened (z fastest): view it as n^3
                 perm_ax, flips = _cube_symmetry(rng)
-                xb = xb.permute(0, 1, *(2 + a for a in perm_ax))
-                tb = tb.permute(0, *(1 + a for a in perm_ax))
+                xs, ts = xb.shape, tb.shape
+                ng = xs[-1]
+                m = int(round(ng ** (1.0 / 3.0)))
+                xb = xb.reshape(xs[0], xs[1], m, m, m).permute(0, 1, *(2 + a for a in perm_ax))
+                tb = tb.reshape(ts[0], m, m, m).permute(0, *(1 + a for a in perm_ax))
                 if flips:
                     xb = xb.flip([2 + a for a in flips])
                     tb = tb.flip([1 + a for a in flips])
+                xb = xb.reshape(xs)
+                tb = tb.reshape(ts)
             xb = xb.contiguous()
             tb = tb.contiguous()
             a = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * k / max(steps, 1)))
