@@ -254,9 +254,10 @@ def bench_uneven(args):
 
 
 def bench_surrogate(args):
-    """The learned screening surrogate: trained on 4096 pair densities of 20
-    mid-size molecules (seeds 100-119), evaluated on 512 held-out pairs of 3
-    others (seeds 200-202) against the propagation that generated them."""
+    """The learned screening surrogate: trained on --n-train pair densities of
+    --n-mol-train mid-size molecules (seeds 100, 101, ...; default 4096 of
+    20), evaluated on 512 held-out pairs of 3 others (seeds 200-202) against
+    the propagation that generated them."""
     import torch
     from paper_2205_06690_amd import bse, surrogate
 
@@ -264,7 +265,7 @@ def bench_surrogate(args):
         print(msg, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    tr_specs = surrogate.surrogate_specs(range(100, 120), n_steps=args.sur_steps)
+    tr_specs = surrogate.surrogate_specs(range(100, 100 + args.n_mol_train), n_steps=args.sur_steps)
     te_specs = surrogate.surrogate_specs(range(200, 203), n_steps=args.sur_steps)
     x_tr, t_tr, s_tr = surrogate.generate(tr_specs, limit=args.n_train, log=log)
     x_te, t_te, s_te = surrogate.generate(te_specs, limit=args.n_test, log=log)
@@ -304,7 +305,8 @@ def bench_surrogate(args):
     t_prop = (time.perf_counter() - t4) / len(pairs)
     out = {
         "metric": "surrogate W-action: held-out relative error on W and W^pol, time per pair",
-        "config": {"workload": f"64^3 Gaussian-well molecules (60 wells, N_occ=120), train seeds 100-119 "
+        "config": {"workload": f"64^3 Gaussian-well molecules (60 wells, N_occ=120), train seeds "
+                               f"100-{99 + args.n_mol_train} "
                                f"({x_tr.shape[0]} pairs), held out seeds 200-202 ({x_te.shape[0]} pairs), "
                                f"targets from {args.sur_steps}-step propagation (L=10, dt=0.05); network: "
                                f"4 Fourier layers, width 32, modes kx,ky in [-{args.modes},{args.modes}), "
@@ -340,6 +342,8 @@ def main():
                     help="oracle steps of the CPU sample (0: 200 at 64^3, 40 at 112^3)")
     ap.add_argument("--n-systems", type=int, default=32)
     ap.add_argument("--n-train", type=int, default=4096)
+    ap.add_argument("--n-mol-train", type=int, default=20,
+                    help="training molecules of the surrogate (seeds 100 ...)")
     ap.add_argument("--n-test", type=int, default=512)
     ap.add_argument("--sur-steps", type=int, default=200)
     ap.add_argument("--sur-batch", type=int, default=8)
