@@ -113,3 +113,33 @@ def test_augmented_training_runs_and_learns():
                            augment=True)
     say("augmented training losses", hist[0], hist[-1])
     assert np.all(np.isfinite(hist)) and hist[-1] < 0.5 * hist[0]
+
+
+def test_adam_updates_match_oracle():
+    """Three training steps of the GPU network against the oracle's Adam on
+    the same gradients: each step's gradient is read with loss_grad at the
+    current weights, the oracle advances FP64 copies of the master weights
+    and moments with it, and the GPU's train_step (same batch, so the same
+    gradient) must move the master weights the same way.  Steps 2 and 3
+    exercise both bias corrections and tell beta1 from beta2."""
+    import torch
+    from paper_2205_06690_amd import bse
+    n, B, lr = 16, 2, 1e-2
+    rng = np.random.default_rng(11)
+    net = bse.Fno(n, cin=3, width=8, modes=4, layers=2, max_batch=B, bf16_weights=False, seed=3)
+    x = torch.from_numpy(rng.standard_normal((B, 3, n, n, n)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((B, n, n, n)).astype(np.float32)).cuda()
+    p_orc = {"w": net.get_params().astype(np.float64)}
+    st = {}
+    for k in range(3):
+        p_before = net.get_params().astype(np.float64)
+        _, g = net.loss_grad(B, x.data_ptr(), t.data_ptr())
+        net.train_step(B, x.data_ptr(), t.data_ptr(), lr)
+        p_after = net.get_params().astype(np.float64)
+        ofno.adam_step(p_orc, {"w": g.astype(np.float64)}, st, lr=lr)
+        d_gpu = p_after - p_before
+        d_orc = p_orc["w"] - p_before
+        e = np.linalg.norm(d_gpu - d_orc) / np.linalg.norm(d_orc)
+        say(f"adam step {k + 1}: rel|d update| {e:.2e}, |update| {np.linalg.norm(d_orc):.3e}")
+        assert e < 1e-3, (k, e)
+        p_orc["w"] = p_after.copy()        # the next step starts from the GPU's weights

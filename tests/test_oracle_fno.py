@@ -79,6 +79,32 @@ def test_first_adam_step_moves_by_lr_sign():
     assert np.allclose(p["c"], [1.01 + 0.99j])
 
 
+def test_adam_three_step_trajectory_by_hand():
+    """Three Adam steps (beta1 = 0.9, beta2 = 0.999, eps = 0, lr = 0.1) of one
+    parameter p = 1 with gradients 1, -2, 1/2, worked by hand in fractions:
+      t = 1: m = 1/10, v = 1/1000, m^ = 1, v^ = 1, p = 0.9
+      t = 2: m = -11/100, v = 4999/10^6, m^ = -11/19, v^ = 4999/1999,
+             p = 0.9 + 0.1 (11/19) / sqrt(4999/1999)
+      t = 3: m = -49/1000, v = 5244001/10^9, m^ = -49/271,
+             v^ = 749143/428143, p = p_2 + 0.1 (49/271) / sqrt(749143/428143)
+    The first step moves every parameter by lr sign(g) whatever the betas;
+    the second and third tell beta1 from beta2 and check both bias
+    corrections.  A complex parameter updates its real and imaginary parts
+    as two independent real parameters."""
+    p2 = 0.9 + 0.1 * (11 / 19) / math.sqrt(4999 / 1999)
+    p3 = p2 + 0.1 * (49 / 271) / math.sqrt(749143 / 428143)
+    traj = []
+    p = {"a": np.array([1.0]), "c": np.array([1.0 - 1.0j])}
+    st = {}
+    for g in (1.0, -2.0, 0.5):
+        fno.adam_step(p, {"a": np.array([g]), "c": np.array([g - 1j * g])}, st, lr=0.1, eps=0.0)
+        traj.append((p["a"][0], p["c"][0]))
+    for (a, c), ref in zip(traj, (0.9, p2, p3)):
+        assert abs(a - ref) < 1e-14
+        assert abs(c.real - ref) < 1e-14 and abs(c.imag + ref) < 1e-14
+    assert abs(p3 - 0.9502794190086671) < 1e-15
+
+
 def test_gelu_values_and_derivative():
     z = np.array([-3.0, -0.5, 0.0, 0.7, 2.5])
     assert np.allclose(fno.gelu(z), z * 0.5 * (1 + erf(z / math.sqrt(2))))

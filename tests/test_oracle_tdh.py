@@ -1,11 +1,15 @@
 """Pins of the oracle's TD-Hartree action of W (Eqs. 10-15) against closed
-forms (sum over states, Casida-type linear response), exact identities
-(Hadamard signs, linearity, symmetry), the finite-alpha scheme and the
-stochastic 1/sqrt(L) law."""
+forms (sum over states, Casida-type linear response, the damped time
+integrals of Eq. 13 in closed form), exact identities (Hadamard signs,
+linearity, symmetry), the finite-alpha scheme and the stochastic 1/sqrt(L)
+law.  The closed forms integrate the Gaussian damping exactly in continuous
+time; none of them takes the oracle's quadrature weights."""
 import math
 
 import numpy as np
 import pytest
+from scipy.integrate import quad
+from scipy.special import dawsn, erf, wofz
 
 from oracle.grid import Grid
 from oracle import tdh
@@ -19,24 +23,50 @@ def tiny_system(n=8, h=0.7, wells=3, seed=5, n_occ=4):
     return Grid(v.shape, h), v, phi.reshape((-1,) + v.shape), eps
 
 
-def chi0_closed_form(grid, phi, eps, n_occ, q, w, t):
+def damped_integral(T, gamma):
+    """int_0^T exp(-gamma^2 t^2 / 2) dt = sqrt(pi/2)/gamma erf(gamma T/sqrt 2)."""
+    return math.sqrt(math.pi / 2.0) / gamma * math.erf(gamma * T / math.sqrt(2.0))
+
+
+def damped_sine_integral(om, T, gamma):
+    """int_0^T exp(-a t^2) sin(om t) dt, a = gamma^2/2, in closed form.
+
+    Completing the square, -a t^2 + i om t = -a (t - i x/sqrt a)^2 - x^2 with
+    x = om/(2 sqrt a), turns the integral into the imaginary part of an error
+    function of complex argument.  Written with Dawson's function F (the
+    T -> infinity value, F(x)/sqrt a) and the Faddeeva function
+    w(z) = exp(-z^2) erfc(-i z) for the tail beyond T:
+      I = F(x)/sqrt(a) - sqrt(pi)/(2 sqrt a) Im[exp(-a T^2 + i om T) w(i z)],
+    z = sqrt(a) T - i x.  Accepts an array of om."""
+    om = np.asarray(om, dtype=np.float64)
+    a = 0.5 * gamma * gamma
+    sa = math.sqrt(a)
+    x = om / (2.0 * sa)
+    z = sa * T - 1j * x
+    tail = np.imag(np.exp(-a * T * T + 1j * om * T) * wofz(1j * z))
+    return dawsn(x) / sa - math.sqrt(math.pi) / (2.0 * sa) * tail
+
+
+def chi0_closed_form(grid, phi, eps, n_occ, q, T, gamma):
     """Independent-particle response, summed over every grid eigenstate:
     v[-4 sum_{s occ, a virt} F(e_a - e_s) <phi_s phi_a|q> phi_s phi_a],
-    F(W) = sum_n w_n sin(W t_n)."""
+    F(W) = int_0^T exp(-gamma^2 t^2/2) sin(W t) dt (continuous time)."""
     acc = np.zeros(grid.shape)
     for s in range(n_occ):
         rho = phi[s][None] * phi[n_occ:]                       # [n_virt, ...]
         qs = np.sum(rho * q[None], axis=(1, 2, 3)) * grid.dv
-        F = np.sin(np.outer(eps[n_occ:] - eps[s], t)) @ w
+        F = damped_sine_integral(eps[n_occ:] - eps[s], T, gamma)
         acc += -4.0 * np.tensordot(F * qs, rho, axes=1)
     return grid.poisson(acc)
 
 
-def rpa_closed_form(grid, phi, eps, n_occ, q, w, t):
+def rpa_closed_form(grid, phi, eps, n_occ, q, T, gamma):
     """Linear TD-Hartree response in the transition space (s occ, a virt):
     x'' = -D^1/2 M D^1/2 ... with M = D^1/2 (D + 4K) D^1/2,
     K_{sa,tb} = (phi_s phi_a | v | phi_t phi_b); x(0) = 0, x'(0) = -D q_sa;
-    density change 4 sum x_sa phi_s phi_a; W^pol = v[sum_n w_n dn(t_n)]."""
+    density change 4 sum x_sa phi_s phi_a; W^pol = v[int_0^T exp(-gamma^2
+    t^2/2) dn(t) dt] with the damped integral of each normal mode in closed
+    form."""
     nv = phi.shape[0] - n_occ
     R = (phi[:n_occ, None] * phi[None, n_occ:]).reshape(n_occ * nv, -1)
     D = (eps[None, n_occ:] - eps[:n_occ, None]).reshape(-1)
@@ -47,9 +77,72 @@ def rpa_closed_form(grid, phi, eps, n_occ, q, w, t):
     M = sD[:, None] * (np.diag(D) + 4.0 * K) * sD[None, :]
     om2, F = np.linalg.eigh(0.5 * (M + M.T))
     om = np.sqrt(om2)
-    Ft = np.sin(np.outer(om, t)) @ w
+    Ft = damped_sine_integral(om, T, gamma)
     X = -sD * (F @ ((Ft / om) * (F.T @ (sD * qv))))
     return grid.poisson((4.0 * X @ R).reshape(grid.shape))
+
+
+def test_damped_sine_closed_form_against_quadrature():
+    """The closed form used by the pins equals adaptive quadrature of the
+    integrand, and tends to Dawson's function, sqrt(2)/gamma F(om/(sqrt 2
+    gamma)), once the damping has decayed by T."""
+    for om, T, g in [(0.3, 10.0, 0.1), (2.0, 10.0, 0.1), (5.0, 30.0, 0.143), (0.05, 5.0, 0.8),
+                     (12.0, 10.0, 0.429)]:
+        ref = quad(lambda t: math.exp(-0.5 * g * g * t * t) * math.sin(om * t), 0.0, T,
+                   limit=500, epsabs=1e-13, epsrel=1e-12)[0]
+        assert abs(damped_sine_integral(om, T, g) - ref) < 1e-11 * max(1.0, abs(ref))
+    for om in (0.1, 1.0, 4.0):
+        g = 0.5
+        inf = math.sqrt(2.0) / g * dawsn(om / (math.sqrt(2.0) * g))
+        assert abs(damped_sine_integral(om, 40.0, g) - inf) < 1e-13
+    assert abs(damped_integral(10.0, 0.1) - quad(lambda t: math.exp(-0.005 * t * t), 0, 10.0)[0]) < 1e-12
+
+
+# (gamma, T): the paper's damping truncated at T = 10 (end weight
+# exp(-1/2) = 0.61), and the default damping of the workloads (1e-4 at T)
+_QUAD_CASES = [(0.1, 10.0), (math.sqrt(2 * math.log(1e4)) / 10.0, 10.0), (0.8, 3.0)]
+
+
+@pytest.mark.parametrize("gamma,T", _QUAD_CASES)
+def test_time_weights_integrate_the_gaussian_damping(gamma, T):
+    """Eq. 13's weights summed equal int_0^T exp(-gamma^2 t^2/2) dt =
+    sqrt(pi/2)/gamma erf(gamma T/sqrt 2) up to the trapezoid rule's
+    Euler-Maclaurin term dt^2/12 (f'(T) - f'(0)) (f'(0) = 0 here): a wrong
+    damping exponent misses the integral, a wrong end weight leaves an O(dt)
+    error that this leading term does not explain."""
+    fpT = -gamma * gamma * T * math.exp(-0.5 * gamma * gamma * T * T)
+    exact = damped_integral(T, gamma)
+    for n in (100, 200, 400):
+        dt = T / n
+        err = float(np.sum(tdh.time_weights(n, dt, gamma))) - exact
+        lead = dt * dt / 12.0 * fpT
+        # the next Euler-Maclaurin term is O(dt^4 gamma^4); 1e-13 covers rounding
+        assert abs(err - lead) < 5e-3 * abs(lead) + 1e-13, (n, err, lead)
+
+
+@pytest.mark.parametrize("gamma,T", _QUAD_CASES)
+def test_time_weights_integrate_damped_sines(gamma, T):
+    """sum_n w_n sin(om t_n) equals the damped sine integral of each mode in
+    closed form up to dt^2/12 (f'(T) - f'(0)), f(t) = exp(-gamma^2 t^2/2)
+    sin(om t): the quadrature the time integral of Eq. 13 applies to every
+    oscillation of the response."""
+    a = 0.5 * gamma * gamma
+    for om in (0.05, 0.7, 2.5):
+        fp0 = om
+        fpT = math.exp(-a * T * T) * (om * math.cos(om * T) - 2 * a * T * math.sin(om * T))
+        exact = float(damped_sine_integral(om, T, gamma))
+        for n in (200, 400, 800):
+            dt = T / n
+            t = np.arange(n + 1) * dt
+            err = float(tdh.time_weights(n, dt, gamma) @ np.sin(om * t)) - exact
+            lead = dt * dt / 12.0 * (fpT - fp0)
+            assert abs(err - lead) < 2e-2 * abs(lead) + 1e-13, (om, n, err, lead)
+
+
+def test_time_weights_small_case_by_hand():
+    """N = 2, dt = 0.5, gamma = 1: weights (1/2, e^{-1/8}, e^{-1/2}/2) dt."""
+    w = tdh.time_weights(2, 0.5, 1.0)
+    assert np.allclose(w, [0.25, 0.5 * math.exp(-0.125), 0.25 * math.exp(-0.5)], rtol=1e-15, atol=0)
 
 
 def _rel(a, b):
@@ -61,25 +154,28 @@ def sys4():
     return tiny_system(n_occ=4)
 
 
-def _run(grid, v, phi, n_occ, q, dt, T, **kw):
+def _run(grid, v, phi, n_occ, q, dt, T, gamma=None, **kw):
     n = int(round(T / dt))
-    gamma = math.sqrt(2 * math.log(1e4)) / T
+    gamma = math.sqrt(2 * math.log(1e4)) / T if gamma is None else gamma
     wp = tdh.w_pol(grid, v, phi[:n_occ], phi[:n_occ], q[None], dt=dt, n_steps=n,
                    gamma=gamma, **kw)[0]
-    return wp, tdh.time_weights(n, dt, gamma), np.arange(n + 1) * dt
+    return wp, T, gamma
 
 
-@pytest.mark.parametrize("clean_every", [0, 10])
-def test_chi0_matches_sum_over_states(sys4, clean_every):
+@pytest.mark.parametrize("clean_every,gamma", [(0, None), (10, None), (10, 0.1)])
+def test_chi0_matches_sum_over_states(sys4, clean_every, gamma):
     """P4: without Hartree feedback the propagated response equals the
-    sum-over-states form, with an O(dt^2) split-operator error."""
+    sum-over-states form integrated in continuous time, with an O(dt^2)
+    error from the split operator and the quadrature together.  The
+    gamma = 0.1 case (the paper's damping, truncated at T = 5 where the
+    weight is still 0.88) makes the end weights of the quadrature count."""
     grid, v, phi, eps = sys4
     q = tdh.source_potential(grid, phi[2], phi[3])
     errs = []
     for dt in (0.1, 0.05, 0.025):
-        wp, w, t = _run(grid, v, phi, 4, q, dt, 5.0, clean_every=clean_every,
+        wp, T, g = _run(grid, v, phi, 4, q, dt, 5.0, gamma=gamma, clean_every=clean_every,
                         feedback=False)
-        errs.append(_rel(wp, chi0_closed_form(grid, phi, eps, 4, q, w, t)))
+        errs.append(_rel(wp, chi0_closed_form(grid, phi, eps, 4, q, T, g)))
     assert errs[-1] < 2e-3
     assert 3.0 < errs[1] / errs[2] < 5.0          # second order in dt
 
@@ -91,12 +187,12 @@ def test_tdh_matches_casida(sys4):
     q = tdh.source_potential(grid, phi[1], phi[3])
     errs = []
     for dt in (0.1, 0.05, 0.025):
-        wp, w, t = _run(grid, v, phi, 4, q, dt, 5.0, clean_every=10)
-        errs.append(_rel(wp, rpa_closed_form(grid, phi, eps, 4, q, w, t)))
+        wp, T, g = _run(grid, v, phi, 4, q, dt, 5.0, clean_every=10)
+        errs.append(_rel(wp, rpa_closed_form(grid, phi, eps, 4, q, T, g)))
     assert errs[-1] < 2e-3
     assert 3.0 < errs[1] / errs[2] < 5.0
     # the feedback matters: the independent-particle form is far away
-    wp0, w, t = _run(grid, v, phi, 4, q, 0.025, 5.0, clean_every=10, feedback=False)
+    wp0, _, _ = _run(grid, v, phi, 4, q, 0.025, 5.0, clean_every=10, feedback=False)
     assert _rel(wp0, wp) > 20 * errs[-1]
 
 
