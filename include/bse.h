@@ -56,7 +56,8 @@ typedef enum {
   BSE_ERR_NUMERIC = -5  /* non-finite result for some pair (see pair_status) */
 } bse_status;
 
-enum { BSE_FP64 = 0, BSE_MIXED = 1 };
+enum { BSE_FP64 = 0, BSE_MIXED = 1 };     /* bse_config.precision              */
+enum { BSE_F64 = 0, BSE_F32 = 1 };        /* element type of a device W output */
 
 typedef struct {
   int32_t nx, ny, nz;   /* grid points per axis (must be equal)                    */
@@ -79,7 +80,15 @@ typedef struct {
 } bse_config;
 
 /* Create a system from V_ext[nx*ny*nz] (host, FP64).  *out receives the
- * handle.  Allocates the device tables of the grid. */
+ * handle.  Allocates the device tables of the grid.
+ * Passage: the Method section's statement of the problem (a closed-shell
+ * system of 2 n_occ electrons whose zero-order Hamiltonian H0 = -1/2 Lap +
+ * V_ext has the eigenstates phi_s, eps_s) and the propagation parameters of
+ * its stochastic W subsection (Eqs. 10-15: dt, the number of steps, the
+ * damping gamma of Eq. 13, the cleaning period M of Eq. 15, L of Eq. 14).
+ * Errors: BSE_ERR_ARG for a non-cubic or unsupported grid, a non-positive
+ * h, dt or max_batch, alpha != 0, a non-finite V_ext or a bad device
+ * ordinal (*out is then NULL); BSE_ERR_OOM / BSE_ERR_DEVICE from HIP. */
 bse_status bse_create_system(const bse_config* cfg, const double* v_ext, bse_system** out);
 
 /* Orbitals phi[n_orb][nx*ny*nz] (host, FP64, h^3-normalised) and
@@ -94,25 +103,65 @@ bse_status bse_set_orbitals(bse_system* sys, int32_t n_orb, const double* phi, c
 bse_status bse_set_signs(bse_system* sys, int32_t n_stoch, int32_t n_occ, const int8_t* xi);
 
 /* W-action on n_pairs pair densities phi_p phi_q, pq[n_pairs][2] (host).
+ * Passage: the subsection on the stochastic evaluation of the action of W
+ * (W = v + W^pol; the kick by q_pq = v[phi_p phi_q], the propagation of
+ * Eqs. 10-11, W^pol(t) of Eq. 12, its damped time integral Eq. 13, the
+ * stochastic orbitals of Eq. 14 and the cleaning of Eq. 15).
  * w_out[n_pairs][ng] (host, FP64) receives W_pq = q_pq + W^pol_pq;
  * wpol_out (nullable) receives W^pol_pq; pair_status (nullable,
- * [n_pairs]) receives 0 or BSE_ERR_NUMERIC per pair (non-finite rows are
- * NaN-filled and the call returns BSE_ERR_NUMERIC after finishing every
- * other pair). */
+ * [n_pairs]) receives 0 or BSE_ERR_NUMERIC per pair.  A pair fails when a
+ * Poisson solve of its densities meets a non-finite value, when its W is
+ * not finite, or (every pair of its batch) when the unperturbed orbitals
+ * lose their norm at a cleaning step (relative drift above 1e-3 in mixed
+ * precision, 1e-8 in FP64); its rows are NaN-filled, the densities packed
+ * with it are shielded from it, and the call returns BSE_ERR_NUMERIC after
+ * finishing every other pair.  Errors: BSE_ERR_STATE before
+ * bse_set_orbitals; BSE_ERR_ARG for null buffers or an orbital index out
+ * of range (nothing written). */
 bse_status bse_apply_W(bse_system* sys, int32_t n_pairs, const int32_t* pq, double* w_out,
                        double* wpol_out, int32_t* pair_status);
 
-/* Device variant: pq on the host, w_dev[n_pairs][ng] (device, FP64) and
- * wpol_dev (device, FP64, nullable) borrowed from the caller; stream-
- * ordered on the bse_set_stream stream; returns after enqueueing. */
-bse_status bse_apply_W_device(bse_system* sys, int32_t n_pairs, const int32_t* pq, void* w_dev,
-                              void* wpol_dev);
+/* Device variant of bse_apply_W (same passage): pq_dev[n_pairs][2]
+ * (device, int32) and w_dev[n_pairs][ng] (device, caller-owned) of element
+ * type dtype: BSE_F64 (double) or BSE_F32 (float, W rounded from the FP64
+ * sum q + W^pol).  Stream-ordered on the bse_set_stream stream: the call
+ * first reads pq_dev back (a small copy that waits for the work already on
+ * that stream) and checks every index, then enqueues the propagation and
+ * returns.  A failed pair (see bse_apply_W) is NaN-filled on the device;
+ * there is no status output.  Errors: BSE_ERR_STATE before
+ * bse_set_orbitals; BSE_ERR_ARG for null buffers, a bad dtype or an index
+ * out of range (nothing written). */
+bse_status bse_apply_W_device(bse_system* sys, int32_t n_pairs, const int32_t* pq_dev, void* w_dev,
+                              int32_t dtype);
+
+/* Failure injection for tests of the error path.  target BSE_FAULT_ORBITAL:
+ * writes value (any double, NaN included) into the device copy of orbital
+ * `index` at grid point `point`, bypassing the input checks of
+ * bse_set_orbitals (the stochastic orbitals and the precision copies made
+ * there are not changed).  target BSE_FAULT_UNPERTURBED: writes value into
+ * the real part of the t = 0 unperturbed stochastic orbital `index` (< L)
+ * at `point` (a finite value that changes its norm trips the norm check of
+ * the cleaning steps).  The next set_orbitals restores both.  Errors:
+ * BSE_ERR_STATE before bse_set_orbitals; BSE_ERR_ARG for a bad target or an
+ * index out of range. */
+enum { BSE_FAULT_ORBITAL = 0, BSE_FAULT_UNPERTURBED = 1 };
+bse_status bse_inject_fault(bse_system* sys, int32_t target, int32_t index, int64_t point, double value);
 
 /* Tamm-Dancoff matrix (Eq. 1) for the highest n_o occupied and lowest n_c
  * virtual orbitals: A[(n_o n_c)^2] (host, FP64, row-major), row index
  * (i - (n_occ - n_o)) * n_c + (a - n_occ).  Propagates the n_o(n_o+1)/2
- * valence pairs, keeps their W_ij on the device for bse_spectrum. */
+ * valence pairs, keeps their W_ij on the device for bse_spectrum.
+ * Errors: BSE_ERR_NUMERIC when some W_ij fails the checks of bse_apply_W
+ * or A has a non-finite element (no spectrum of it is then possible);
+ * BSE_ERR_ARG for a window outside the orbitals set. */
 bse_status bse_build_A(bse_system* sys, int32_t n_o, int32_t n_c, double* A);
+
+/* The W_ij that the last successful bse_build_A propagated and keeps on
+ * the device (the screened interaction of its direct term, Eq. 1):
+ * w_out[n_o(n_o+1)/2][nx*ny*nz] (host, FP64, caller-allocated), pairs
+ * (i, j), i <= j, of the valence window in row-major order of (i, j).
+ * Errors: BSE_ERR_STATE before a successful bse_build_A. */
+bse_status bse_valence_W(bse_system* sys, double* w_out);
 
 /* Lowest n_exc excitons of the last A (Lanczos in FP64 on the device):
  * omega[n_exc] (Hartree), dip2[n_exc][3] = |<X_n|f0_axis>|^2 with

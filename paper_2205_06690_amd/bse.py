@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 
 BSE_OK, BSE_ERR_ARG, BSE_ERR_STATE, BSE_ERR_OOM, BSE_ERR_DEVICE, BSE_ERR_NUMERIC = 0, -1, -2, -3, -4, -5
 BSE_FP64, BSE_MIXED = 0, 1
+BSE_F64, BSE_F32 = 0, 1
 
 # every symbol declared in include/bse.h
 EXPORTS = (
@@ -34,7 +35,7 @@ EXPORTS = (
     "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
-    "bse_boundary_potential", "bse_fit_box_correction",
+    "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
 )
 
 
@@ -74,8 +75,10 @@ def _load():
     lib.bse_set_orbitals.argtypes = [P, C.c_int32, dp, dp]
     lib.bse_set_signs.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_int8)]
     lib.bse_apply_W.argtypes = [P, C.c_int32, ip, dp, dp, ip]
-    lib.bse_apply_W_device.argtypes = [P, C.c_int32, ip, P, P]
+    lib.bse_apply_W_device.argtypes = [P, C.c_int32, P, P, C.c_int32]
+    lib.bse_inject_fault.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_double]
     lib.bse_build_A.argtypes = [P, C.c_int32, C.c_int32, dp]
+    lib.bse_valence_W.argtypes = [P, dp]
     lib.bse_spectrum.argtypes = [P, C.c_int32, dp, dp, C.c_int32, dp, C.c_double, dp]
     lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                            C.c_double, dp, dp, dp]
@@ -233,16 +236,42 @@ class System:
             out = out + (st,)
         return out if len(out) > 1 else out[0]
 
-    def apply_w_device(self, pairs, w_dev_ptr: int, wpol_dev_ptr: Optional[int] = None):
-        pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
-        _check(LIB.bse_apply_W_device(self._h, pq.shape[0], _iptr(pq), C.c_void_p(w_dev_ptr),
-                                      C.c_void_p(wpol_dev_ptr) if wpol_dev_ptr else None))
+    def apply_w_device(self, pq_dev, w_dev):
+        """bse_apply_W_device: pq_dev a contiguous int32 device tensor [n][2],
+        w_dev a contiguous float64 (BSE_F64) or float32 (BSE_F32) device
+        tensor [n][ng]; stream-ordered on the stream of set_stream."""
+        if pq_dev.dtype != torch.int32 or pq_dev.dim() != 2 or pq_dev.shape[1] != 2 or not pq_dev.is_contiguous():
+            raise ValueError("pq_dev must be a contiguous int32 tensor [n][2]")
+        n = pq_dev.shape[0]
+        if tuple(w_dev.shape) != (n, self.ng) or not w_dev.is_contiguous():
+            raise ValueError("w_dev must be a contiguous tensor [n][ng]")
+        if w_dev.dtype == torch.float64:
+            dt = BSE_F64
+        elif w_dev.dtype == torch.float32:
+            dt = BSE_F32
+        else:
+            raise ValueError("w_dev must be float64 or float32")
+        _check(LIB.bse_apply_W_device(self._h, n, C.c_void_p(pq_dev.data_ptr()), C.c_void_p(w_dev.data_ptr()),
+                                      dt))
+
+    def inject_fault(self, index: int, point: int, value: float, unperturbed: bool = False):
+        """bse_inject_fault: one value of the device copy of orbital ``index``
+        (or of the t = 0 unperturbed stochastic orbital ``index``), bypassing
+        the input checks (tests of the failure path)."""
+        _check(LIB.bse_inject_fault(self._h, 1 if unperturbed else 0, int(index), int(point), float(value)))
 
     def build_a(self, n_o: int, n_c: int) -> np.ndarray:
         A = np.empty((n_o * n_c, n_o * n_c))
         _check(LIB.bse_build_A(self._h, n_o, n_c, _dptr(A)))
         self.a_window = (n_o, n_c)
         return A
+
+    def valence_w(self) -> np.ndarray:
+        """bse_valence_W: the W_ij of the last build_a, [n_o(n_o+1)/2][ng]."""
+        n_o = getattr(self, "a_window", (0, 0))[0]
+        w = np.empty((n_o * (n_o + 1) // 2, self.ng))
+        _check(LIB.bse_valence_W(self._h, _dptr(w)))
+        return w
 
     def apply_a_mixed(self, f: np.ndarray) -> np.ndarray:
         """A f in the mixed representation; f [n_vec][n_o][ng] or [n_o][ng]."""

@@ -220,10 +220,12 @@ template <> Tables& tabs<float>(bse_system* s) { return s->tf; }
 template <> Tables& tabs<double>(bse_system* s) { return s->td; }
 
 // Coulomb potential of B real FP64 densities (rho64) into q (FP64)
-void poisson64(bse_system* s, const double* rho, int B, double* out, double* acc, double wn) {
+void poisson64(bse_system* s, const double* rho, int B, double* out, double* acc, double wn,
+               int* flags = nullptr) {
   const size_t need = sizeof(cplx<double>) * s->ng * (size_t)((B + 1) / 2);
   s->work64.alloc(need);
   PoisArgs<double> a{};
+  a.flags = flags;
   a.rho = rho;
   a.B = B;
   a.work = s->work64.as<cplx<double>>();
@@ -323,6 +325,7 @@ void poissonT(bse_system* s, int B, double* acc, double wn) {
   a.acc = acc;
   a.wn = wn;
   a.pscale = s->pscale.as<double>() + 3 * (size_t)B;
+  a.flags = s->flags.as<int>();
   auto* t = s->timer.begin("poisson");
   HIPC(launch_poisson<T>(s->n, a, s->stream));
   s->timer.end(t);
@@ -342,8 +345,13 @@ void propagate_batch(bse_system* s, int B) {
   const int N = s->cfg.n_steps;
   const int M = s->cfg.clean_every;
   hipStream_t st = s->stream;
+  // per-pair failure flags, sticky over the whole propagation: bit 0 a
+  // non-finite density met by a Poisson solve, bit 1 a norm drift of the
+  // unperturbed set at a cleaning step (every pair), and the final check
+  // of W sets bit 0 too
+  HIPC(launch_fill_zero(s->flags.p, sizeof(int) * B, st));
   HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, ng, s->rho64.as<double>(), st));
-  poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0);
+  poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0, s->flags.as<int>());
   // per-pair scales for the packed Poisson solves of the induced densities:
   // the RMS of q_b (the response is linear in it), so that a pair whose
   // source is orders of magnitude weaker than its partner's is not buried
@@ -419,6 +427,10 @@ void propagate_batch(bse_system* s, int B) {
     } else {
       poissonT<T>(s, B, nullptr, 0.0);
       clean<T>(s, B, 1, hnext);
+      // the check point of Eq. 15: the unperturbed set must keep the norms
+      // of eta_l(0) under the unitary propagation
+      HIPC(launch_norm_drift<T>(hnext, L, ng, s->dv, s->n0.as<double>(), sizeof(T) == 4 ? 1e-3 : 1e-8,
+                                s->flags.as<int>(), B, st));
       poissonT<T>(s, B, s->wpol.as<double>(), wn);
       half = true;
     }
@@ -463,14 +475,22 @@ void check_ready(bse_system* s) {
   if (!s->ready) fail(BSE_ERR_STATE, "bse_set_orbitals has not been called");
 }
 
-// Run W for n_pairs pairs into device outputs (FP64 [n_pairs][ng]).
-void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev, double* wpol_dev,
-                    int32_t* status_host) {
-  check_ready(s);
-  if (n_pairs < 0 || (n_pairs > 0 && (!pq || !w_dev))) fail(BSE_ERR_ARG, "bad pair arguments");
+void check_pairs(const bse_system* s, int n_pairs, const int32_t* pq) {
   for (int k = 0; k < n_pairs; ++k)
     if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
       fail(BSE_ERR_ARG, "pair index out of range");
+}
+
+// Run W for n_pairs pairs (host list pq, already validated) into device
+// outputs [n_pairs][ng], FP64 (w_f32 = false) or FP32.  A pair whose
+// propagation met a non-finite value or whose unperturbed set drifted is
+// NaN-filled on the device; status_host (nullable) receives the per-pair
+// status, which costs one synchronisation per batch.
+void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, void* w_dev, bool w_f32, double* wpol_dev,
+                    int32_t* status_host) {
+  check_ready(s);
+  if (n_pairs < 0 || (n_pairs > 0 && (!pq || !w_dev))) fail(BSE_ERR_ARG, "bad pair arguments");
+  check_pairs(s, n_pairs, pq);
   s->timer.st = s->stream;
   const int Bmax = std::max(1, s->cfg.max_batch);
   bool any_bad = false;
@@ -483,26 +503,33 @@ void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, double* w_dev
     else propagate_batch<float>(s, B);
     const size_t off = (size_t)k0 * s->ng;
     const size_t cnt = (size_t)B * s->ng;
-    HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), cnt, w_dev + off, s->stream));
-    if (wpol_dev)
+    // W = q + W^pol; the check reads the FP64 sum before any narrowing
+    double* wsum = w_f32 ? s->rho64.as<double>() : reinterpret_cast<double*>(w_dev) + off;
+    HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), cnt, wsum, s->stream));
+    HIPC(launch_finite_check(wsum, B, s->ng, s->flags.as<int>(), s->stream));
+    if (w_f32) {
+      float* wf = reinterpret_cast<float*>(w_dev) + off;
+      HIPC(launch_add_f32(s->q.as<double>(), s->wpol.as<double>(), cnt, wf, s->stream));
+      HIPC(launch_nan_flagged_f32(wf, B, s->ng, s->flags.as<int>(), s->stream));
+    } else {
+      HIPC(launch_nan_flagged(wsum, B, s->ng, s->flags.as<int>(), s->stream));
+    }
+    if (wpol_dev) {
       HIPC(hipMemcpyAsync(wpol_dev + off, s->wpol.p, sizeof(double) * cnt, hipMemcpyDeviceToDevice,
                           s->stream));
-    HIPC(launch_finite_check(w_dev + off, B, s->ng, s->flags.as<int>(), s->stream));
+      HIPC(launch_nan_flagged(wpol_dev + off, B, s->ng, s->flags.as<int>(), s->stream));
+    }
     if (status_host) {
       std::vector<int> fl(B);
       HIPC(hipMemcpyAsync(fl.data(), s->flags.p, sizeof(int) * B, hipMemcpyDeviceToHost, s->stream));
       HIPC(hipStreamSynchronize(s->stream));
       for (int b = 0; b < B; ++b) {
         status_host[k0 + b] = fl[b] ? BSE_ERR_NUMERIC : 0;
-        if (fl[b]) {
-          any_bad = true;
-          HIPC(launch_fill_nan(w_dev + off + (size_t)b * s->ng, s->ng, s->stream));
-          if (wpol_dev) HIPC(launch_fill_nan(wpol_dev + off + (size_t)b * s->ng, s->ng, s->stream));
-        }
+        if (fl[b]) any_bad = true;
       }
     }
   }
-  if (any_bad) fail(BSE_ERR_NUMERIC, "non-finite W for some pairs");
+  if (any_bad) fail(BSE_ERR_NUMERIC, "non-finite W (or a drifting unperturbed set) for some pairs");
 }
 
 // ---------------------------------------------------------------------------
@@ -526,7 +553,18 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
   hipStream_t st = s->stream;
   // 1. W_ij for the valence pairs (kept on the device)
   s->wij.alloc(sizeof(double) * ng * n_ij);
-  apply_w_device(s, n_ij, pij.data(), s->wij.as<double>(), nullptr, nullptr);
+  {
+    std::vector<int32_t> stw(n_ij, 0);
+    try {
+      apply_w_device(s, n_ij, pij.data(), s->wij.as<double>(), false, nullptr, stw.data());
+    } catch (const Fail& f) {
+      if (f.st != BSE_ERR_NUMERIC) throw;
+      int nb = 0;
+      for (int k = 0; k < n_ij; ++k) nb += stw[k] != 0;
+      fail(BSE_ERR_NUMERIC, "bse_build_A: W_ij failed the numerical checks for " + std::to_string(nb) + " of " +
+                                std::to_string(n_ij) + " valence pairs");
+    }
+  }
   // scratch kept by the system across calls (grow-only), so repeated
   // builds allocate nothing
   DBuf& pq = s->ba_pq;
@@ -623,6 +661,11 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
   HIPC(launch_dipoles(s->phi64.as<double>(), pq.as<int>(), n_ia, s->n, s->cfg.h, s->f0_d.as<double>(), st));
   HIPC(hipMemcpyAsync(A_host, s->A_d.p, sizeof(double) * (size_t)n_ia * n_ia, hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
+  for (size_t k = 0; k < (size_t)n_ia * n_ia; ++k)
+    if (!std::isfinite(A_host[k])) {
+      s->a_no = s->a_nc = 0;   // no spectrum of a failed A
+      fail(BSE_ERR_NUMERIC, "bse_build_A: non-finite element in A (exchange or direct term)");
+    }
   s->a_no = n_o;
   s->a_nc = n_c;
 }
@@ -1306,23 +1349,24 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
   }
   HIPC(hipSetDevice(dev));
   std::vector<hipStream_t> saved(n_sys);
+  std::vector<char> timer_was(n_sys, 0);
   for (int i = 0; i < n_sys; ++i) {
     bse_system* s = sys[i];
     if (!s->own_stream) HIPC(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
-    if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, n_pairs[i]);
-    else ensure_batch<float>(s, n_pairs[i]);
-    HIPC(hipMemcpy(s->pq_d.p, pq[i], sizeof(int) * 2 * n_pairs[i], hipMemcpyHostToDevice));
     saved[i] = s->stream;
-    s->stream = s->own_stream;
-    s->timer.on = false;
+    timer_was[i] = s->timer.on ? 1 : 0;
   }
   hipStream_t origin = nullptr;
-  std::vector<hipEvent_t> ev(n_sys + 1, nullptr);
+  std::vector<hipEvent_t> ev(n_sys + 1, nullptr), pre(n_sys, nullptr);
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto restore = [&]() {
-    for (int i = 0; i < n_sys; ++i) sys[i]->stream = saved[i];
+    for (int i = 0; i < n_sys; ++i) {
+      sys[i]->stream = saved[i];
+      sys[i]->timer.on = timer_was[i] != 0;
+    }
     for (auto e : ev) if (e) (void)hipEventDestroy(e);
+    for (auto e : pre) if (e) (void)hipEventDestroy(e);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (origin) (void)hipStreamDestroy(origin);
@@ -1330,6 +1374,23 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
   try {
     HIPC(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
     for (auto& e : ev) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : pre) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // the batch reuses each system's workspace and writes the caller's
+    // buffers: it starts after the work already queued on every system's
+    // stream (a device W-action still running, the caller's fill of w_dev)
+    for (int i = 0; i < n_sys; ++i) {
+      bse_system* s = sys[i];
+      HIPC(hipEventRecord(pre[i], saved[i]));
+      HIPC(hipStreamWaitEvent(origin, pre[i], 0));
+      HIPC(hipStreamWaitEvent(s->own_stream, pre[i], 0));
+      if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, n_pairs[i]);
+      else ensure_batch<float>(s, n_pairs[i]);
+      HIPC(hipMemcpyAsync(s->pq_d.p, pq[i], sizeof(int) * 2 * n_pairs[i], hipMemcpyHostToDevice, s->own_stream));
+      s->stream = s->own_stream;
+      s->timer.on = false;
+    }
+    // the pair lists are on the device before the captured work reads them
+    for (int i = 0; i < n_sys; ++i) HIPC(hipStreamSynchronize(sys[i]->own_stream));
     if (use_graph) HIPC(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
     HIPC(hipEventRecord(ev[n_sys], origin));
     for (int i = 0; i < n_sys; ++i) {
@@ -1338,8 +1399,10 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
       const int B = n_pairs[i];
       if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
       else propagate_batch<float>(s, B);
-      HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)B * s->ng,
-                      reinterpret_cast<double*>(w_dev[i]), s->stream));
+      double* w = reinterpret_cast<double*>(w_dev[i]);
+      HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)B * s->ng, w, s->stream));
+      HIPC(launch_finite_check(w, B, s->ng, s->flags.as<int>(), s->stream));
+      HIPC(launch_nan_flagged(w, B, s->ng, s->flags.as<int>(), s->stream));
       HIPC(hipEventRecord(ev[i], s->stream));
       HIPC(hipStreamWaitEvent(origin, ev[i], 0));
     }
@@ -1543,7 +1606,7 @@ void apply_w_surrogate(bse_system* s, bse_fno* net, int n_pairs, const int32_t* 
     if (!idx.empty()) {
       DBuf tmp;
       tmp.alloc(sizeof(double) * s->ng * idx.size());
-      apply_w_device(s, (int)idx.size(), rej.data(), tmp.as<double>(), nullptr, nullptr);
+      apply_w_device(s, (int)idx.size(), rej.data(), tmp.p, false, nullptr, nullptr);
       for (size_t j = 0; j < idx.size(); ++j)
         HIPC(hipMemcpyAsync(w_dev + (size_t)idx[j] * s->ng, tmp.as<double>() + j * s->ng,
                             sizeof(double) * s->ng, hipMemcpyDeviceToDevice, s->stream));
@@ -1688,11 +1751,42 @@ bse_status bse_set_orbitals(bse_system* s, int32_t n_orb, const double* phi, con
   API_END
 }
 
-bse_status bse_apply_W_device(bse_system* s, int32_t n_pairs, const int32_t* pq, void* w_dev,
-                              void* wpol_dev) {
+bse_status bse_apply_W_device(bse_system* s, int32_t n_pairs, const int32_t* pq_dev, void* w_dev,
+                              int32_t dtype) {
   API_BEGIN
-  apply_w_device(s, n_pairs, pq, reinterpret_cast<double*>(w_dev),
-                 reinterpret_cast<double*>(wpol_dev), nullptr);
+  check_ready(s);
+  if (n_pairs < 0 || (n_pairs > 0 && (!pq_dev || !w_dev))) fail(BSE_ERR_ARG, "bad pair arguments");
+  if (dtype != BSE_F64 && dtype != BSE_F32) fail(BSE_ERR_ARG, "dtype must be BSE_F64 or BSE_F32");
+  if (n_pairs == 0) return BSE_OK;
+  // the indices are read back (after the work already on the stream) and
+  // checked before anything is written
+  std::vector<int32_t> pq(2 * (size_t)n_pairs);
+  HIPC(hipMemcpyAsync(pq.data(), pq_dev, sizeof(int32_t) * pq.size(), hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
+  check_pairs(s, n_pairs, pq.data());
+  apply_w_device(s, n_pairs, pq.data(), w_dev, dtype == BSE_F32, nullptr, nullptr);
+  API_END
+}
+
+bse_status bse_inject_fault(bse_system* s, int32_t target, int32_t index, int64_t point, double value) {
+  API_BEGIN
+  check_ready(s);
+  if (target != BSE_FAULT_ORBITAL && target != BSE_FAULT_UNPERTURBED) fail(BSE_ERR_ARG, "bse_inject_fault: bad target");
+  const int count = target == BSE_FAULT_ORBITAL ? s->n_orb : s->L;
+  if (index < 0 || index >= count || point < 0 || (size_t)point >= s->ng)
+    fail(BSE_ERR_ARG, "bse_inject_fault: index or point out of range");
+  HIPC(hipStreamSynchronize(s->stream));
+  if (target == BSE_FAULT_ORBITAL) {
+    HIPC(hipMemcpy(s->phi64.as<double>() + (size_t)index * s->ng + point, &value, sizeof(double),
+                   hipMemcpyHostToDevice));
+  } else if (s->cfg.precision == BSE_FP64) {
+    HIPC(hipMemcpy(s->h0.as<cplx<double>>() + (size_t)index * s->ng + point, &value, sizeof(double),
+                   hipMemcpyHostToDevice));
+  } else {
+    const float v = (float)value;
+    HIPC(hipMemcpy(s->h0.as<cplx<float>>() + (size_t)index * s->ng + point, &v, sizeof(float),
+                   hipMemcpyHostToDevice));
+  }
   API_END
 }
 
@@ -1709,7 +1803,7 @@ bse_status bse_apply_W(bse_system* s, int32_t n_pairs, const int32_t* pq, double
   std::vector<int32_t> st(n_pairs, 0);
   bse_status rc = BSE_OK;
   try {
-    apply_w_device(s, n_pairs, pq, w.as<double>(), wpol_out ? wp.as<double>() : nullptr, st.data());
+    apply_w_device(s, n_pairs, pq, w.p, false, wpol_out ? wp.as<double>() : nullptr, st.data());
   } catch (const Fail& f) {
     if (f.st != BSE_ERR_NUMERIC) throw;
     rc = BSE_ERR_NUMERIC;
@@ -1774,6 +1868,16 @@ int32_t bse_kernel_times(bse_system* s, int32_t cap, const char** names, double*
 bse_status bse_build_A(bse_system* s, int32_t n_o, int32_t n_c, double* A) {
   API_BEGIN
   build_a(s, n_o, n_c, A);
+  API_END
+}
+
+bse_status bse_valence_W(bse_system* s, double* w_out) {
+  API_BEGIN
+  if (!s || !w_out) fail(BSE_ERR_ARG, "bse_valence_W: null argument");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_valence_W: call bse_build_A first");
+  const size_t n_ij = (size_t)s->a_no * (s->a_no + 1) / 2;
+  HIPC(hipMemcpyAsync(w_out, s->wij.p, sizeof(double) * n_ij * s->ng, hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
   API_END
 }
 

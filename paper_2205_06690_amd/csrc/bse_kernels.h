@@ -4,6 +4,7 @@
 #include <cstddef>
 
 namespace bse {
+// flags[b] |= 1 for every row b of w[B][ng] with a non-finite value
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st);
 hipError_t launch_fill_nan(double* w, size_t n, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);

@@ -15,7 +15,7 @@
 namespace bse {
 
 
-// flags[b] = 1 if row b of w has a non-finite value
+// flags[b] |= 1 if row b of w has a non-finite value (flags are not cleared)
 __global__ void k_finite_check(const double* __restrict__ w, size_t ng, int* __restrict__ flags) {
   const int b = blockIdx.y;
   __shared__ int bad;
@@ -823,8 +823,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 hipError_t launch_finite_check(const double* w, int B, size_t ng, int* flags, hipStream_t st) {
-  hipError_t e = launch_fill_zero(flags, sizeof(int) * B, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finite_check, dim3(64, B), dim3(256), 0, st, w, ng, flags);
   return hipGetLastError();
 }

@@ -47,6 +47,8 @@ template <typename T> struct PoisArgs {
   const double* pscale;  // nullable [B]: density b enters its packed transform as rho_b / pscale[b]
                          // and its potential leaves times pscale[b], so that two packed
                          // densities of very different size keep their own relative rounding
+  int* flags;          // nullable [B]: a non-finite input value of density b is replaced by 0
+                       // (so that it cannot reach the density packed with it) and flags[b] |= 1
 };
 
 template <typename T> struct CleanArgs {
@@ -107,5 +109,14 @@ hipError_t launch_pair_density(const double* phi, const int* pq, int B, size_t n
                                hipStream_t st);
 hipError_t launch_add(const double* a, const double* b, size_t n, double* out, hipStream_t st);
 hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double* out, hipStream_t st);
+// unitarity of the unperturbed propagation: if |dv sum |H_l|^2 / n0[l] - 1| > tol for any l, or the
+// sum is not finite, flags[b] |= 2 for every b < B
+template <typename T>
+hipError_t launch_norm_drift(const cplx<T>* H, int L, size_t ng, double dv, const double* n0, double tol,
+                             int* flags, int B, hipStream_t st);
+// rows b < B of w[B][ng] with flags[b] != 0 become NaN
+hipError_t launch_nan_flagged(double* w, int B, size_t ng, const int* flags, hipStream_t st);
+hipError_t launch_nan_flagged_f32(float* w, int B, size_t ng, const int* flags, hipStream_t st);
+hipError_t launch_add_f32(const double* a, const double* b, size_t n, float* out, hipStream_t st);
 
 }  // namespace bse

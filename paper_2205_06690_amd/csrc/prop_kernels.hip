@@ -415,6 +415,22 @@ __global__ void __launch_bounds__(PY_NT) k_prop_y(PropYZArgs<T> a) {
 // Coulomb potential v[rho] of real densities, two packed per complex field
 // (the 4 pi/k^2 kernel is real and even, so re and im stay independent).
 // ---------------------------------------------------------------------------
+// One packed input value: with checking on, a non-finite density value is
+// replaced by 0 and remembered, so that a failed pair cannot reach the pair
+// that shares its transform.
+template <typename C, typename T>
+__device__ __forceinline__ C load_pair(T v0, T v1, bool check, int& bad0, int& bad1) {
+  if (check) {
+    if (!isfinite(v0)) { v0 = (T)0; bad0 = 1; }
+    if (!isfinite(v1)) { v1 = (T)0; bad1 = 1; }
+  }
+  return cmk<C>(v0, v1);
+}
+__device__ __forceinline__ void flag_bad(int* flags, int b0, int b1, int bad0, int bad1) {
+  if (bad0) atomicOr(&flags[b0], 1);
+  if (bad1) atomicOr(&flags[b1], 1);
+}
+
 template <int N, typename T, int NT>
 __global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
   using C = cplx<T>;
@@ -431,7 +447,10 @@ __global__ void __launch_bounds__(NT) k_poisson_yz_fwd(PoisArgs<T> a) {
   stage_tables<N, C>(tw, a.tw, nullptr, tid, NT);
   const T i0 = a.pscale ? (T)(1.0 / a.pscale[b0]) : (T)1;
   const T i1 = (a.pscale && r1) ? (T)(1.0 / a.pscale[b1]) : (T)1;
-  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = cmk<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0);
+  int bad0 = 0, bad1 = 0;
+  for (int e = tid; e < P; e += NT)
+    s[plane_idx<N>(e)] = load_pair<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0, a.flags != nullptr, bad0, bad1);
+  flag_bad(a.flags, b0, b1, bad0, bad1);
   __syncthreads();
   NoMul nm;
   stageA_fwd<N>(s, N, S, 1, tw, tid, NT, true);
@@ -560,8 +579,10 @@ __global__ void __launch_bounds__(256) k_poisson_z(PoisArgs<T> a, int dir) {
     const T* r1 = has1 ? a.rho + (size_t)b1 * ng + base : nullptr;
     const T i0 = a.pscale ? (T)(1.0 / a.pscale[b0]) : (T)1;
     const T i1 = (a.pscale && has1) ? (T)(1.0 / a.pscale[b1]) : (T)1;
+    int bad0 = 0, bad1 = 0;
     for (int e = tid; e < E; e += 256)
-      s[(e / N) * S + e % N] = cmk<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0);
+      s[(e / N) * S + e % N] = load_pair<C>(r0[e] * i0, r1 ? r1[e] * i1 : (T)0, a.flags != nullptr, bad0, bad1);
+    flag_bad(a.flags, b0, b1, bad0, bad1);
     __syncthreads();
     stageA_fwd<N>(s, TL, S, 1, tw, tid, 256, true);
     __syncthreads();
@@ -928,6 +949,44 @@ __global__ void k_norms(const double* __restrict__ eta0, size_t ng, double dv, d
   if (threadIdx.x == 0) out[l] = red[0] * dv;
 }
 
+__global__ void k_add_f32(const double* __restrict__ a, const double* __restrict__ b, size_t n,
+                          float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(a[i] + b[i]);
+}
+
+// The unperturbed set evolves by a unitary map, so its norms stay those of
+// eta_l(0): one block per orbital sums |H_l|^2 in FP64 and, on a drift
+// beyond tol (or a non-finite sum), marks every pair of the batch.
+template <typename T>
+__global__ void k_norm_drift(const cplx<T>* __restrict__ H, size_t ng, double dv, const double* __restrict__ n0,
+                             double tol, int* __restrict__ flags, int B) {
+  const int l = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0;
+  for (size_t i = threadIdx.x; i < ng; i += 256) {
+    const cplx<T> v = H[(size_t)l * ng + i];
+    acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0] * dv / n0[l] - 1.0;
+  if (!(fabs(r) <= tol))
+    for (int b = threadIdx.x; b < B; b += 256) atomicOr(&flags[b], 2);
+}
+
+template <typename W>
+__global__ void k_nan_flagged(W* __restrict__ w, size_t ng, const int* __restrict__ flags) {
+  const int b = blockIdx.y;
+  if (!flags[b]) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (size_t)gridDim.x * blockDim.x)
+    w[(size_t)b * ng + i] = (W)__builtin_nan("");
+}
+
 template <typename T>
 __global__ void k_to_real(const double* __restrict__ in, size_t n, T* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1245,8 +1304,29 @@ hipError_t launch_add(const double* a, const double* b, size_t n, double* out, h
   hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n, out);
   return hipGetLastError();
 }
+hipError_t launch_add_f32(const double* a, const double* b, size_t n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
 hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_norms, dim3(L), dim3(256), 0, st, eta0, ng, dv, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_norm_drift(const cplx<T>* H, int L, size_t ng, double dv, const double* n0, double tol,
+                             int* flags, int B, hipStream_t st) {
+  if (L <= 0 || B <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_norm_drift<T>), dim3(L), dim3(256), 0, st, H, ng, dv, n0, tol, flags, B);
+  return hipGetLastError();
+}
+hipError_t launch_nan_flagged(double* w, int B, size_t ng, const int* flags, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_nan_flagged<double>), dim3(64, B), dim3(256), 0, st, w, ng, flags);
+  return hipGetLastError();
+}
+hipError_t launch_nan_flagged_f32(float* w, int B, size_t ng, const int* flags, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_nan_flagged<float>), dim3(64, B), dim3(256), 0, st, w, ng, flags);
   return hipGetLastError();
 }
 template <typename T>
@@ -1270,7 +1350,9 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
   template hipError_t launch_kick<T>(const double*, const double*, int, int, size_t, cplx<T>*, \
                                      hipStream_t);                                             \
   template hipError_t launch_clean<T>(const CleanArgs<T>&, hipStream_t);                       \
-  template hipError_t launch_to_real<T>(const double*, size_t, T*, hipStream_t);
+  template hipError_t launch_to_real<T>(const double*, size_t, T*, hipStream_t);                \
+  template hipError_t launch_norm_drift<T>(const cplx<T>*, int, size_t, double, const double*,  \
+                                           double, int*, int, hipStream_t);
 
 BSE_INST(float)
 BSE_INST(double)

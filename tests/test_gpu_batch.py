@@ -71,3 +71,74 @@ def test_batch_argument_errors():
     with pytest.raises(bse.BseError) as e:
         bse.apply_w_batch([s], [pair_lists[0]], [0])      # 3 pairs > max_batch 2
     assert e.value.code == bse.BSE_ERR_ARG
+
+
+@pytest.mark.timeout(900)
+def test_uneven_members_of_each_grid_against_oracle():
+    """The first member of each grid size in the 32-molecule uneven batch
+    (32^3, 48^3 and 64^3 molecules at h = 0.4, L = 10, 400 steps, FP32
+    propagation) with its whole pair list, the three propagated together in
+    one captured graph as the batch benchmark runs them; two pairs of each
+    (the first, and one packed in the middle of the batch) against the FP64
+    oracle on the whole grid, with the pointwise error beside the L2 one."""
+    import torch
+    from paper_2205_06690_amd import bse
+    specs = inputs.uneven_batch_specs(32)
+    chosen, seen = [], set()
+    for sp, npair in specs:
+        if sp.n not in seen:
+            seen.add(sp.n)
+            chosen.append((sp, npair))
+    assert sorted(seen) == [32, 48, 64]
+    systems, plists, outs, sysds = [], [], [], []
+    for sp, npair in chosen:
+        say(f"uneven member {sp.n}^3: N_occ {sp.n_occ}, {npair} pairs, inputs")
+        sd = inputs.make_system(sp)
+        p = inputs.ia_pairs(sp)[:npair]
+        systems.append(gpu_system(sp, sd, bse.BSE_MIXED, max_batch=len(p)))
+        plists.append(p)
+        sysds.append(sd)
+        outs.append(torch.zeros((len(p), sp.ng), dtype=torch.float64, device="cuda"))
+    say("uneven members: one graph launch")
+    bse.apply_w_batch(systems, plists, [o.data_ptr() for o in outs], use_graph=True)
+    torch.cuda.synchronize()
+    for (sp, _), sd, p, o in zip(chosen, sysds, plists, outs):
+        ks = [0, len(p) // 2 + 1]
+        say(f"uneven member {sp.n}^3: oracle on pairs {p[ks].tolist()}")
+        w_o, _ = oracle_w(sp, sd, p[ks])
+        w_o = w_o.reshape(len(ks), -1)
+        got = o.cpu().numpy()[ks]
+        e = rel(got, w_o)
+        e_pt = np.abs(got - w_o).max(axis=1) / np.abs(w_o).max(axis=1)
+        say(f"uneven member {sp.n}^3: rel L2 {e.max():.2e}, max|dW|/max|W| {e_pt.max():.2e}")
+        assert e.max() < 1e-3 and e_pt.max() < 1e-3
+    for s in systems:
+        s.close()
+
+
+def test_batch_waits_for_work_on_the_systems_streams():
+    """A system whose stream (set by bse_set_stream, non-blocking) still has
+    the caller's fill of the output queued: the batch starts after it, so
+    the batch's results are not overwritten by the fill."""
+    import torch
+    from paper_2205_06690_amd import bse
+    specs, pair_lists = _systems()
+    sysds = [inputs.make_system(sp) for sp in specs]
+    systems = [gpu_system(sp, sd, bse.BSE_MIXED, max_batch=len(p))
+               for sp, sd, p in zip(specs, sysds, pair_lists)]
+    ref = [s.apply_w(p) for s, p in zip(systems, pair_lists)]
+    st = torch.cuda.Stream()
+    for s in systems:
+        s.set_stream(st.cuda_stream)
+    outs = [torch.empty((len(p), sp.ng), dtype=torch.float64, device="cuda")
+            for sp, p in zip(specs, pair_lists)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        # a long fill on the systems' stream just before the batch
+        for _ in range(50):
+            for o in outs:
+                o.fill_(-1.0)
+    bse.apply_w_batch(systems, pair_lists, [o.data_ptr() for o in outs], use_graph=True)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
