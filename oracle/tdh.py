@@ -81,7 +81,7 @@ def _project_out(grid: Grid, phi_occ2: np.ndarray, d: np.ndarray) -> np.ndarray:
 def w_pol(grid: Grid, v_ext: np.ndarray, phi_occ: np.ndarray, eta0: np.ndarray,
           q: np.ndarray, *, dt: float, n_steps: int, gamma: float, clean_every: int,
           mode: str = "linear", alpha: float = 1e-6, feedback: bool = True,
-          renorm: bool = True, clean_t0: bool = True) -> np.ndarray:
+          renorm: bool = True, clean_t0: bool = True, progress=None) -> np.ndarray:
     """W^pol for each source potential in q [B, nx, ny, nz].
 
     eta0: the propagated occupied set [L, nx, ny, nz] (stochastic orbitals,
@@ -89,6 +89,8 @@ def w_pol(grid: Grid, v_ext: np.ndarray, phi_occ: np.ndarray, eta0: np.ndarray,
     feedback=False drops u from the propagation (independent-particle
     response) while still accumulating v[density change]; it is a test mode.
     clean_every = 0 disables cleaning (including t = 0 unless clean_t0).
+    progress (nullable) is called with the step count after every step (a
+    report hook for long runs; it sees no data).
     """
     if mode not in ("linear", "finite"):
         raise ValueError(mode)
@@ -132,6 +134,8 @@ def w_pol(grid: Grid, v_ext: np.ndarray, phi_occ: np.ndarray, eta0: np.ndarray,
                 d = clean(d, eta_u)
                 u = grid.poisson(dens(d, eta_u))
             wpol += w[n + 1] * u
+            if progress is not None:
+                progress(n + 1)
         return wpol
 
     # finite alpha: the paper's scheme literally, divided by alpha
