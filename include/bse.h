@@ -220,6 +220,28 @@ bse_status bse_chebyshev_spectrum(bse_system* sys, int32_t n_mom, double e_min, 
                                   int32_t n_w, const double* w_grid, double sigma_broad,
                                   double* sigma, double* residues, double* bounds);
 
+/* Allocation-free variant of bse_chebyshev_spectrum, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels, arithmetic and results (bit for bit), with every device buffer
+ * of the call (the three recursion vectors per polarisation, the per-block
+ * partial residues, the residues, the node sums, the frequency grid, the
+ * Gershgorin bounds) carved from one fixed 64 MiB device array that the
+ * library holds per GPU until the process ends; the start vectors and the
+ * Gershgorin interval are formed on the device, so the call makes no host
+ * staging copies either.  It calls no hipMalloc, hipFree or allocating
+ * routine.  Limit: about 0.75 n_mom (n_o n_c) + 9 n_o n_c + 9 n_mom +
+ * 2 n_w doubles must fit in the 64 MiB (e.g. n_mom up to ~13000 at
+ * n_o n_c = 800); larger requests return BSE_ERR_ARG before any work.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (two host threads, or two streams) race and must be serialised by
+ * the caller.  Nothing in the array needs to start at zero (every element
+ * a call reads, it has written first).  Errors: as bse_chebyshev_spectrum,
+ * plus BSE_ERR_ARG for a request above the limit. */
+bse_status bse_chebyshev_spectrum_noalloc(bse_system* sys, int32_t n_mom, double e_min, double e_max,
+                                          int32_t n_w, const double* w_grid, double sigma_broad,
+                                          double* sigma, double* residues, double* bounds);
+
 /* Frequency-resolved exciton states (Eq. 8) and their densities, on the A
  * of the last bse_build_A, in FP64 on the device.  For each frequency
  * w_list[q] (Hartree) and each of the three dipole start vectors f0 (as in

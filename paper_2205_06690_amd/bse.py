@@ -36,6 +36,7 @@ EXPORTS = (
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
     "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
+    "bse_chebyshev_spectrum_noalloc",
 )
 
 
@@ -82,6 +83,8 @@ def _load():
     lib.bse_spectrum.argtypes = [P, C.c_int32, dp, dp, C.c_int32, dp, C.c_double, dp]
     lib.bse_chebyshev_spectrum.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
                                            C.c_double, dp, dp, dp]
+    lib.bse_chebyshev_spectrum_noalloc.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp,
+                                                   C.c_double, dp, dp, dp]
     lib.bse_apply_A_mixed.argtypes = [P, C.c_int32, dp, dp]
     lib.bse_exciton_states.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, dp, C.c_double,
                                        dp, dp, dp]
@@ -341,6 +344,23 @@ class System:
         sg = np.empty(wg.size)
         _check(LIB.bse_chebyshev_spectrum(self._h, n_mom, lo, hi, wg.size, _dptr(wg), sigma, _dptr(sg),
                                           _dptr(res), _dptr(bo)))
+        return sg, res, bo
+
+    def chebyshev_spectrum_noalloc(self, n_mom: int, w_grid=None, sigma: float = 0.08 / 27.211386245988,
+                                   bounds=None):
+        """bse_chebyshev_spectrum_noalloc: as chebyshev_spectrum, with the
+        library's fixed device scratch instead of allocations."""
+        res = np.empty((3, n_mom))
+        bo = np.empty(2)
+        lo, hi = (0.0, 0.0) if bounds is None else (float(bounds[0]), float(bounds[1]))
+        if w_grid is None:
+            _check(LIB.bse_chebyshev_spectrum_noalloc(self._h, n_mom, lo, hi, 0, None, sigma, None,
+                                                      _dptr(res), _dptr(bo)))
+            return None, res, bo
+        wg = np.ascontiguousarray(w_grid, dtype=np.float64)
+        sg = np.empty(wg.size)
+        _check(LIB.bse_chebyshev_spectrum_noalloc(self._h, n_mom, lo, hi, wg.size, _dptr(wg), sigma,
+                                                  _dptr(sg), _dptr(res), _dptr(bo)))
         return sg, res, bo
 
     def spectrum(self, n_exc: int, w_grid=None, sigma: float = 0.08 / 27.211386245988):

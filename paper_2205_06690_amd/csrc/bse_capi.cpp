@@ -10,6 +10,7 @@
 #include <sstream>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,40 @@ struct Timer {
 struct Tables {
   DBuf tw, kph, pf, ph, k2;
 };
+
+}  // namespace
+
+// Device scratch of the allocation-free entry point: one array per GPU,
+// loaded with the library's code object and held until the process ends.
+// Host code must not pass `scratch` itself to a kernel (on the host the name
+// stands for a host-side shadow); every use goes through the device address
+// that hipGetSymbolAddress gives for the current device (scratch_dev).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// Called with `dev` current (at system creation): records the device
+// address of this device's copy of `scratch`, once per device.
+void init_scratch(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) fail(BSE_ERR_ARG, "device ordinal above the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    fail(BSE_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_dev[dev] = reinterpret_cast<double*>(p);
+}
+
+double* scratch_dev(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (dev >= 0 && dev < MAX_DEVICES) ? g_scratch_dev[dev] : nullptr;
+}
 
 }  // namespace
 
@@ -1112,6 +1147,73 @@ void chebyshev_spectrum(bse_system* s, int n_mom, double e_min, double e_max, in
   }
 }
 
+// chebyshev_spectrum without allocation: the same launches and arithmetic,
+// with every device buffer carved from this device's `scratch` array and no
+// host staging (start vectors and the Gershgorin interval on the device).
+// Sizes in doubles, each part rounded up to 256 bytes.
+size_t cheb_noalloc_doubles(int n, int n_mom, int n_w) {
+  auto r = [](size_t x) { return (x + 31) / 32 * 32; };
+  const size_t K = (size_t)n_mom / 2, nblk = (size_t)cheb_blocks(n), M = 2 * (size_t)n_mom;
+  return r(9 * (size_t)n) + r(6 * K * nblk) + r(3 * (size_t)n_mom) + r(3 * M) + 2 * r((size_t)n_w) +
+         r(2 * (size_t)n) + r(2);
+}
+
+void chebyshev_spectrum_noalloc(bse_system* s, int n_mom, double e_min, double e_max, int n_w,
+                                const double* w_grid, double sig, double* sigma, double* residues,
+                                double* bounds) {
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (s->a_no == 0) fail(BSE_ERR_STATE, "bse_chebyshev_spectrum_noalloc: call bse_build_A first");
+  const int n = s->a_no * s->a_nc;
+  if (n_mom < 2 || n_mom % 2 != 0 || n_w < 0 || (n_w > 0 && (!w_grid || !sigma || !(sig > 0))) ||
+      (n_w == 0 && !residues))
+    fail(BSE_ERR_ARG, "bse_chebyshev_spectrum_noalloc: bad arguments");
+  if (cheb_noalloc_doubles(n, n_mom, n_w) * sizeof(double) > NOALLOC_SCRATCH_BYTES)
+    fail(BSE_ERR_ARG, "bse_chebyshev_spectrum_noalloc: n_mom, n_w and the size of A need more than the "
+                      "64 MiB of scratch (about 0.75 n_mom n_ia + 9 n_ia + 9 n_mom + 2 n_w doubles)");
+  double* base = scratch_dev(s->cfg.device);
+  if (!base) fail(BSE_ERR_STATE, "bse_chebyshev_spectrum_noalloc: no scratch on this device");
+  HIPC(hipSetDevice(s->cfg.device));
+  hipStream_t st = s->stream;
+  auto r = [](size_t x) { return (x + 31) / 32 * 32; };
+  const int K = n_mom / 2, nblk = cheb_blocks(n), M = 2 * n_mom;
+  double* fv = base;
+  double* part = fv + r(9 * (size_t)n);
+  double* mu = part + r(6 * (size_t)K * nblk);
+  double* D = mu + r(3 * (size_t)n_mom);
+  double* wd = D + r(3 * (size_t)M);
+  double* sd = wd + r((size_t)n_w);
+  double* lohi = sd + r((size_t)n_w);
+  double* mm = lohi + r(2 * (size_t)n);
+  const double* A = s->A_d.as<double>();
+  if (!(e_min < e_max)) {
+    double h[2];
+    HIPC(launch_gershgorin(A, n, lohi, st));
+    HIPC(launch_interval(lohi, n, mm, st));
+    HIPC(hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    e_min = h[0];
+    e_max = h[1];
+    if (!(e_min < e_max)) fail(BSE_ERR_ARG, "bse_chebyshev_spectrum_noalloc: degenerate interval; pass bounds");
+  }
+  const double b = 0.5 * (e_max + e_min), a = 0.5 * (e_max - e_min) * 1.01;
+  if (n_w > 0) HIPC(hipMemcpyAsync(wd, w_grid, sizeof(double) * n_w, hipMemcpyHostToDevice, st));
+  HIPC(launch_cheb_start(s->f0_d.as<double>(), n, fv, st));
+  for (int k = 0; k < K; ++k) {
+    const double* fc = fv + (size_t)(k % 3) * 3 * n;
+    const double* fp = fv + (size_t)((k + 2) % 3) * 3 * n;
+    double* fn = fv + (size_t)((k + 1) % 3) * 3 * n;
+    HIPC(launch_cheb_step(A, n, fc, fp, fn, a, b, k == 0 ? 1 : 0, part + (size_t)k * nblk * 6, st));
+  }
+  HIPC(launch_cheb_spectrum(part, K, nblk, mu, M, D, a, b, wd, n_w, sig, sd, st));
+  if (n_w > 0) HIPC(hipMemcpyAsync(sigma, sd, sizeof(double) * n_w, hipMemcpyDeviceToHost, st));
+  if (residues) HIPC(hipMemcpyAsync(residues, mu, sizeof(double) * 3 * (size_t)n_mom, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (bounds) {
+    bounds[0] = e_min;
+    bounds[1] = e_max;
+  }
+}
+
 // Frequency-resolved exciton states (Eq. 8) on the device copy of A: the full
 // three-term recursion from the dipole start vectors with
 // F_q += g_m(omega_q) f^m at every step, then (optionally) the exciton
@@ -1665,6 +1767,7 @@ bse_status bse_create_system(const bse_config* cfg, const double* v_ext, bse_sys
   HIPC(hipGetDeviceCount(&ndev));
   if (c.device < 0 || c.device >= ndev) fail(BSE_ERR_ARG, "bad device ordinal");
   HIPC(hipSetDevice(c.device));
+  init_scratch(c.device);
   auto* s = new bse_system();
   try {
     s->cfg = c;
@@ -1921,6 +2024,14 @@ bse_status bse_chebyshev_spectrum(bse_system* s, int32_t n_mom, double e_min, do
                                   double* sigma, double* residues, double* bounds) {
   API_BEGIN
   chebyshev_spectrum(s, n_mom, e_min, e_max, n_w, w_grid, sigma_broad, sigma, residues, bounds);
+  API_END
+}
+
+bse_status bse_chebyshev_spectrum_noalloc(bse_system* s, int32_t n_mom, double e_min, double e_max,
+                                          int32_t n_w, const double* w_grid, double sigma_broad,
+                                          double* sigma, double* residues, double* bounds) {
+  API_BEGIN
+  chebyshev_spectrum_noalloc(s, n_mom, e_min, e_max, n_w, w_grid, sigma_broad, sigma, residues, bounds);
   API_END
 }
 

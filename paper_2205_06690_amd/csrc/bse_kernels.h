@@ -62,6 +62,10 @@ hipError_t launch_mixed_dipole(const double* phv, int n_o, int n, double h, int 
 // residues mu[3][2K], node weights D[3][M] and sigma[n_w] from the partials
 hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t st);
 int cheb_blocks(int n);
+// the dipoles f0[n][3] as the three start vectors out[3][n]
+hipError_t launch_cheb_start(const double* f0, int n, double* out, hipStream_t st);
+// mm[0] = min of lohi[0..n), mm[1] = max of lohi[n..2n) (the Gershgorin interval)
+hipError_t launch_interval(const double* lohi, int n, double* mm, hipStream_t st);
 hipError_t launch_cheb_step(const double* A, int n, const double* fc, const double* fp, double* fn,
                             double a, double b, int first, double* part, hipStream_t st);
 hipError_t launch_cheb_spectrum(const double* part, int K, int nblk, double* mu, int M, double* D,

@@ -332,6 +332,39 @@ __global__ void __launch_bounds__(256) k_gershgorin(const double* __restrict__ A
   }
 }
 
+// [n][3] electron-hole dipoles -> the three start vectors [3][n]
+__global__ void k_cheb_start(const double* __restrict__ f0, int n, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) out[(size_t)p * n + i] = f0[(size_t)i * 3 + p];
+}
+
+// mm[0] = min_i lohi[i], mm[1] = max_i lohi[n + i]: one block
+__global__ void __launch_bounds__(256) k_interval(const double* __restrict__ lohi, int n,
+                                                  double* __restrict__ mm) {
+  __shared__ double lo_s[256], hi_s[256];
+  double lo = lohi[0], hi = lohi[n];
+  for (int i = threadIdx.x; i < n; i += 256) {
+    lo = fmin(lo, lohi[i]);
+    hi = fmax(hi, lohi[n + i]);
+  }
+  lo_s[threadIdx.x] = lo;
+  hi_s[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      lo_s[threadIdx.x] = fmin(lo_s[threadIdx.x], lo_s[threadIdx.x + w]);
+      hi_s[threadIdx.x] = fmax(hi_s[threadIdx.x], hi_s[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mm[0] = lo_s[0];
+    mm[1] = hi_s[0];
+  }
+}
+
 // one recursion step, one wave per row; part[blk][0..2] = <fc|fc>,
 // part[blk][3..5] = <fn|fc> over the block's rows
 __global__ void __launch_bounds__(256) k_cheb_step(const double* __restrict__ A, int n,
@@ -946,6 +979,16 @@ hipError_t launch_gershgorin(const double* A, int n, double* lohi, hipStream_t s
   return hipGetLastError();
 }
 int cheb_blocks(int n) { return (n + 3) / 4; }
+hipError_t launch_cheb_start(const double* f0, int n, double* out, hipStream_t st) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cheb_start, dim3((n + 255) / 256), dim3(256), 0, st, f0, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_interval(const double* lohi, int n, double* mm, hipStream_t st) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_interval, dim3(1), dim3(256), 0, st, lohi, n, mm);
+  return hipGetLastError();
+}
 hipError_t launch_cheb_step(const double* A, int n, const double* fc, const double* fp, double* fn,
                             double a, double b, int first, double* part, hipStream_t st) {
   hipLaunchKernelGGL(k_cheb_step, dim3(cheb_blocks(n)), dim3(256), 0, st, A, n, fc, fp, fn, 1.0 / a, b,
