@@ -22,7 +22,9 @@ LIB = os.path.join(OUT_DIR, "libbse.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["prop_kernels.hip", "clean_mfma.hip", "contract_mfma.hip", "bse_kernels.hip",
-           "fno_kernels.hip", "bse_capi.cpp", "fno.cpp"]
+           "fno_kernels.hip", "bse_capi.cpp", "fno.cpp", "host_math.cpp"]
+# plain C++ host code (no device code): compiled as C++, not as HIP
+HOST_ONLY = ("host_math.cpp",)
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,9 +39,12 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS]
-    if src.endswith(".cpp"):
-        cmd += ["-x", "hip"]
+    if src in HOST_ONLY:
+        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-x", "c++"]
+    else:
+        cmd = [HIPCC, *FLAGS]
+        if src.endswith(".cpp"):
+            cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

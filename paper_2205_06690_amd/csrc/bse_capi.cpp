@@ -19,8 +19,11 @@
 #include "prop_kernels.h"
 #include "clean_mfma.h"
 #include "contract_mfma.h"
+#include "host_math.h"
 
 using namespace bse;
+using bse_host::splitmix64_draw;
+using bse_host::tridiag_lowest;
 
 namespace {
 
@@ -63,13 +66,6 @@ struct DBuf {
   ~DBuf() { release(); }
   template <typename X> X* as() const { return reinterpret_cast<X*>(p); }
 };
-
-uint64_t splitmix64_draw(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
 
 struct Timer {
   struct Rec {
@@ -187,6 +183,7 @@ struct bse_system {
   int cap_b = 0;
   DBuf d, u, dens, wpol, q, rho64, work, work64, part, part32, gpart, coef, coefE, E, pq_d, flags;
   DBuf pscale;    // [B][3] row sums of q, then [B] per-pair scales of the packed Poisson solves
+  DBuf normpart;  // partial norms of the unperturbed set (check at the cleaning steps)
   int nchunk = 0;
   // A / spectrum state
   int a_no = 0, a_nc = 0;
@@ -302,6 +299,7 @@ void ensure_batch(bse_system* s, int B) {
   s->flags.alloc(sizeof(int) * B);
   s->work64.alloc(sizeof(cplx<double>) * ng * (size_t)((B + 1) / 2));
   s->pscale.alloc(sizeof(double) * 4 * (size_t)B);
+  s->normpart.alloc(sizeof(double) * norm_drift_part_elems(L));
   s->cap_b = B;
 }
 
@@ -465,7 +463,7 @@ void propagate_batch(bse_system* s, int B) {
       // the check point of Eq. 15: the unperturbed set must keep the norms
       // of eta_l(0) under the unitary propagation
       HIPC(launch_norm_drift<T>(hnext, L, ng, s->dv, s->n0.as<double>(), sizeof(T) == 4 ? 1e-3 : 1e-8,
-                                s->flags.as<int>(), B, st));
+                                s->flags.as<int>(), B, s->normpart.as<double>(), st));
       poissonT<T>(s, B, s->wpol.as<double>(), wn);
       half = true;
     }
@@ -496,13 +494,8 @@ void prepare_unperturbed(bse_system* s) {
 }
 
 void compute_weights(bse_system* s) {
-  const int N = s->cfg.n_steps;
-  s->wts.assign(N + 1, 0.0);
-  for (int n = 0; n <= N; ++n) {
-    const double t = n * s->cfg.dt;
-    const double c = (n == 0 || n == N) ? 0.5 : 1.0;
-    s->wts[n] = c * std::exp(-0.5 * s->cfg.gamma * s->cfg.gamma * t * t) * s->cfg.dt;
-  }
+  s->wts.assign(s->cfg.n_steps + 1, 0.0);
+  bse_host::time_weights(s->cfg.n_steps, s->cfg.dt, s->cfg.gamma, s->wts.data());
 }
 
 void check_ready(bse_system* s) {
@@ -703,119 +696,6 @@ void build_a(bse_system* s, int n_o, int n_c, double* A_host) {
     }
   s->a_no = n_o;
   s->a_nc = n_c;
-}
-
-// ---------------------------------------------------------------------------
-// symmetric tridiagonal eigenpairs (host, FP64): Sturm-count bisection for
-// the k lowest eigenvalues, inverse iteration for their vectors
-// ---------------------------------------------------------------------------
-// Sturm counts (eigenvalues of T below x) at nx points at once: the points'
-// recurrences are independent, so interleaving them keeps the divider busy.
-void sturm_counts(const std::vector<double>& a, const std::vector<double>& b2, int m, const double* x, int nx,
-                  int* cnt) {
-  constexpr int XB = 32;
-  for (int x0 = 0; x0 < nx; x0 += XB) {
-    const int nb = std::min(XB, nx - x0);
-    double q[XB];
-    int c[XB];
-    for (int j = 0; j < nb; ++j) {
-      q[j] = a[0] - x[x0 + j];
-      c[j] = q[j] < 0;
-    }
-    for (int i = 1; i < m; ++i)
-      for (int j = 0; j < nb; ++j) {
-        const double qq = (std::fabs(q[j]) < 1e-300) ? 1e-300 : q[j];
-        q[j] = a[i] - x[x0 + j] - b2[i - 1] / qq;
-        c[j] += q[j] < 0;
-      }
-    for (int j = 0; j < nb; ++j) cnt[x0 + j] = c[j];
-  }
-}
-
-// The k lowest eigenpairs of the symmetric tridiagonal T (diagonal a,
-// off-diagonal b): bisection on Sturm counts until each bracket is below
-// tol relative to its magnitude, then inverse iteration.
-void tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, int m, int k,
-                    std::vector<double>& theta, std::vector<std::vector<double>>& vecs, double tol = 1e-15) {
-  double lo = a[0], hi = a[0];
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
-    lo = std::min(lo, a[i] - r);
-    hi = std::max(hi, a[i] + r);
-  }
-  const double span = std::max(hi - lo, 1e-30);
-  std::vector<double> b2(std::max(m - 1, 1));
-  for (int i = 0; i + 1 < m; ++i) b2[i] = b[i] * b[i];
-  // bisection of the k lowest eigenvalues, all brackets advanced together
-  std::vector<double> l(k, lo - 1e-12 * span), h(k, hi + 1e-12 * span), mid(k);
-  std::vector<int> act(k), cnt(k);
-  for (int it = 0; it < 200; ++it) {
-    int na = 0;
-    for (int j = 0; j < k; ++j)
-      if (h[j] - l[j] > tol * std::max(1.0, std::fabs(l[j]) + std::fabs(h[j]))) {
-        act[na] = j;
-        mid[na++] = 0.5 * (l[j] + h[j]);
-      }
-    if (!na) break;
-    sturm_counts(a, b2, m, mid.data(), na, cnt.data());
-    for (int q = 0; q < na; ++q) {
-      const int j = act[q];
-      if (cnt[q] > j) h[j] = mid[q]; else l[j] = mid[q];
-    }
-  }
-  theta.assign(k, 0.0);
-  for (int j = 0; j < k; ++j) theta[j] = 0.5 * (l[j] + h[j]);
-  vecs.assign(k, std::vector<double>(m, 0.0));
-  uint64_t seed = 977;
-  for (int j = 0; j < k; ++j) {
-    std::vector<double>& y = vecs[j];
-    for (int i = 0; i < m; ++i) {
-      seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
-      y[i] = ((seed >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
-    }
-    const double sh = theta[j] + 1e-13 * span;
-    for (int it = 0; it < 4; ++it) {
-      // solve (T - sh I) z = y by Gaussian elimination with partial pivoting
-      std::vector<double> dl(m), d(m), du(m), du2(m, 0.0), z = y;
-      for (int i = 0; i < m; ++i) { d[i] = a[i] - sh; if (i < m - 1) { du[i] = b[i]; dl[i] = b[i]; } }
-      std::vector<int> piv(m, 0);
-      for (int i = 0; i < m - 1; ++i) {
-        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
-          if (d[i] == 0.0) d[i] = 1e-300;
-          const double f = dl[i] / d[i];
-          dl[i] = f;
-          d[i + 1] -= f * du[i];
-        } else {
-          const double f = d[i] / dl[i];
-          d[i] = dl[i];
-          dl[i] = f;
-          const double t = du[i];
-          du[i] = d[i + 1];
-          d[i + 1] = t - f * d[i + 1];
-          if (i < m - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
-          piv[i] = 1;
-        }
-      }
-      if (d[m - 1] == 0.0) d[m - 1] = 1e-300;
-      for (int i = 0; i < m - 1; ++i) {
-        if (piv[i]) { const double t = z[i]; z[i] = z[i + 1]; z[i + 1] = t - dl[i] * z[i + 1]; }
-        else z[i + 1] -= dl[i] * z[i];
-      }
-      z[m - 1] /= d[m - 1];
-      if (m > 1) z[m - 2] = (z[m - 2] - du[m - 2] * z[m - 1]) / d[m - 2];
-      for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / d[i];
-      // orthogonalise against earlier vectors (degenerate clusters)
-      for (int q = 0; q < j; ++q) {
-        double c = 0;
-        for (int i = 0; i < m; ++i) c += vecs[q][i] * z[i];
-        for (int i = 0; i < m; ++i) z[i] -= c * vecs[q][i];
-      }
-      double nrm = 0;
-      for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
-      nrm = std::sqrt(nrm);
-      for (int i = 0; i < m; ++i) y[i] = z[i] / nrm;
-    }
-  }
 }
 
 // Lanczos with full re-orthogonalisation on the device copy of A.  The
@@ -1553,42 +1433,6 @@ double boundary_potential(bse_system* s) {
   return v;
 }
 
-// Least squares of omega[b][m] = c_m + e v[b]: with box means removed,
-// e = sum_bm (omega_bm - mean_b omega_bm)(v_b - mean v) / (n_exc sum_b (v_b - mean v)^2).
-void fit_box_correction(int n_box, int n_exc, const double* omega, const double* v, double* eps_inv,
-                        double* c, double* w_k0) {
-  if (n_box < 2 || n_exc < 1 || !omega || !v || !eps_inv || !w_k0)
-    fail(BSE_ERR_ARG, "bse_fit_box_correction: need n_box >= 2, n_exc >= 1 and non-null buffers");
-  for (int i = 0; i < n_box * n_exc; ++i)
-    if (!std::isfinite(omega[i])) fail(BSE_ERR_ARG, "bse_fit_box_correction: non-finite omega");
-  double vm = 0, vmax = 0;
-  for (int b = 0; b < n_box; ++b) {
-    if (!std::isfinite(v[b])) fail(BSE_ERR_ARG, "bse_fit_box_correction: non-finite v_bndry");
-    vm += v[b];
-    vmax = std::max(vmax, std::fabs(v[b]));
-  }
-  vm /= n_box;
-  double spread = 0, den = 0;
-  for (int b = 0; b < n_box; ++b) {
-    spread = std::max(spread, std::fabs(v[b] - vm));
-    den += (v[b] - vm) * (v[b] - vm);
-  }
-  if (!(spread > 1e-12 * std::max(vmax, 1e-300)))
-    fail(BSE_ERR_ARG, "bse_fit_box_correction: the boxes' boundary potentials coincide");
-  std::vector<double> om_mean(n_exc, 0.0);
-  for (int b = 0; b < n_box; ++b)
-    for (int m = 0; m < n_exc; ++m) om_mean[m] += omega[(size_t)b * n_exc + m];
-  for (int m = 0; m < n_exc; ++m) om_mean[m] /= n_box;
-  double num = 0;
-  for (int b = 0; b < n_box; ++b)
-    for (int m = 0; m < n_exc; ++m) num += (omega[(size_t)b * n_exc + m] - om_mean[m]) * (v[b] - vm);
-  const double e = num / (n_exc * den);
-  *eps_inv = e;
-  if (c)
-    for (int m = 0; m < n_exc; ++m) c[m] = om_mean[m] - e * vm;
-  for (int b = 0; b < n_box; ++b) w_k0[b] = e * v[b];
-}
-
 // ---------------------------------------------------------------------------
 // surrogate samples and surrogate W-action
 // ---------------------------------------------------------------------------
@@ -1742,10 +1586,7 @@ bse_status bse_generate_signs(uint64_t seed, int32_t n_stoch, int32_t n_occ, int
     g_err = "bse_generate_signs: bad arguments";
     return BSE_ERR_ARG;
   }
-  for (int l = 0; l < n_stoch; ++l)
-    for (int s = 0; s < n_occ; ++s)
-      xi[(size_t)l * n_occ + s] =
-          (splitmix64_draw(seed, (uint64_t)l * n_occ + s) >> 63) == 0 ? (int8_t)1 : (int8_t)-1;
+  bse_host::stochastic_signs(seed, n_stoch, n_occ, xi);
   return BSE_OK;
 }
 
@@ -2001,7 +1842,8 @@ bse_status bse_boundary_potential(bse_system* s, double* v_bndry) {
 bse_status bse_fit_box_correction(int32_t n_box, int32_t n_exc, const double* omega, const double* v_bndry,
                                   double* eps_inv, double* c, double* w_k0) {
   API_BEGIN
-  fit_box_correction(n_box, n_exc, omega, v_bndry, eps_inv, c, w_k0);
+  if (const char* msg = bse_host::fit_box_correction(n_box, n_exc, omega, v_bndry, eps_inv, c, w_k0))
+    fail(BSE_ERR_ARG, msg);
   API_END
 }
 

@@ -110,10 +110,11 @@ hipError_t launch_pair_density(const double* phi, const int* pq, int B, size_t n
 hipError_t launch_add(const double* a, const double* b, size_t n, double* out, hipStream_t st);
 hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double* out, hipStream_t st);
 // unitarity of the unperturbed propagation: if |dv sum |H_l|^2 / n0[l] - 1| > tol for any l, or the
-// sum is not finite, flags[b] |= 2 for every b < B
+// sum is not finite, flags[b] |= 2 for every b < B; part holds norm_drift_part_elems(L) doubles
+size_t norm_drift_part_elems(int L);
 template <typename T>
 hipError_t launch_norm_drift(const cplx<T>* H, int L, size_t ng, double dv, const double* n0, double tol,
-                             int* flags, int B, hipStream_t st);
+                             int* flags, int B, double* part, hipStream_t st);
 // rows b < B of w[B][ng] with flags[b] != 0 become NaN
 hipError_t launch_nan_flagged(double* w, int B, size_t ng, const int* flags, hipStream_t st);
 hipError_t launch_nan_flagged_f32(float* w, int B, size_t ng, const int* flags, hipStream_t st);

@@ -956,15 +956,20 @@ __global__ void k_add_f32(const double* __restrict__ a, const double* __restrict
 }
 
 // The unperturbed set evolves by a unitary map, so its norms stay those of
-// eta_l(0): one block per orbital sums |H_l|^2 in FP64 and, on a drift
-// beyond tol (or a non-finite sum), marks every pair of the batch.
+// eta_l(0).  First pass: NORM_NB blocks per orbital sum |H_l|^2 over their
+// share of the points (FP64) into part[l][blk]; second pass (one block):
+// the partials of each orbital added in block order and, on a drift beyond
+// tol (or a non-finite sum), every pair of the batch marked.
+constexpr int NORM_NB = 64;
 template <typename T>
-__global__ void k_norm_drift(const cplx<T>* __restrict__ H, size_t ng, double dv, const double* __restrict__ n0,
-                             double tol, int* __restrict__ flags, int B) {
-  const int l = blockIdx.x;
+__global__ void __launch_bounds__(256) k_norm_part(const cplx<T>* __restrict__ H, size_t ng,
+                                                   double* __restrict__ part) {
+  const int l = blockIdx.y, blk = blockIdx.x;
+  const size_t per = (ng + NORM_NB - 1) / NORM_NB;
+  const size_t i0 = (size_t)blk * per, i1 = i0 + per < ng ? i0 + per : ng;
   __shared__ double red[256];
   double acc = 0;
-  for (size_t i = threadIdx.x; i < ng; i += 256) {
+  for (size_t i = i0 + threadIdx.x; i < i1; i += 256) {
     const cplx<T> v = H[(size_t)l * ng + i];
     acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
   }
@@ -974,8 +979,23 @@ __global__ void k_norm_drift(const cplx<T>* __restrict__ H, size_t ng, double dv
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const double r = red[0] * dv / n0[l] - 1.0;
-  if (!(fabs(r) <= tol))
+  if (threadIdx.x == 0) part[(size_t)l * NORM_NB + blk] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_norm_check(const double* __restrict__ part, int L, double dv,
+                                                    const double* __restrict__ n0, double tol,
+                                                    int* __restrict__ flags, int B) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int l = threadIdx.x; l < L; l += 256) {
+    double acc = 0;
+    for (int k = 0; k < NORM_NB; ++k) acc += part[(size_t)l * NORM_NB + k];
+    const double r = acc * dv / n0[l] - 1.0;
+    if (!(fabs(r) <= tol)) atomicOr(&bad, 1);
+  }
+  __syncthreads();
+  if (bad)
     for (int b = threadIdx.x; b < B; b += 256) atomicOr(&flags[b], 2);
 }
 
@@ -1312,11 +1332,13 @@ hipError_t launch_norms(const double* eta0, int L, size_t ng, double dv, double*
   hipLaunchKernelGGL(k_norms, dim3(L), dim3(256), 0, st, eta0, ng, dv, out);
   return hipGetLastError();
 }
+size_t norm_drift_part_elems(int L) { return (size_t)L * NORM_NB; }
 template <typename T>
 hipError_t launch_norm_drift(const cplx<T>* H, int L, size_t ng, double dv, const double* n0, double tol,
-                             int* flags, int B, hipStream_t st) {
+                             int* flags, int B, double* part, hipStream_t st) {
   if (L <= 0 || B <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_norm_drift<T>), dim3(L), dim3(256), 0, st, H, ng, dv, n0, tol, flags, B);
+  hipLaunchKernelGGL((k_norm_part<T>), dim3(NORM_NB, L), dim3(256), 0, st, H, ng, part);
+  hipLaunchKernelGGL(k_norm_check, dim3(1), dim3(256), 0, st, part, L, dv, n0, tol, flags, B);
   return hipGetLastError();
 }
 hipError_t launch_nan_flagged(double* w, int B, size_t ng, const int* flags, hipStream_t st) {
@@ -1352,7 +1374,7 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
   template hipError_t launch_clean<T>(const CleanArgs<T>&, hipStream_t);                       \
   template hipError_t launch_to_real<T>(const double*, size_t, T*, hipStream_t);                \
   template hipError_t launch_norm_drift<T>(const cplx<T>*, int, size_t, double, const double*,  \
-                                           double, int*, int, hipStream_t);
+                                           double, int*, int, double*, hipStream_t);
 
 BSE_INST(float)
 BSE_INST(double)

@@ -61,6 +61,10 @@ def test_one_by_one_a_and_two_moments(small):
     say(f"1x1 A: gpu {A[0, 0]:.12f} oracle {A_o[0, 0]:.12f}")
     assert A.shape == (1, 1) and abs(A[0, 0] - A_o[0, 0]) < 1e-10
     f0 = obse.dipoles(grid, phi[i:i + 1], phi[a_:a_ + 1])
+    # the Lanczos path on one row: the exciton is A itself, its strength |f0|^2
+    om1, d21 = s.spectrum(1)
+    assert abs(om1[0] - A[0, 0]) < 1e-12 * max(1.0, abs(A[0, 0]))
+    assert np.allclose(d21[0], f0[0] ** 2, rtol=1e-10, atol=1e-14)
     lo, hi = A_o[0, 0] - 0.1, A_o[0, 0] + 0.1
     a, b = obse.chebyshev_scale(lo, hi)
     _, R, _ = s.chebyshev_spectrum(2, None, bounds=(lo, hi))
