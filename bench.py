@@ -223,16 +223,24 @@ def bench_uneven(args):
     total = sum(len(p) for p in pairs)
     res = {}
 
+    # the captured plan: one graph of the whole batch, made once here
+    t_pl = time.perf_counter()
+    plan = bse.BatchPlan(systems, pairs, [o.data_ptr() for o in outs])
+    t_plan_make = time.perf_counter() - t_pl
+    log(f"[bench] plan captured and instantiated in {t_plan_make:.1f}s")
+
     def run(mode):
         if mode == "sequential":
             for S, p, o in zip(systems, pairs_dev, outs):
                 S.apply_w_device(p, o)
+        elif mode == "plan":
+            plan.run()
         else:
             bse.apply_w_batch(systems, pairs, [o.data_ptr() for o in outs],
                               use_graph=(mode == "graph"))
         torch.cuda.synchronize()
 
-    for mode in ("sequential", "streams", "graph"):
+    for mode in ("sequential", "streams", "graph", "plan"):
         for _ in range(args.warmup):
             run(mode)
         t0 = time.perf_counter()
@@ -245,17 +253,20 @@ def bench_uneven(args):
         hist[f"{sp.n}^3"] = hist.get(f"{sp.n}^3", 0) + 1
     out = {
         "metric": "W-action pair solves/s at <=1e-3 rel err vs FP64 oracle",
-        "value": round(total / res["graph"], 3), "unit": "pair solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["graph"] * 1e3, 3),
+        "value": round(total / res["plan"], 3), "unit": "pair solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["plan"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"uneven batch: {len(specs)} Gaussian-well molecules, grids {hist}, "
                                "h=0.4, N_occ 10-100, 16-200 pair densities each, L=10, dt=0.05, "
-                               "400 steps, M=10, one HIP-graph launch",
+                               "400 steps, M=10, replay of one captured HIP graph",
                    "pairs_per_step": total, "autotuned": bool(args.autotune)},
         "sequential_solves_per_s": round(total / res["sequential"], 3),
         "streams_solves_per_s": round(total / res["streams"], 3),
+        "graph_captured_per_call_solves_per_s": round(total / res["graph"], 3),
+        "plan_capture_s": round(t_plan_make, 2),
     }
+    plan.close()
     print(json.dumps(out), flush=True)
 
 
@@ -293,23 +304,35 @@ def bench_surrogate(args):
     rel_wpol = (torch.linalg.norm(yy - tt, dim=1) / torch.linalg.norm(tt, dim=1)).cpu().numpy()
     rel_w = (torch.linalg.norm(yy - tt, dim=1) / torch.linalg.norm(x0 + tt, dim=1)).cpu().numpy()
     rel_w_q = (torch.linalg.norm(tt, dim=1) / torch.linalg.norm(x0 + tt, dim=1)).cpu().numpy()
-    # acceptance and cost on the first held-out molecule: surrogate vs propagation
+    # the judged surrogate W-action on the first held-out molecule: at the
+    # 1e-3 bar, and at a loose bar that the network's measured errors pass,
+    # with the true error of every kept prediction against the propagation
     from paper_2205_06690_amd import inputs
     spec = te_specs[0]
     S = surrogate.open_system(spec, inputs.make_system(spec))
     pairs = surrogate.system_pairs(spec)
     w = torch.empty((len(pairs), spec.ng), dtype=torch.float64, device="cuda")
-    bse.apply_w_surrogate(S, net, pairs[:8], w.data_ptr(), fallback=False)      # warm-up
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    acc = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), fallback=False)
-    torch.cuda.synchronize()
-    t_sur = (time.perf_counter() - t3) / len(pairs)
     pairs_dev = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.int32)).cuda()
+    w_ref = torch.empty_like(w)
     t4 = time.perf_counter()
-    S.apply_w_device(pairs_dev, w)
+    S.apply_w_device(pairs_dev, w_ref)
     torch.cuda.synchronize()
     t_prop = (time.perf_counter() - t4) / len(pairs)
+    judged = {}
+    for tol in (1e-3, args.loose_tol):
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        acc, jerr = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), tol=tol, n_judge=args.n_judge)
+        torch.cuda.synchronize()
+        t_sur = (time.perf_counter() - t3) / len(pairs)
+        e_rows = (torch.linalg.norm(w - w_ref, dim=1) / torch.linalg.norm(w_ref, dim=1)).cpu().numpy()
+        kept = e_rows[acc.astype(bool)]
+        judged[f"tol_{tol:g}"] = {
+            "accepted_fraction": float(np.mean(acc)), "judged_pairs": args.n_judge,
+            "judged_err": [float(x) for x in jerr],
+            "kept_predictions_err": ({"median": float(np.median(kept)), "max": float(kept.max())}
+                                     if kept.size else None),
+            "ms_per_pair": round(t_sur * 1e3, 3)}
     out = {
         "metric": "surrogate W-action: held-out relative error on W and W^pol, time per pair",
         "config": {"workload": f"64^3 Gaussian-well molecules (60 wells, N_occ=120), train seeds "
@@ -326,8 +349,7 @@ def bench_surrogate(args):
                               "frac_below_1e-3": float(np.mean(rel_w < 1e-3)),
                               "frac_below_1e-2": float(np.mean(rel_w < 1e-2))},
         "no_network_rel_err_W": {"median": float(np.median(rel_w_q)), "note": "W approximated by q"},
-        "accepted_fraction": float(np.mean(acc)),
-        "ms_per_pair_surrogate": round(t_sur * 1e3, 3),
+        "judged_surrogate": judged,
         "ms_per_pair_propagation": round(t_prop * 1e3, 3),
         "ms_per_pair_inference_only": round(t_inf * 1e3, 3),
         "seconds": {"data": round(t_gen, 1), "train": round(t_train, 1)},
@@ -346,6 +368,9 @@ def main():
                          "build_a: bse_build_A + bse_spectrum per step")
     ap.add_argument("--slice", type=int, default=21, help="pairs per slice step")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--n-steps", type=int, default=0,
+                    help="propagation steps per solve (0: the workload's); only for counter runs, "
+                         "whose per-launch figures do not depend on it")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-par-steps", type=int, default=-1,
@@ -366,6 +391,9 @@ def main():
     ap.add_argument("--no-augment", action="store_true",
                     help="train the surrogate without the cube-symmetry augmentation")
     ap.add_argument("--train-seconds", type=float, default=420.0)
+    ap.add_argument("--n-judge", type=int, default=8, help="pairs the propagation judges per surrogate call")
+    ap.add_argument("--loose-tol", type=float, default=0.5,
+                    help="a second acceptance bar, loose enough for the network's errors")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev, mixed, box)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -402,6 +430,10 @@ def main():
         print(f"unknown --config {args.config}", file=sys.stderr)
         sys.exit(2)
     spec = inputs.CONFIGS[args.config]
+    if args.n_steps > 0:
+        import dataclasses
+        spec = dataclasses.replace(spec, n_steps=args.n_steps, gamma=spec.gamma_eff)
+        args.no_parity = True
     step_kind = args.step or ("slice" if args.config == "paper112" else "build_a")
     if args.cpu_steps <= 0:
         args.cpu_steps = 10 if spec.n >= 112 else min(200, spec.n_steps)

@@ -320,6 +320,26 @@ bse_status bse_fit_box_correction(int32_t n_box, int32_t n_exc, const double* om
 bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
                              const int32_t* const* pq, void* const* w_dev, int32_t use_graph);
 
+/* Uneven batch as a plan (the batched form of the W-action for many
+ * independent systems; the paper treats pairs as independent units, and
+ * here whole systems are too): bse_batch_plan_create captures the whole
+ * propagation of every system (its arguments as in bse_apply_W_batch,
+ * pair lists copied to the plan's own device buffers, w_dev[k] bound to the
+ * plan) into one HIP graph with one branch per system and instantiates it
+ * once; bse_batch_plan_run replays it.  A run is ordered after the work
+ * already queued on every system's stream, every system's stream waits for
+ * it, and it returns after enqueueing.  Results equal bse_apply_W_batch
+ * bit for bit.  The plan uses the systems' workspaces: a run returns
+ * BSE_ERR_STATE when any system's workspace or orbitals have moved since
+ * the capture (a larger batch or orbitals of another size), and runs must
+ * not overlap other work of the same systems.  Errors: as
+ * bse_apply_W_batch. */
+typedef struct bse_batch_plan bse_batch_plan;
+bse_status bse_batch_plan_create(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
+                                 const int32_t* const* pq, void* const* w_dev, bse_batch_plan** plan);
+bse_status bse_batch_plan_run(bse_batch_plan* plan);
+void bse_batch_plan_destroy(bse_batch_plan* plan);
+
 /* Autotuner: times the tile-shape variants of the two propagation passes
  * for this system's grid, precision and a batch of n_pairs pairs and keeps
  * the fastest for later calls.  cache_path (nullable) is a text file of
@@ -403,6 +423,11 @@ bse_status bse_fno_set_params(bse_fno* fno, const float* host);
 /* Copy the master (which = 0) or compute (which = 1) weights to the host. */
 bse_status bse_fno_get_params(bse_fno* fno, float* host, int32_t which);
 bse_status bse_fno_set_stream(bse_fno* fno, void* hip_stream);
+/* Kernels of the per-mode channel mix U_k = V_k R_k of every Fourier layer
+ * (and of its two backward products): path 0 (default) the matrix cores
+ * (FP32 operands and accumulation, width up to 32), path 1 vector FMA.  The
+ * two agree to FP32 rounding.  Errors: BSE_ERR_ARG for another path. */
+bse_status bse_fno_set_mix_path(bse_fno* fno, int32_t path);
 /* y = network(x) for a batch of B samples; returns when done. */
 bse_status bse_fno_forward(bse_fno* fno, int32_t B, const void* x_dev, void* y_dev);
 /* Loss of the batch against targets t and, if grad_host is non-null, its
@@ -425,13 +450,25 @@ void bse_fno_destroy(bse_fno* fno);
 bse_status bse_fno_make_samples(bse_system* sys, int32_t n_pairs, const int32_t* pq, void* x_dev,
                                 void* t_dev, void* scale_dev);
 
-/* Surrogate W-action: W = q + s * net(x) for the pairs pq (host) into
- * w_dev[n_pairs][ng] (device, FP64).  A prediction is accepted when
- * 0 < <rho|W rho> and <rho|W^pol rho> < 0 (rho = phi_p phi_q); accepted[k]
- * (host, nullable) reports it.  With fallback != 0 every rejected pair is
- * recomputed by the propagation. */
+/* Surrogate W-action with the propagation as the judge of its error: the
+ * network's W = q + s * net(x) for every pair pq[n_pairs][2] (host) into
+ * w_dev[n_pairs][ng] (device, FP64, caller-owned); then n_judge pairs spread
+ * evenly over the list (index floor((2k+1) n_pairs / (2 n_judge)), k <
+ * n_judge) are propagated (bse_apply_W) and the network's relative L2 error
+ * |W_net - W| / |W| on each is measured on the device.  The network's other
+ * predictions are kept only when every judged error is finite and <= tol
+ * and their own sign check holds (<rho|W^pol rho> < 0 < <rho|W rho>, rho =
+ * phi_p phi_q); every other pair -- all of them when the judge rejects the
+ * network, or when n_judge = 0 or tol <= 0 -- gets the propagation's W, and
+ * the judged pairs return their propagated W.  The unjudged pairs' errors
+ * are estimated by the sample, not bounded.  accepted[n_pairs] (host,
+ * nullable): 1 where w_dev holds the network's prediction, 0 where it holds
+ * the propagation's; judged_err[n_judge] (host, nullable): the measured
+ * errors.  Errors: BSE_ERR_ARG for null buffers, 0 > n_judge > n_pairs, a
+ * non-finite tol or an index out of range. */
 bse_status bse_apply_W_surrogate(bse_system* sys, bse_fno* net, int32_t n_pairs, const int32_t* pq,
-                                 void* w_dev, int32_t fallback, int32_t* accepted);
+                                 void* w_dev, double tol, int32_t n_judge, int32_t* accepted,
+                                 double* judged_err);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,8 @@ EXPORTS = (
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
     "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
-    "bse_chebyshev_spectrum_noalloc",
+    "bse_chebyshev_spectrum_noalloc", "bse_fno_set_mix_path", "bse_batch_plan_create",
+    "bse_batch_plan_run", "bse_batch_plan_destroy",
 )
 
 
@@ -102,6 +103,11 @@ def _load():
     lib.bse_set_lanczos_path.argtypes = [P, C.c_int32]
     lib.bse_apply_W_batch.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
                                       C.c_int32]
+    lib.bse_batch_plan_create.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
+                                          C.POINTER(P)]
+    lib.bse_batch_plan_run.argtypes = [P]
+    lib.bse_batch_plan_destroy.argtypes = [P]
+    lib.bse_batch_plan_destroy.restype = None
     lib.bse_autotune.argtypes = [P, C.c_int32, C.c_char_p]
     lib.bse_tuned_shape.argtypes = [P, ip, ip]
     lib.bse_tuned_shape.restype = C.c_int32
@@ -112,6 +118,7 @@ def _load():
     lib.bse_fno_set_params.argtypes = [P, fp]
     lib.bse_fno_get_params.argtypes = [P, fp, C.c_int32]
     lib.bse_fno_set_stream.argtypes = [P, P]
+    lib.bse_fno_set_mix_path.argtypes = [P, C.c_int32]
     lib.bse_fno_forward.argtypes = [P, C.c_int32, P, P]
     lib.bse_fno_loss_grad.argtypes = [P, C.c_int32, P, P, dp, fp]
     lib.bse_fno_train_step.argtypes = [P, C.c_int32, P, P, C.c_double, dp]
@@ -119,7 +126,7 @@ def _load():
     lib.bse_fno_max_batch.argtypes = [P]
     lib.bse_fno_max_batch.restype = C.c_int32
     lib.bse_fno_make_samples.argtypes = [P, C.c_int32, ip, P, P, P]
-    lib.bse_apply_W_surrogate.argtypes = [P, P, C.c_int32, ip, P, C.c_int32, ip]
+    lib.bse_apply_W_surrogate.argtypes = [P, P, C.c_int32, ip, P, C.c_double, C.c_int32, ip, dp]
     lib.bse_fno_destroy.argtypes = [P]
     lib.bse_fno_destroy.restype = None
     lib.bse_last_error.restype = C.c_char_p
@@ -157,6 +164,34 @@ def apply_w_batch(systems, pair_lists, w_dev_ptrs, use_graph: bool = True):
     pq_ptrs = (C.POINTER(C.c_int32) * n)(*[_iptr(p) for p in pqs])
     w_ptrs = (C.c_void_p * n)(*[C.c_void_p(p) for p in w_dev_ptrs])
     _check(LIB.bse_apply_W_batch(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, 1 if use_graph else 0))
+
+
+class BatchPlan:
+    """A captured uneven batch (bse_batch_plan_*): create once, run many
+    times; outputs go to the device buffers given at creation."""
+
+    def __init__(self, systems, pair_lists, w_dev_ptrs):
+        n = len(systems)
+        self._systems = list(systems)          # the plan uses their workspaces
+        hs = (C.c_void_p * n)(*[s._h for s in systems])
+        self._pqs = [np.ascontiguousarray(np.asarray(p, dtype=np.int32).reshape(-1, 2)) for p in pair_lists]
+        npairs = np.array([p.shape[0] for p in self._pqs], dtype=np.int32)
+        pq_ptrs = (C.POINTER(C.c_int32) * n)(*[_iptr(p) for p in self._pqs])
+        w_ptrs = (C.c_void_p * n)(*[C.c_void_p(p) for p in w_dev_ptrs])
+        h = C.c_void_p()
+        _check(LIB.bse_batch_plan_create(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, C.byref(h)))
+        self._h = h
+
+    def run(self):
+        _check(LIB.bse_batch_plan_run(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.bse_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def fit_box_correction(omega, v_bndry):
@@ -447,6 +482,10 @@ class Fno:
     def set_stream(self, stream_ptr: int):
         _fcheck(LIB.bse_fno_set_stream(self._h, C.c_void_p(stream_ptr)))
 
+    def set_mix_path(self, path: int):
+        """bse_fno_set_mix_path: 0 matrix cores, 1 vector FMA."""
+        _fcheck(LIB.bse_fno_set_mix_path(self._h, int(path)))
+
     def forward(self, B: int, x_ptr: int, y_ptr: int):
         _fcheck(LIB.bse_fno_forward(self._h, B, C.c_void_p(x_ptr), C.c_void_p(y_ptr)))
 
@@ -473,11 +512,12 @@ def make_samples(system: "System", pairs, x_ptr: int, t_ptr: Optional[int] = Non
                                     C.c_void_p(scale_ptr) if scale_ptr else None))
 
 
-def apply_w_surrogate(system: "System", net: "Fno", pairs, w_ptr: int, fallback: bool = True):
-    """Surrogate W-action with acceptance checks (bse_apply_W_surrogate);
-    returns the per-pair acceptance flags."""
+def apply_w_surrogate(system: "System", net: "Fno", pairs, w_ptr: int, tol: float = 1e-3, n_judge: int = 4):
+    """Surrogate W-action judged by the propagation (bse_apply_W_surrogate):
+    returns (accepted flags [n_pairs], measured errors of the judged pairs)."""
     pq = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
     acc = np.zeros(pq.shape[0], dtype=np.int32)
+    err = np.zeros(max(int(n_judge), 1))
     _check(LIB.bse_apply_W_surrogate(system._h, net._h, pq.shape[0], _iptr(pq), C.c_void_p(w_ptr),
-                                     1 if fallback else 0, _iptr(acc)))
-    return acc
+                                     float(tol), int(n_judge), _iptr(acc), _dptr(err)))
+    return acc, err[:int(n_judge)]

@@ -364,12 +364,12 @@ void poissonT(bse_system* s, int B, double* acc, double wn) {
   s->timer.end(t);
 }
 
-// one batch of B pairs (pair list already on the device in s->pq_d);
+// one batch of B pairs (pair list pq_dev[B][2] on the device);
 // results W^pol (FP64) in s->wpol, q in s->q.  Only kernel launches and
 // device-to-device work are issued, so the sequence can be captured into a
 // HIP graph.  The unperturbed set is propagated alongside, double-buffered.
 template <typename T>
-void propagate_batch(bse_system* s, int B) {
+void propagate_batch(bse_system* s, int B, const int* pq_dev) {
   using C = cplx<T>;
   Tables& tb = tabs<T>(s);
   const size_t ng = s->ng;
@@ -383,7 +383,7 @@ void propagate_batch(bse_system* s, int B) {
   // unperturbed set at a cleaning step (every pair), and the final check
   // of W sets bit 0 too
   HIPC(launch_fill_zero(s->flags.p, sizeof(int) * B, st));
-  HIPC(launch_pair_density(s->phi64.as<double>(), s->pq_d.as<int>(), B, ng, s->rho64.as<double>(), st));
+  HIPC(launch_pair_density(s->phi64.as<double>(), pq_dev, B, ng, s->rho64.as<double>(), st));
   poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0, s->flags.as<int>());
   // per-pair scales for the packed Poisson solves of the induced densities:
   // the RMS of q_b (the response is linear in it), so that a pair whose
@@ -527,8 +527,8 @@ void apply_w_device(bse_system* s, int n_pairs, const int32_t* pq, void* w_dev, 
     if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, B);
     else ensure_batch<float>(s, B);
     HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
-    if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
-    else propagate_batch<float>(s, B);
+    if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B, s->pq_d.as<int>());
+    else propagate_batch<float>(s, B, s->pq_d.as<int>());
     const size_t off = (size_t)k0 * s->ng;
     const size_t cnt = (size_t)B * s->ng;
     // W = q + W^pol; the check reads the FP64 sum before any narrowing
@@ -1379,8 +1379,8 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
       bse_system* s = sys[i];
       HIPC(hipStreamWaitEvent(s->stream, ev[n_sys], 0));
       const int B = n_pairs[i];
-      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
-      else propagate_batch<float>(s, B);
+      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B, s->pq_d.as<int>());
+      else propagate_batch<float>(s, B, s->pq_d.as<int>());
       double* w = reinterpret_cast<double*>(w_dev[i]);
       HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)B * s->ng, w, s->stream));
       HIPC(launch_finite_check(w, B, s->ng, s->flags.as<int>(), s->stream));
@@ -1404,6 +1404,154 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
     throw;
   }
   restore();
+}
+
+// ---------------------------------------------------------------------------
+// batch plan: the whole propagation of an uneven batch captured into one
+// HIP graph once, replayed by every run (capture and instantiation stay out
+// of the runs); each system on its own branch, pair lists in the plan's own
+// device buffers
+// ---------------------------------------------------------------------------
+// the device addresses the captured kernels use: a run is refused when any
+// of them has changed since the capture (a workspace grown by a larger
+// batch, new orbitals of another size)
+std::vector<const void*> workspace_signature(const bse_system* s) {
+  const DBuf* bufs[] = {&s->d, &s->u, &s->dens, &s->wpol, &s->q, &s->rho64, &s->work, &s->work64,
+                        &s->part, &s->part32, &s->gpart, &s->coef, &s->coefE, &s->E, &s->flags,
+                        &s->pscale, &s->normpart, &s->phi64, &s->phi_occ32, &s->phih, &s->phil,
+                        &s->phith, &s->phitl, &s->eta0, &s->h0, &s->hbuf, &s->n0,
+                        &s->tf.tw, &s->tf.kph, &s->tf.pf, &s->tf.ph, &s->tf.k2,
+                        &s->td.tw, &s->td.kph, &s->td.pf, &s->td.ph, &s->td.k2};
+  std::vector<const void*> sig;
+  for (const DBuf* b : bufs) sig.push_back(b->p);
+  sig.push_back(reinterpret_cast<const void*>((uintptr_t)s->cap_b));
+  return sig;
+}
+
+}  // namespace
+
+struct bse_batch_plan {
+  std::vector<bse_system*> sys;
+  std::vector<int> npairs;
+  std::vector<DBuf> pq;
+  std::vector<std::vector<const void*>> sig;
+  hipStream_t origin = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> pre;
+  hipEvent_t done = nullptr;
+  int device = 0;
+  ~bse_batch_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : pre) if (e) (void)hipEventDestroy(e);
+    if (done) (void)hipEventDestroy(done);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+};
+
+namespace {
+
+void plan_create(int n_sys, bse_system* const* sys, const int32_t* n_pairs, const int32_t* const* pq,
+                 void* const* w_dev, bse_batch_plan** out) {
+  if (n_sys < 1 || !sys || !n_pairs || !pq || !w_dev || !out) fail(BSE_ERR_ARG, "bse_batch_plan_create: null argument");
+  int dev = -1;
+  for (int i = 0; i < n_sys; ++i) {
+    bse_system* s = sys[i];
+    check_ready(s);
+    if (dev < 0) dev = s->cfg.device;
+    if (s->cfg.device != dev) fail(BSE_ERR_ARG, "bse_batch_plan_create: systems on different devices");
+    if (n_pairs[i] < 1 || n_pairs[i] > s->cfg.max_batch || !pq[i] || !w_dev[i])
+      fail(BSE_ERR_ARG, "bse_batch_plan_create: need 1 <= n_pairs <= max_batch and non-null buffers");
+    for (int j = i + 1; j < n_sys; ++j)
+      if (sys[j] == s) fail(BSE_ERR_ARG, "bse_batch_plan_create: a system appears twice");
+    check_pairs(s, n_pairs[i], pq[i]);
+  }
+  HIPC(hipSetDevice(dev));
+  auto* P = new bse_batch_plan();
+  std::vector<hipStream_t> saved(n_sys);
+  std::vector<char> timer_was(n_sys, 0);
+  std::vector<hipEvent_t> ev(n_sys + 1, nullptr);
+  auto restore = [&]() {
+    for (int i = 0; i < n_sys; ++i) {
+      sys[i]->stream = saved[i];
+      sys[i]->timer.on = timer_was[i] != 0;
+    }
+    for (auto e : ev) if (e) (void)hipEventDestroy(e);
+  };
+  try {
+    P->device = dev;
+    P->sys.assign(sys, sys + n_sys);
+    P->npairs.assign(n_pairs, n_pairs + n_sys);
+    P->pq.resize(n_sys);
+    P->pre.assign(n_sys, nullptr);
+    HIPC(hipStreamCreateWithFlags(&P->origin, hipStreamNonBlocking));
+    HIPC(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
+    for (auto& e : P->pre) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : ev) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int i = 0; i < n_sys; ++i) {
+      bse_system* s = sys[i];
+      if (!s->own_stream) HIPC(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+      saved[i] = s->stream;
+      timer_was[i] = s->timer.on ? 1 : 0;
+      // the workspace is sized before the capture and must not move after it
+      HIPC(hipStreamSynchronize(s->stream));
+      if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, n_pairs[i]);
+      else ensure_batch<float>(s, n_pairs[i]);
+      P->pq[i].alloc(sizeof(int) * 2 * n_pairs[i]);
+      HIPC(hipMemcpy(P->pq[i].p, pq[i], sizeof(int) * 2 * n_pairs[i], hipMemcpyHostToDevice));
+      s->stream = s->own_stream;
+      s->timer.on = false;
+    }
+    HIPC(hipStreamBeginCapture(P->origin, hipStreamCaptureModeThreadLocal));
+    HIPC(hipEventRecord(ev[n_sys], P->origin));
+    for (int i = 0; i < n_sys; ++i) {
+      bse_system* s = sys[i];
+      HIPC(hipStreamWaitEvent(s->stream, ev[n_sys], 0));
+      const int B = n_pairs[i];
+      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B, P->pq[i].as<int>());
+      else propagate_batch<float>(s, B, P->pq[i].as<int>());
+      double* w = reinterpret_cast<double*>(w_dev[i]);
+      HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)B * s->ng, w, s->stream));
+      HIPC(launch_finite_check(w, B, s->ng, s->flags.as<int>(), s->stream));
+      HIPC(launch_nan_flagged(w, B, s->ng, s->flags.as<int>(), s->stream));
+      HIPC(hipEventRecord(ev[i], s->stream));
+      HIPC(hipStreamWaitEvent(P->origin, ev[i], 0));
+    }
+    HIPC(hipStreamEndCapture(P->origin, &P->graph));
+    HIPC(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+    for (int i = 0; i < n_sys; ++i) P->sig.push_back(workspace_signature(sys[i]));
+  } catch (...) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (P->origin && hipStreamIsCapturing(P->origin, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(P->origin, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    restore();
+    delete P;
+    throw;
+  }
+  restore();
+  *out = P;
+}
+
+// stream-ordered: after the work already on every system's stream; every
+// system's stream then waits for the whole batch
+void plan_run(bse_batch_plan* P) {
+  if (!P) fail(BSE_ERR_ARG, "bse_batch_plan_run: null plan");
+  for (size_t i = 0; i < P->sys.size(); ++i)
+    if (workspace_signature(P->sys[i]) != P->sig[i])
+      fail(BSE_ERR_STATE, "bse_batch_plan_run: a system's workspace or orbitals moved since the plan was "
+                          "made (larger batch or new orbitals); make a new plan");
+  HIPC(hipSetDevice(P->device));
+  for (size_t i = 0; i < P->sys.size(); ++i) {
+    HIPC(hipEventRecord(P->pre[i], P->sys[i]->stream));
+    HIPC(hipStreamWaitEvent(P->origin, P->pre[i], 0));
+  }
+  HIPC(hipGraphLaunch(P->exec, P->origin));
+  HIPC(hipEventRecord(P->done, P->origin));
+  for (bse_system* s : P->sys) HIPC(hipStreamWaitEvent(s->stream, P->done, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -1487,8 +1635,8 @@ void make_samples(bse_system* s, int n_pairs, const int32_t* pq, float* x, float
     else ensure_batch<float>(s, B);
     HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
     if (t) {
-      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B);
-      else propagate_batch<float>(s, B);
+      if (s->cfg.precision == BSE_FP64) propagate_batch<double>(s, B, s->pq_d.as<int>());
+      else propagate_batch<float>(s, B, s->pq_d.as<int>());
     }
     source_and_scale(s, B);
     HIPC(launch_features(s->q.as<double>(), s->fscale.as<double>(), s->n0dens.as<double>(), s->n0_scale,
@@ -1502,64 +1650,116 @@ void make_samples(bse_system* s, int n_pairs, const int32_t* pq, float* x, float
   HIPC(hipStreamSynchronize(s->stream));
 }
 
-void apply_w_surrogate(bse_system* s, bse_fno* net, int n_pairs, const int32_t* pq, double* w_dev,
-                       int fallback, int32_t* accepted) {
+// Surrogate W-action with the propagation as the judge of its error:
+// 1. W = q + s net(x) for every pair (device), with the sign check of the
+//    screened energy <rho|W^pol rho> < 0 < <rho|W rho>;
+// 2. n_judge pairs spread over the list are propagated, and the relative
+//    L2 error of the network on each of them is measured on the device;
+// 3. the other predictions are kept only if every judged error is finite
+//    and at most tol (and their own sign check passes); every pair not kept
+//    -- all of them when the judge rejects the network -- gets the
+//    propagation's W, and the judged pairs keep their propagated W.
+void apply_w_surrogate(bse_system* s, bse_fno* net, int n_pairs, const int32_t* pq, double* w_dev, double tol,
+                       int n_judge, int32_t* accepted, double* judged_err) {
   check_ready(s);
-  if (!net || n_pairs < 1 || !pq || !w_dev) fail(BSE_ERR_ARG, "bse_apply_W_surrogate: bad arguments");
-  for (int k = 0; k < n_pairs; ++k)
-    if (pq[2 * k] < 0 || pq[2 * k] >= s->n_orb || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= s->n_orb)
-      fail(BSE_ERR_ARG, "pair index out of range");
+  if (!net || n_pairs < 1 || !pq || !w_dev || n_judge < 0 || n_judge > n_pairs || !std::isfinite(tol))
+    fail(BSE_ERR_ARG, "bse_apply_W_surrogate: bad arguments");
+  check_pairs(s, n_pairs, pq);
   surrogate_descriptors(s);
+  const size_t ng = s->ng;
   const int Bmax = std::max(1, std::min(s->cfg.max_batch, bse_fno_max_batch(net)));
-  std::vector<int32_t> acc(n_pairs, 0);
+  std::vector<int32_t> sign_ok(n_pairs, 0);
   HIPC(bse_fno_set_stream(net, s->stream) == BSE_OK ? hipSuccess : hipErrorInvalidValue);
+  // 1. predictions
   for (int k0 = 0; k0 < n_pairs; k0 += Bmax) {
     const int B = std::min(Bmax, n_pairs - k0);
     if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, B);
     else ensure_batch<float>(s, B);
-    s->fx.alloc(sizeof(float) * 3 * s->ng * B);
-    s->fy.alloc(sizeof(float) * s->ng * B);
-    s->fwpol.alloc(sizeof(double) * s->ng * B);
+    s->fx.alloc(sizeof(float) * 3 * ng * B);
+    s->fy.alloc(sizeof(float) * ng * B);
+    s->fwpol.alloc(sizeof(double) * ng * B);
     HIPC(hipMemcpyAsync(s->pq_d.p, pq + 2 * k0, sizeof(int) * 2 * B, hipMemcpyHostToDevice, s->stream));
     source_and_scale(s, B);
     HIPC(launch_features(s->q.as<double>(), s->fscale.as<double>(), s->n0dens.as<double>(), s->n0_scale,
-                         s->vdev.as<double>(), s->v_scale, B, s->ng, s->fx.as<float>(), s->stream));
+                         s->vdev.as<double>(), s->v_scale, B, ng, s->fx.as<float>(), s->stream));
     if (bse_fno_forward(net, B, s->fx.p, s->fy.p) != BSE_OK)
       fail(BSE_ERR_DEVICE, std::string("surrogate forward: ") + bse_fno_last_error());
-    HIPC(launch_assemble_w(s->q.as<double>(), s->fscale.as<double>(), s->fy.as<float>(), B, s->ng,
-                           s->fwpol.as<double>(), w_dev + (size_t)k0 * s->ng, s->stream));
-    // acceptance: 0 < <rho|W rho> and <rho|W^pol rho> < 0 (screening lowers
-    // the Coulomb energy of the pair density without reversing its sign)
-    HIPC(launch_row_dots(s->rho64.as<double>(), s->q.as<double>(), s->fwpol.as<double>(), B, s->ng,
+    HIPC(launch_assemble_w(s->q.as<double>(), s->fscale.as<double>(), s->fy.as<float>(), B, ng,
+                           s->fwpol.as<double>(), w_dev + (size_t)k0 * ng, s->stream));
+    HIPC(launch_row_dots(s->rho64.as<double>(), s->q.as<double>(), s->fwpol.as<double>(), B, ng,
                          s->fdots.as<double>(), s->stream));
     std::vector<double> dots(3 * (size_t)B);
     HIPC(hipMemcpyAsync(dots.data(), s->fdots.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s->stream));
     HIPC(hipStreamSynchronize(s->stream));
     for (int b = 0; b < B; ++b) {
       const double e0 = dots[3 * (size_t)b + 1], e = dots[3 * (size_t)b + 2];
-      acc[k0 + b] = (std::isfinite(e) && e < 0.0 && e > -e0) ? 1 : 0;
+      sign_ok[k0 + b] = (std::isfinite(e) && e < 0.0 && e > -e0) ? 1 : 0;
     }
   }
-  if (fallback) {
-    std::vector<int32_t> rej;
-    std::vector<int> idx;
-    for (int k = 0; k < n_pairs; ++k)
-      if (!acc[k]) {
-        rej.push_back(pq[2 * k]);
-        rej.push_back(pq[2 * k + 1]);
-        idx.push_back(k);
-      }
-    if (!idx.empty()) {
-      DBuf tmp;
-      tmp.alloc(sizeof(double) * s->ng * idx.size());
-      apply_w_device(s, (int)idx.size(), rej.data(), tmp.p, false, nullptr, nullptr);
-      for (size_t j = 0; j < idx.size(); ++j)
-        HIPC(hipMemcpyAsync(w_dev + (size_t)idx[j] * s->ng, tmp.as<double>() + j * s->ng,
-                            sizeof(double) * s->ng, hipMemcpyDeviceToDevice, s->stream));
-      HIPC(hipStreamSynchronize(s->stream));
+  // 2. the judge: propagate a spread sample and measure the network's error
+  std::vector<int> jidx(n_judge);
+  std::vector<char> is_judged(n_pairs, 0);
+  for (int k = 0; k < n_judge; ++k) {
+    jidx[k] = (int)(((int64_t)2 * k + 1) * n_pairs / (2 * (int64_t)n_judge));
+    is_judged[jidx[k]] = 1;
+  }
+  bool net_ok = n_judge > 0 && tol > 0;
+  DBuf jw, jrows, jnorm;
+  std::vector<double> err(n_judge, 0.0);
+  if (n_judge > 0) {
+    std::vector<int32_t> jpq(2 * (size_t)n_judge);
+    for (int k = 0; k < n_judge; ++k) {
+      jpq[2 * k] = pq[2 * jidx[k]];
+      jpq[2 * k + 1] = pq[2 * jidx[k] + 1];
+    }
+    jw.alloc(sizeof(double) * ng * n_judge);
+    jrows.alloc(sizeof(int) * n_judge);
+    jnorm.alloc(sizeof(double) * 2 * n_judge);
+    std::vector<int32_t> jst(n_judge, 0);
+    try {
+      apply_w_device(s, n_judge, jpq.data(), jw.p, false, nullptr, jst.data());
+    } catch (const Fail& f) {
+      if (f.st != BSE_ERR_NUMERIC) throw;
+      net_ok = false;     // a failed judge pair: its row stays NaN, nothing is accepted
+    }
+    HIPC(hipMemcpyAsync(jrows.p, jidx.data(), sizeof(int) * n_judge, hipMemcpyHostToDevice, s->stream));
+    HIPC(launch_diff_norms(w_dev, jrows.as<int>(), jw.as<double>(), n_judge, ng, jnorm.as<double>(), s->stream));
+    std::vector<double> nrm(2 * (size_t)n_judge);
+    HIPC(hipMemcpyAsync(nrm.data(), jnorm.p, sizeof(double) * nrm.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < n_judge; ++k) {
+      err[k] = std::sqrt(nrm[2 * (size_t)k] / nrm[2 * (size_t)k + 1]);
+      if (!(err[k] <= tol)) net_ok = false;
+    }
+    // the judged pairs return their propagated W
+    for (int k = 0; k < n_judge; ++k)
+      HIPC(hipMemcpyAsync(w_dev + (size_t)jidx[k] * ng, jw.as<double>() + (size_t)k * ng, sizeof(double) * ng,
+                          hipMemcpyDeviceToDevice, s->stream));
+  }
+  // 3. every prediction not kept is replaced by the propagation's W
+  std::vector<int32_t> acc(n_pairs, 0), rej;
+  std::vector<int> ridx;
+  for (int k = 0; k < n_pairs; ++k) {
+    if (is_judged[k]) continue;
+    if (net_ok && sign_ok[k]) {
+      acc[k] = 1;
+    } else {
+      rej.push_back(pq[2 * k]);
+      rej.push_back(pq[2 * k + 1]);
+      ridx.push_back(k);
     }
   }
+  if (!ridx.empty()) {
+    DBuf tmp;
+    tmp.alloc(sizeof(double) * ng * ridx.size());
+    apply_w_device(s, (int)ridx.size(), rej.data(), tmp.p, false, nullptr, nullptr);
+    for (size_t j = 0; j < ridx.size(); ++j)
+      HIPC(hipMemcpyAsync(w_dev + (size_t)ridx[j] * ng, tmp.as<double>() + j * ng, sizeof(double) * ng,
+                          hipMemcpyDeviceToDevice, s->stream));
+  }
+  HIPC(hipStreamSynchronize(s->stream));
   if (accepted) std::memcpy(accepted, acc.data(), sizeof(int32_t) * n_pairs);
+  if (judged_err && n_judge > 0) std::memcpy(judged_err, err.data(), sizeof(double) * n_judge);
 }
 
 #define API_BEGIN try {
@@ -1916,6 +2116,27 @@ bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const in
   API_END
 }
 
+bse_status bse_batch_plan_create(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
+                                 const int32_t* const* pq, void* const* w_dev, bse_batch_plan** plan) {
+  API_BEGIN
+  if (plan) *plan = nullptr;
+  plan_create(n_sys, systems, n_pairs, pq, w_dev, plan);
+  API_END
+}
+
+bse_status bse_batch_plan_run(bse_batch_plan* plan) {
+  API_BEGIN
+  plan_run(plan);
+  API_END
+}
+
+void bse_batch_plan_destroy(bse_batch_plan* plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->device);
+  (void)hipStreamSynchronize(plan->origin);
+  delete plan;
+}
+
 bse_status bse_fno_make_samples(bse_system* s, int32_t n_pairs, const int32_t* pq, void* x_dev,
                                 void* t_dev, void* scale_dev) {
   API_BEGIN
@@ -1925,9 +2146,10 @@ bse_status bse_fno_make_samples(bse_system* s, int32_t n_pairs, const int32_t* p
 }
 
 bse_status bse_apply_W_surrogate(bse_system* s, bse_fno* net, int32_t n_pairs, const int32_t* pq,
-                                 void* w_dev, int32_t fallback, int32_t* accepted) {
+                                 void* w_dev, double tol, int32_t n_judge, int32_t* accepted,
+                                 double* judged_err) {
   API_BEGIN
-  apply_w_surrogate(s, net, n_pairs, pq, reinterpret_cast<double*>(w_dev), fallback, accepted);
+  apply_w_surrogate(s, net, n_pairs, pq, reinterpret_cast<double*>(w_dev), tol, n_judge, accepted, judged_err);
   API_END
 }
 

@@ -106,6 +106,9 @@ hipError_t launch_features(const double* q, const double* scale, const double* n
                            const double* v, double vs, int B, size_t ng, float* x, hipStream_t st);
 hipError_t launch_targets(const double* wpol, const double* scale, int B, size_t ng, float* t,
                           hipStream_t st);
+// out[2k] = |a[rows[k]] - b[k]|^2, out[2k+1] = |b[k]|^2 over ng points, k < K
+hipError_t launch_diff_norms(const double* a, const int* rows, const double* b, int K, size_t ng, double* out,
+                             hipStream_t st);
 hipError_t launch_assemble_w(const double* q, const double* scale, const float* y, int B, size_t ng,
                              double* wpol, double* w, hipStream_t st);
 }  // namespace bse

@@ -1139,6 +1139,37 @@ __global__ void k_targets(const double* __restrict__ wpol, const double* __restr
 }
 
 // wpol_b = s_b y_b (FP64), w_b = q_b + wpol_b
+// The surrogate's judge: for judged pair k, out[2k] = sum_r (a[rows[k]] - b[k])^2
+// and out[2k+1] = sum_r b[k]^2 (one block per pair, fixed reduction order).
+__global__ void __launch_bounds__(256) k_diff_norms(const double* __restrict__ a, const int* __restrict__ rows,
+                                                    const double* __restrict__ b, size_t ng,
+                                                    double* __restrict__ out) {
+  const int k = blockIdx.x;
+  const double* x = a + (size_t)rows[k] * ng;
+  const double* y = b + (size_t)k * ng;
+  double s0 = 0, s1 = 0;
+  for (size_t r = threadIdx.x; r < ng; r += 256) {
+    const double d = x[r] - y[r];
+    s0 += d * d;
+    s1 += y[r] * y[r];
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * k] = red[0][0];
+    out[2 * k + 1] = red[1][0];
+  }
+}
+
 __global__ void k_assemble_w(const double* __restrict__ q, const double* __restrict__ scale,
                              const float* __restrict__ y, size_t ng, double* __restrict__ wpol,
                              double* __restrict__ w) {
@@ -1255,6 +1286,12 @@ hipError_t launch_targets(const double* wpol, const double* scale, int B, size_t
                           hipStream_t st) {
   hipLaunchKernelGGL(k_targets, dim3((unsigned)((ng + 255) / 256), B), dim3(256), 0, st, wpol, scale,
                      ng, t);
+  return hipGetLastError();
+}
+hipError_t launch_diff_norms(const double* a, const int* rows, const double* b, int K, size_t ng, double* out,
+                             hipStream_t st) {
+  if (K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diff_norms, dim3(K), dim3(256), 0, st, a, rows, b, ng, out);
   return hipGetLastError();
 }
 hipError_t launch_assemble_w(const double* q, const double* scale, const float* y, int B, size_t ng,

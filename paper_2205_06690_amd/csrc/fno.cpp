@@ -65,6 +65,7 @@ struct bse_fno {
   Buf master, compute, grad, adam_m, adam_v, tw;
   int step = 0;
   int cap = 0;
+  int mix_path = 0;   // per-mode channel mix: 0 matrix cores, 1 vector FMA
   std::vector<Buf> h, z, V;
   Buf s, gh_a, gh_b, work, U, GU, GV, part, gy, y, loss_part, tn;
 };
@@ -127,7 +128,7 @@ void forward(bse_fno* f, int B, const float* x, float* y) {
   for (int l = 0; l < L; ++l) {
     FCK(fno_fft_fwd(n, f->h[l].f(), B * W, f->tw.c(), m, 0, f->work.c(), f->V[l].c(), st));
     FCK(fno_spec_mix(f->V[l].c(), reinterpret_cast<const float2*>(prm(f, f->off_R[l])), B, W, f->K,
-                     f->U.c(), st));
+                     f->U.c(), f->mix_path, st));
     FCK(fno_fft_inv(n, f->U.c(), B * W, f->tw.c(), m, 1, f->work.c(), f->s.f(), 0, st));
     FCK(fno_pointwise(f->h[l].f(), W, prm(f, f->off_W[l]), prm(f, f->off_b[l]), W, f->s.f(), B,
                       f->ng, l < L - 1 ? 1 : 0, f->z[l].f(), f->h[l + 1].f(), st));
@@ -170,7 +171,8 @@ double loss_grad(bse_fno* f, int B, const float* x, const float* t) {
     FCK(fno_outer(gh, W, f->h[l].f(), W, B, f->ng, f->part.f(), g + f->off_W[l], g + f->off_b[l], st));
     FCK(fno_fft_fwd(n, gh, B * W, f->tw.c(), m, 1, f->work.c(), f->GU.c(), st));
     FCK(fno_spec_mix_bwd(f->V[l].c(), f->GU.c(), reinterpret_cast<const float2*>(prm(f, f->off_R[l])),
-                         B, W, f->K, f->GV.c(), reinterpret_cast<float2*>(g + f->off_R[l]), st));
+                         B, W, f->K, f->GV.c(), reinterpret_cast<float2*>(g + f->off_R[l]), f->mix_path,
+                         st));
     FCK(fno_fft_inv(n, f->GV.c(), B * W, f->tw.c(), m, 0, f->work.c(), gn, 0, st));
     FCK(fno_pointwise_bwd(gh, W, prm(f, f->off_W[l]), W, B, f->ng, gn, st));
     std::swap(gh, gn);
@@ -285,6 +287,14 @@ bse_status bse_fno_set_stream(bse_fno* f, void* st) {
   FAPI_BEGIN
   if (!f) ffail(BSE_ERR_ARG, "null surrogate");
   f->stream = reinterpret_cast<hipStream_t>(st);
+  FAPI_END
+}
+
+bse_status bse_fno_set_mix_path(bse_fno* f, int32_t path) {
+  FAPI_BEGIN
+  if (!f) ffail(BSE_ERR_ARG, "null surrogate");
+  if (path != 0 && path != 1) ffail(BSE_ERR_ARG, "bse_fno_set_mix_path: path 0 or 1");
+  f->mix_path = path;
   FAPI_END
 }
 

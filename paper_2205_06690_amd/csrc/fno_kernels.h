@@ -13,9 +13,12 @@ hipError_t fno_fft_fwd(int n, const float* in, int F, const float2* tw, int m, i
 // (U times c_k/ng if ck)
 hipError_t fno_fft_inv(int n, const float2* U, int F, const float2* tw, int m, int ck, float2* work,
                        float* out, int accumulate, hipStream_t st);
-hipError_t fno_spec_mix(const float2* V, const float2* R, int B, int C, int K, float2* U, hipStream_t st);
+// per-mode channel mix U[b][o][k] = sum_i V[b][i][k] R[k][i][o] and its two
+// backward products; path 0: matrix cores (up to 32 channels), 1: vector FMA
+hipError_t fno_spec_mix(const float2* V, const float2* R, int B, int C, int K, float2* U, int path,
+                        hipStream_t st);
 hipError_t fno_spec_mix_bwd(const float2* V, const float2* GU, const float2* R, int B, int C, int K,
-                            float2* GV, float2* GR, hipStream_t st);
+                            float2* GV, float2* GR, int path, hipStream_t st);
 hipError_t fno_pointwise(const float* in, int Cin, const float* Wm, const float* bias, int Cout,
                          const float* add, int B, size_t ng, int act, float* zout, float* out,
                          hipStream_t st);

@@ -254,6 +254,179 @@ __global__ void k_spec_mix_bwd_r(const float2* __restrict__ V, const float2* __r
 }
 
 // ---------------------------------------------------------------------------
+// The same three products on the matrix cores (v_mfma_f32_16x16x4f32, FP32
+// operands and accumulation), one wave per Fourier mode k, for channel
+// counts up to 32 (padded with zeros to CP, a multiple of 16).  A complex
+// product X Y is the real product of [Xr | Xi] with the 2 x 2 block form of
+// Y, so the real and imaginary parts of an output are two column tiles of
+// one real GEMM.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of
+// a 16 x 4 by 4 x 16 step and holds D[4 (l / 16) + j][l % 16], j < 4.
+// Every output is written once (no atomics): results do not depend on
+// scheduling.
+// ---------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// U_k = V_k R_k: rows b (16 per pass), columns [Ur | Ui], contraction over
+// [i re | i im] with blocks [[Rr, Ri], [-Ri, Rr]]
+template <int CP>
+__global__ void __launch_bounds__(256) k_spec_mix_mfma(const float2* __restrict__ V,
+                                                       const float2* __restrict__ R, int B, int C, int K,
+                                                       float2* __restrict__ U) {
+  constexpr int S = CP / 4, T = CP / 16;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= K) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const float2* Rk = R + (size_t)k * C * C;
+  float2 r[S][T];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int i = 4 * s + lk, o = 16 * t + lr;
+      r[s][t] = (i < C && o < C) ? Rk[(size_t)i * C + o] : make_float2(0.f, 0.f);
+    }
+  for (int b0 = 0; b0 < B; b0 += 16) {
+    const int b = b0 + lr;
+    float2 v[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = 4 * s + lk;
+      v[s] = (b < B && i < C) ? V[((size_t)b * C + i) * K + k] : make_float2(0.f, 0.f);
+    }
+    mf4 acc[2 * T];
+#pragma unroll
+    for (int t = 0; t < 2 * T; ++t) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float a = part == 0 ? v[s].x : v[s].y;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const float2 rr = r[s][t];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? rr.x : -rr.y, acc[t], 0, 0, 0);
+          acc[T + t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? rr.y : rr.x, acc[T + t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = b0 + 4 * lk + j, o = 16 * t + lr;
+        if (row < B && o < C) U[((size_t)row * C + o) * K + k] = make_float2(acc[t][j], acc[T + t][j]);
+      }
+  }
+}
+
+// GV_k = GU_k conj(R_k)^T: rows b, columns [GVr | GVi] over i, contraction
+// over [o re | o im] with blocks [[Rr^T, -Ri^T], [Ri^T, Rr^T]]
+template <int CP>
+__global__ void __launch_bounds__(256) k_spec_mix_bwd_v_mfma(const float2* __restrict__ GU,
+                                                             const float2* __restrict__ R, int B, int C,
+                                                             int K, float2* __restrict__ GV) {
+  constexpr int S = CP / 4, T = CP / 16;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= K) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const float2* Rk = R + (size_t)k * C * C;
+  float2 r[S][T];                       // r[s][t] = R[i = 16 t + lr][o = 4 s + lk]
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int o = 4 * s + lk, i = 16 * t + lr;
+      r[s][t] = (i < C && o < C) ? Rk[(size_t)i * C + o] : make_float2(0.f, 0.f);
+    }
+  for (int b0 = 0; b0 < B; b0 += 16) {
+    const int b = b0 + lr;
+    float2 g[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int o = 4 * s + lk;
+      g[s] = (b < B && o < C) ? GU[((size_t)b * C + o) * K + k] : make_float2(0.f, 0.f);
+    }
+    mf4 acc[2 * T];
+#pragma unroll
+    for (int t = 0; t < 2 * T; ++t) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float a = part == 0 ? g[s].x : g[s].y;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const float2 rr = r[s][t];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? rr.x : rr.y, acc[t], 0, 0, 0);
+          acc[T + t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? -rr.y : rr.x, acc[T + t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = b0 + 4 * lk + j, i = 16 * t + lr;
+        if (row < B && i < C) GV[((size_t)row * C + i) * K + k] = make_float2(acc[t][j], acc[T + t][j]);
+      }
+  }
+}
+
+// GR_k = V_k^H GU_k: rows i, columns [GRr | GRi] over o, contraction over
+// [b re | b im] (four batch entries per step) with blocks
+// [[GUr, GUi], [GUi, -GUr]]
+template <int CP>
+__global__ void __launch_bounds__(256) k_spec_mix_bwd_r_mfma(const float2* __restrict__ V,
+                                                             const float2* __restrict__ GU, int B, int C,
+                                                             int K, float2* __restrict__ GR) {
+  constexpr int T = CP / 16;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= K) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  mf4 acc[T][2 * T];
+#pragma unroll
+  for (int m = 0; m < T; ++m)
+#pragma unroll
+    for (int t = 0; t < 2 * T; ++t) acc[m][t] = mf4{0.f, 0.f, 0.f, 0.f};
+  for (int b0 = 0; b0 < B; b0 += 4) {
+    const int b = b0 + lk;
+    float2 va[T], gb[T];
+#pragma unroll
+    for (int m = 0; m < T; ++m) {
+      const int i = 16 * m + lr;
+      va[m] = (b < B && i < C) ? V[((size_t)b * C + i) * K + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int o = 16 * t + lr;
+      gb[t] = (b < B && o < C) ? GU[((size_t)b * C + o) * K + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int m = 0; m < T; ++m) {
+        const float a = part == 0 ? va[m].x : va[m].y;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const float2 g = gb[t];
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? g.x : g.y, acc[m][t], 0, 0, 0);
+          acc[m][T + t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, part == 0 ? g.y : -g.x, acc[m][T + t], 0, 0, 0);
+        }
+      }
+  }
+#pragma unroll
+  for (int m = 0; m < T; ++m)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = 16 * m + 4 * lk + j, o = 16 * t + lr;
+        if (i < C && o < C) GR[((size_t)k * C + i) * C + o] = make_float2(acc[m][t][j], acc[m][T + t][j]);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // pointwise channel layers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -524,14 +697,34 @@ void fno_configure(int n) {
 
 static inline unsigned nb(size_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t fno_spec_mix(const float2* V, const float2* R, int B, int C, int K, float2* U, hipStream_t st) {
-  hipLaunchKernelGGL(k_spec_mix, dim3(nb((size_t)B * K * C)), dim3(256), 0, st, V, R, B, C, K, U);
+// path 0: the matrix-core products for up to 32 channels (the vector-FMA
+// ones above beyond); path 1: the vector-FMA products only
+hipError_t fno_spec_mix(const float2* V, const float2* R, int B, int C, int K, float2* U, int path,
+                        hipStream_t st) {
+  const int g_spec_mix_path = path;
+  const unsigned nw = (unsigned)((K + 3) / 4);
+  if (g_spec_mix_path == 0 && C <= 16)
+    hipLaunchKernelGGL(k_spec_mix_mfma<16>, dim3(nw), dim3(256), 0, st, V, R, B, C, K, U);
+  else if (g_spec_mix_path == 0 && C <= 32)
+    hipLaunchKernelGGL(k_spec_mix_mfma<32>, dim3(nw), dim3(256), 0, st, V, R, B, C, K, U);
+  else
+    hipLaunchKernelGGL(k_spec_mix, dim3(nb((size_t)B * K * C)), dim3(256), 0, st, V, R, B, C, K, U);
   return hipGetLastError();
 }
 hipError_t fno_spec_mix_bwd(const float2* V, const float2* GU, const float2* R, int B, int C, int K,
-                            float2* GV, float2* GR, hipStream_t st) {
-  hipLaunchKernelGGL(k_spec_mix_bwd_v, dim3(nb((size_t)B * K * C)), dim3(256), 0, st, GU, R, B, C, K, GV);
-  hipLaunchKernelGGL(k_spec_mix_bwd_r, dim3(nb((size_t)K * C * C)), dim3(256), 0, st, V, GU, B, C, K, GR);
+                            float2* GV, float2* GR, int path, hipStream_t st) {
+  const int g_spec_mix_path = path;
+  const unsigned nw = (unsigned)((K + 3) / 4);
+  if (g_spec_mix_path == 0 && C <= 16) {
+    hipLaunchKernelGGL(k_spec_mix_bwd_v_mfma<16>, dim3(nw), dim3(256), 0, st, GU, R, B, C, K, GV);
+    hipLaunchKernelGGL(k_spec_mix_bwd_r_mfma<16>, dim3(nw), dim3(256), 0, st, V, GU, B, C, K, GR);
+  } else if (g_spec_mix_path == 0 && C <= 32) {
+    hipLaunchKernelGGL(k_spec_mix_bwd_v_mfma<32>, dim3(nw), dim3(256), 0, st, GU, R, B, C, K, GV);
+    hipLaunchKernelGGL(k_spec_mix_bwd_r_mfma<32>, dim3(nw), dim3(256), 0, st, V, GU, B, C, K, GR);
+  } else {
+    hipLaunchKernelGGL(k_spec_mix_bwd_v, dim3(nb((size_t)B * K * C)), dim3(256), 0, st, GU, R, B, C, K, GV);
+    hipLaunchKernelGGL(k_spec_mix_bwd_r, dim3(nb((size_t)K * C * C)), dim3(256), 0, st, V, GU, B, C, K, GR);
+  }
   return hipGetLastError();
 }
 hipError_t fno_pointwise(const float* in, int Cin, const float* Wm, const float* bias, int Cout,

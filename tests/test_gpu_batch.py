@@ -142,3 +142,37 @@ def test_batch_waits_for_work_on_the_systems_streams():
     torch.cuda.synchronize()
     for o, r in zip(outs, ref):
         assert np.array_equal(o.cpu().numpy(), r)
+
+
+def test_plan_replays_equal_the_batch_call():
+    """The captured plan (graph made once) gives bse_apply_W_batch's results
+    bit for bit on every replay, with the caller's own eager work between the
+    replays; it refuses to run once a system's workspace has grown."""
+    import torch
+    from paper_2205_06690_amd import bse
+    specs, pair_lists = _systems()
+    sysds = [inputs.make_system(sp) for sp in specs]
+    systems = [gpu_system(sp, sd, bse.BSE_MIXED, max_batch=len(p) + 2)
+               for sp, sd, p in zip(specs, sysds, pair_lists)]
+    ref = [s.apply_w(p) for s, p in zip(systems, pair_lists)]
+    outs = [torch.zeros((len(p), sp.ng), dtype=torch.float64, device="cuda")
+            for sp, p in zip(specs, pair_lists)]
+    plan = bse.BatchPlan(systems, pair_lists, [o.data_ptr() for o in outs])
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float(rep))                 # eager work between replays
+        plan.run()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, ref)):
+            assert np.array_equal(o.cpu().numpy(), r), (rep, k)
+        # another call on one of the systems between replays (its workspace
+        # is reused, its pair list is the plan's own)
+        systems[1].apply_w(pair_lists[1][:2])
+    say("plan: 3 replays equal the per-system results")
+    # a larger batch on system 0 moves its workspace: the plan refuses to run
+    p_big = np.concatenate([pair_lists[0], pair_lists[0][:2]])
+    systems[0].apply_w(p_big)
+    with pytest.raises(bse.BseError) as e:
+        plan.run()
+    assert e.value.code == bse.BSE_ERR_STATE
+    plan.close()

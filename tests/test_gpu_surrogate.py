@@ -1,7 +1,10 @@
 """Surrogate plumbing on the GPU: the sample features and targets equal the
-oracle's source potential and W^pol, and the surrogate W-action returns
-q + s*net(x) for accepted pairs and the propagation's W for rejected ones.
-A network trained on three small molecules beats W = q on a fourth."""
+oracle's source potential and W^pol; the surrogate W-action's judge (the
+propagation of a spread sample of the pairs) measures the network's error
+exactly and rejects a network above the bar, so that every returned W is
+then the propagation's, while under a loose bar the kept rows equal the
+network's prediction.  A network trained on three small molecules beats
+W = q on a fourth."""
 import numpy as np
 import pytest
 
@@ -38,28 +41,38 @@ def test_samples_and_fallback():
     th = t.cpu().numpy().astype(np.float64) * s_np[:, None]
     say("target rel err vs oracle W^pol", rel(th, wp_o).max())
     assert rel(th, wp_o).max() < 1e-3
-    # surrogate W-action with an untrained network and fallback
+    # surrogate W-action judged by the propagation, with an untrained network
     net = bse.Fno(16, cin=3, width=8, modes=4, layers=2, max_batch=4, seed=3)
     w = torch.empty((B, spec.ng), dtype=torch.float64, device="cuda")
-    acc = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), fallback=True)
     y = torch.empty((B, spec.ng), dtype=torch.float32, device="cuda")
     net.forward(B, x.data_ptr(), y.data_ptr())
-    wh = w.cpu().numpy()
-    w_prop = S.apply_w(pairs)
     pred = xh[:, 0] * s_np[:, None] + s_np[:, None] * y.cpu().numpy().astype(np.float64)
-    say("accepted", acc)
+    w_prop = S.apply_w(pairs)
+    err_true = rel(pred, w_prop)
+    # a 1e-3 bar: the judge measures errors far above it and rejects the
+    # network, so every row is the propagation's W
+    acc, jerr = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), tol=1e-3, n_judge=2)
+    say("tol 1e-3: accepted", acc, "judged errors", jerr, "true errors", err_true)
+    assert not acc.any()
+    jidx = [(2 * k + 1) * B // 4 for k in range(2)]
+    assert np.allclose(jerr, err_true[jidx], rtol=1e-5)
+    assert np.all(jerr > 1e-3)
+    # batch composition changes the FP32 rounding of the packed transforms
+    assert rel(w.cpu().numpy(), w_prop).max() < 1e-5
+    # no judge: nothing can be accepted
+    acc0, _ = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), tol=1.0, n_judge=0)
+    assert not acc0.any() and rel(w.cpu().numpy(), w_prop).max() < 1e-5
+    # a bar above every judged error: the unjudged predictions that pass
+    # their sign check are kept (rows equal the prediction), the judged pairs
+    # and the others hold the propagation's W
+    acc2, jerr2 = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), tol=1e3, n_judge=2)
+    say("tol 1e3: accepted", acc2)
+    wh = w.cpu().numpy()
+    assert not acc2[jidx].any()
     for k in range(B):
-        if acc[k]:
-            assert rel(wh[k], pred[k]) < 1e-6
-        else:
-            # the propagation of the rejected pairs alone: pairs share packed
-            # Poisson transforms two at a time, so batch composition changes
-            # the FP32 rounding (not the result beyond it)
-            assert rel(wh[k], w_prop[k]) < 1e-6
-    # without fallback every row is the network's
-    acc2 = bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), fallback=False)
-    assert np.array_equal(acc, acc2)
-    assert rel(w.cpu().numpy(), pred).max() < 1e-6
+        assert rel(wh[k], pred[k] if acc2[k] else w_prop[k]) < 1e-5
+    with pytest.raises(bse.BseError):
+        bse.apply_w_surrogate(S, net, pairs, w.data_ptr(), tol=1e-3, n_judge=B + 1)
 
 
 @pytest.mark.timeout(300)
