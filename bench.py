@@ -368,6 +368,8 @@ def main():
                          "build_a: bse_build_A + bse_spectrum per step")
     ap.add_argument("--slice", type=int, default=21, help="pairs per slice step")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--launch-order", type=int, default=-1,
+                    help="workgroup order of the x and y-line passes (bse_set_launch_order); -1 library default")
     ap.add_argument("--n-steps", type=int, default=0,
                     help="propagation steps per solve (0: the workload's); only for counter runs, "
                          "whose per-launch figures do not depend on it")
@@ -452,6 +454,8 @@ def main():
     stream = torch.cuda.current_stream()
     S.set_stream(stream.cuda_stream)
     S.set_orbitals(sysd["phi"], sysd["eps"])
+    if args.launch_order >= 0:
+        S.set_launch_order(args.launch_order)
     n_exc = 20
 
     if step_kind == "slice":

@@ -368,6 +368,18 @@ int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, doubl
  * Poisson, exciton states).  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
+/* Workgroup order of the propagation's x pass (bit 0 of order) and y-line
+ * pass (bit 1); results do not depend on it.  Bit clear: the fields of a
+ * tile consecutive on a 2-D grid, so that they run close together; bit set:
+ * a 1-D grid renumbered so that each of the eight XCDs (each with its own
+ * L2) walks a contiguous range of (tile, field), so that the fields of a
+ * tile share one L2 for its unperturbed orbitals and phase tables.
+ * Default 1 (measured at 112^3, 21 pairs: the grouped x pass fetches 1.02x
+ * its algorithmic bytes instead of 1.52x and runs 1 % faster; the grouped
+ * y-line pass, 7 % slower, stays in the default order).  Errors:
+ * BSE_ERR_ARG outside 0..3. */
+bse_status bse_set_launch_order(bse_system* sys, int32_t order);
+
 /* Kernel schedule of bse_spectrum's Lanczos iteration (the arithmetic and
  * the convergence checks are the same either way; results agree to
  * rounding).  0 (default): for n_o n_c <= 384 every step up to the next

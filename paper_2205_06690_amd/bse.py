@@ -37,7 +37,7 @@ EXPORTS = (
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
     "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
     "bse_chebyshev_spectrum_noalloc", "bse_fno_set_mix_path", "bse_batch_plan_create",
-    "bse_batch_plan_run", "bse_batch_plan_destroy",
+    "bse_batch_plan_run", "bse_batch_plan_destroy", "bse_set_launch_order",
 )
 
 
@@ -101,6 +101,7 @@ def _load():
     lib.bse_kernel_times.restype = C.c_int32
     lib.bse_set_timing.argtypes = [P, C.c_int32]
     lib.bse_set_lanczos_path.argtypes = [P, C.c_int32]
+    lib.bse_set_launch_order.argtypes = [P, C.c_int32]
     lib.bse_apply_W_batch.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
                                       C.c_int32]
     lib.bse_batch_plan_create.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
@@ -426,6 +427,10 @@ class System:
         v = C.c_double()
         _check(LIB.bse_boundary_potential(self._h, C.byref(v)))
         return v.value
+
+    def set_launch_order(self, order: int):
+        """bse_set_launch_order: bit 0 XCD-grouped x pass, bit 1 XCD-grouped y-line pass."""
+        _check(LIB.bse_set_launch_order(self._h, int(order)))
 
     def set_lanczos_path(self, path):
         """0: single-workgroup launches up to each convergence check where A

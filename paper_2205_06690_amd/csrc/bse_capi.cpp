@@ -196,6 +196,7 @@ struct bse_system {
   int lz_path = 0;   // 0 fused launches where A fits, 1 a launch per operation
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
+  int launch_order = 1;           // workgroup order bits of the x (1) and y-line (2) passes (bse_set_launch_order)
   hipStream_t own_stream = nullptr;
   // surrogate descriptors and buffers
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
@@ -414,6 +415,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pe.dt = (T)s->cfg.dt;
     pe.L = L;
     pe.mode = PX_ETA0;
+    pe.order = s->launch_order & 1;
     HIPC(launch_prop_x<T>(s->n, pe, L, st, s->tune_tc));
     PropYZArgs<T> pze{};
     pze.d = hnext;
@@ -421,6 +423,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pze.kph = tb.kph.as<C>();
     pze.L = L;
     pze.density = 0;
+    pze.order = (s->launch_order >> 1) & 1;
     HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
     // perturbed set
     PropXArgs<T> px{};
@@ -435,6 +438,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     px.dt = (T)s->cfg.dt;
     px.L = L;
     px.mode = half ? PX_HALF : PX_FULL;
+    px.order = s->launch_order & 1;
     auto* t1 = s->timer.slot("prop_x", 1);
     const LaunchEvents e1{t1 ? t1->first : nullptr, t1 ? t1->second : nullptr};
     HIPC(launch_prop_x<T>(s->n, px, B, st, s->tune_tc, t1 ? &e1 : nullptr));
@@ -446,6 +450,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pz.dens = s->dens.as<T>();
     pz.L = L;
     pz.density = 1;
+    pz.order = (s->launch_order >> 1) & 1;
     const bool split = prop_yz_split<T>(s->n);
     auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
     auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
@@ -1972,6 +1977,15 @@ bse_status bse_set_timing(bse_system* s, int32_t enable) {
   s->timer.on = enable != 0;
   s->timer.level = enable;
   s->timer.reset();
+  API_END
+}
+
+bse_status bse_set_launch_order(bse_system* s, int32_t order) {
+  API_BEGIN
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (order < 0 || order > 3) fail(BSE_ERR_ARG, "bse_set_launch_order: order 0..3");
+  HIPC(hipStreamSynchronize(s->stream));
+  s->launch_order = order;
   API_END
 }
 

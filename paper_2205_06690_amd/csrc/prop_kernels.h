@@ -20,6 +20,8 @@ template <typename T> struct PropXArgs {
   T dt;
   int L;
   int mode;
+  int order;           // workgroup order: 0 field fastest on a 2-D grid, 1 XCD-grouped (see launch_order)
+  int nf;              // fields (or pairs) of the launch; set by the launcher
 };
 
 template <typename T> struct PropYZArgs {
@@ -30,6 +32,8 @@ template <typename T> struct PropYZArgs {
   T* dens;
   int L;
   int density;
+  int order;           // workgroup order of the y-line pass, as PropXArgs::order
+  int nf;              // fields (or pairs) of the launch; set by the launcher
 };
 
 template <typename T> struct PoisArgs {

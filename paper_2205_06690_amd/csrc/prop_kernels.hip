@@ -60,6 +60,32 @@ __device__ __forceinline__ void kinetic_x_tile(cplx<T>* s, const cplx<T>* __rest
 // stage B runs through LDS; stage C reads its N1 slots back and the results
 // go straight to HBM.  The pair variant keeps u_b in registers across the L
 // orbitals and has the next orbital's loads in flight during the transform.
+// The (field, tile) of a workgroup.  Order 0: a 2-D grid (fields, tiles),
+// field fastest, so that the fields of one tile run close together.  Order
+// 1: a 1-D grid renumbered so that XCD x (workgroup ids are dealt round-robin
+// to the eight XCDs, x = id mod 8) walks its own contiguous range of
+// (tile, field) with the field fastest: the fields of a tile then share one
+// XCD's L2 for the tile's shared operands (the unperturbed orbitals, the
+// phase tables) instead of each of the eight L2s fetching them.
+__device__ __forceinline__ bool field_tile(int order, int nf, int ntile, int& f, int& tile) {
+  if (order == 0) {
+    f = blockIdx.x;
+    tile = blockIdx.y;
+    return true;
+  }
+  const unsigned id = blockIdx.x, per = gridDim.x >> 3;
+  const unsigned v = (id & 7u) * per + (id >> 3);
+  if (v >= (unsigned)nf * (unsigned)ntile) return false;
+  f = (int)(v % (unsigned)nf);
+  tile = (int)(v / (unsigned)nf);
+  return true;
+}
+inline dim3 field_tile_grid(int order, int nf, int ntile) {
+  if (order == 0) return dim3(nf, ntile);
+  const unsigned n = (unsigned)nf * (unsigned)ntile;
+  return dim3(8 * ((n + 7) / 8));
+}
+
 template <int N, int TC, typename T, bool ETA>
 __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   using C = cplx<T>;
@@ -70,9 +96,11 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   constexpr int IT = TC * N2 / NTH;
   static_assert(TC * N2 % NTH == 0, "work items must fill the block");
   const size_t ng = (size_t)N * N * N;
-  // grid: (fields or pairs, tiles) with the field fastest, so that the blocks
-  // of one tile run close together and share its H and phase tiles in L2
-  const int c0 = blockIdx.y * TC;
+  // the blocks of one tile run close together and share its H and phase
+  // tiles in L2 (field_tile)
+  int fb, tile;
+  if (!field_tile(a.order, a.nf, N * N / TC, fb, tile)) return;
+  const int c0 = tile * TC;
   const int tid = threadIdx.x;
   C* tws = s + N * TC;
   stage_tables<N>(tws, a.tw, a.kph, tid, NTH);
@@ -107,7 +135,7 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   };
   auto mul = [kp](int, C v, int k) { return cmul(v, kp[k]); };
   if (ETA) {
-    const size_t fo = (size_t)blockIdx.x * ng;
+    const size_t fo = (size_t)fb * ng;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       C v[N1];
@@ -130,7 +158,7 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
     }
     return;
   }
-  const int b = blockIdx.x;
+  const int b = fb;
   const bool half = a.mode == PX_HALF;
   const T cu = half ? (T)0.5 * a.dt : a.dt;
   const C* __restrict__ ptab = half ? a.ph : a.pf;
@@ -358,7 +386,9 @@ __global__ void __launch_bounds__(PY_NT) k_prop_y(PropYZArgs<T> a) {
   constexpr int TZ = PY_TZ, E = N * TZ, PER = E / PY_NT;
   static_assert(N % TZ == 0 && E % PY_NT == 0, "tiles must divide the grid");
   const size_t ng = (size_t)N * N * N;
-  const int tid = threadIdx.x, b = blockIdx.x, tile = blockIdx.y;
+  int b, tile;
+  if (!field_tile(a.order, a.nf, N * (N / TZ), b, tile)) return;
+  const int tid = threadIdx.x;
   const int x = tile / (N / TZ), z0 = (tile % (N / TZ)) * TZ;
   const size_t off = (size_t)x * N * N + z0;
   C* tws = s + N * PY_ES;
@@ -1048,12 +1078,14 @@ struct Launch {
     if constexpr (!x_valid<N, TC>()) {
       return hipErrorInvalidValue;
     } else {
-      dim3 grid(F, N * N / TC);
+      PropXArgs<T> b = a;
+      b.nf = F;
+      const dim3 grid = field_tile_grid(a.order, F, N * N / TC);
       size_t sm = x_lds<N, TC, T>();
       if (a.mode == PX_ETA0)
-        go(k_prop_x<N, TC, T, true>, grid, dim3(256), sm, st, ev, a);
+        go(k_prop_x<N, TC, T, true>, grid, dim3(256), sm, st, ev, b);
       else
-        go(k_prop_x<N, TC, T, false>, grid, dim3(256), sm, st, ev, a);
+        go(k_prop_x<N, TC, T, false>, grid, dim3(256), sm, st, ev, b);
       return hipGetLastError();
     }
   }
@@ -1085,11 +1117,13 @@ struct Launch {
       const size_t smz = sizeof(cplx<T>) * ((size_t)PZ_TL * (N + 1) + 2 * N);
       const size_t smy = sizeof(cplx<T>) * ((size_t)N * PY_ES + 2 * N);
       go(k_prop_z<N, T>, dim3(N * N / PZ_TL, F), dim3(256), smz, st, ev, a);
-      const dim3 gy(nb, N * (N / PY_TZ));
+      PropYZArgs<T> ay = a;
+      ay.nf = nb;
+      const dim3 gy = field_tile_grid(a.order, nb, N * (N / PY_TZ));
       if (a.density)
-        go(k_prop_y<N, T, true>, gy, dim3(PY_NT), smy, st, ev2, a);
+        go(k_prop_y<N, T, true>, gy, dim3(PY_NT), smy, st, ev2, ay);
       else
-        go(k_prop_y<N, T, false>, gy, dim3(PY_NT), smy, st, ev2, a);
+        go(k_prop_y<N, T, false>, gy, dim3(PY_NT), smy, st, ev2, ay);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;

@@ -101,3 +101,26 @@ def test_lanczos_at_the_single_workgroup_limit(n_o, n_c):
     assert np.abs(om0 - w_dense).max() < 1e-9 * scale
     assert np.abs(om1 - w_dense).max() < 1e-9 * scale
     assert np.allclose(d0, d1, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.timeout(300)
+def test_launch_order_does_not_change_results():
+    """The XCD-grouped workgroup order of the x and y-line passes (order 3)
+    gives W bit for bit equal to the plain order (0), on a 64^3 grid (plane pass) and
+    on the 112^3 grid (z and y line passes), both precisions at 112^3."""
+    import dataclasses
+    from paper_2205_06690_amd import bse, inputs
+    cases = [(dataclasses.replace(inputs.CONFIGS["mid64"], n_steps=30), bse.BSE_MIXED),
+             (dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=20), bse.BSE_MIXED),
+             (dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=20), bse.BSE_FP64)]
+    for spec, prec in cases:
+        sysd = inputs.make_system(spec)
+        pairs = inputs.ij_pairs(spec)[-5:]
+        res = []
+        for order in (0, 3):
+            s = gpu_system(spec, sysd, prec, max_batch=len(pairs))
+            s.set_launch_order(order)
+            res.append(s.apply_w(pairs))
+            s.close()
+        say(f"launch order {spec.n}^3 precision {prec}: max|dW| {np.abs(res[0] - res[1]).max():.1e}")
+        assert np.array_equal(res[0], res[1])
