@@ -368,6 +368,13 @@ int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, doubl
  * Poisson, exciton states).  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
+/* Kernel schedule of the y and z factors of the kinetic step on grids whose
+ * y-z plane fills most of the LDS (112^3 in mixed precision): 0 (default)
+ * one pass over whole planes with the lines held in registers; 1 a z-line
+ * pass and a y-line pass (one more HBM pass).  Results agree to FP32
+ * rounding.  Errors: BSE_ERR_ARG for other values. */
+bse_status bse_set_yz_schedule(bse_system* sys, int32_t schedule);
+
 /* Workgroup order of the propagation's x pass (bit 0 of order) and y-line
  * pass (bit 1); results do not depend on it.  Bit clear: the fields of a
  * tile consecutive on a 2-D grid, so that they run close together; bit set:

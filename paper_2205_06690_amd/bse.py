@@ -38,6 +38,7 @@ EXPORTS = (
     "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
     "bse_chebyshev_spectrum_noalloc", "bse_fno_set_mix_path", "bse_batch_plan_create",
     "bse_batch_plan_run", "bse_batch_plan_destroy", "bse_set_launch_order",
+    "bse_set_yz_schedule",
 )
 
 
@@ -102,6 +103,7 @@ def _load():
     lib.bse_set_timing.argtypes = [P, C.c_int32]
     lib.bse_set_lanczos_path.argtypes = [P, C.c_int32]
     lib.bse_set_launch_order.argtypes = [P, C.c_int32]
+    lib.bse_set_yz_schedule.argtypes = [P, C.c_int32]
     lib.bse_apply_W_batch.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
                                       C.c_int32]
     lib.bse_batch_plan_create.argtypes = [C.c_int32, C.POINTER(P), ip, C.POINTER(ip), C.POINTER(P),
@@ -431,6 +433,10 @@ class System:
     def set_launch_order(self, order: int):
         """bse_set_launch_order: bit 0 XCD-grouped x pass, bit 1 XCD-grouped y-line pass."""
         _check(LIB.bse_set_launch_order(self._h, int(order)))
+
+    def set_yz_schedule(self, schedule: int):
+        """bse_set_yz_schedule: 0 one register-line plane pass, 1 two line passes."""
+        _check(LIB.bse_set_yz_schedule(self._h, int(schedule)))
 
     def set_lanczos_path(self, path):
         """0: single-workgroup launches up to each convergence check where A

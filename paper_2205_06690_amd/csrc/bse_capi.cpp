@@ -197,6 +197,7 @@ struct bse_system {
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
   int launch_order = 1;           // workgroup order bits of the x (1) and y-line (2) passes (bse_set_launch_order)
+  int yz_schedule = 0;            // 0 one register-line plane pass where available, 1 line passes
   hipStream_t own_stream = nullptr;
   // surrogate descriptors and buffers
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
@@ -424,6 +425,8 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pze.L = L;
     pze.density = 0;
     pze.order = (s->launch_order >> 1) & 1;
+    const bool fused = s->yz_schedule == 0 && prop_yz_fused<T>(s->n);
+    pze.fused = fused ? 1 : 0;
     HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
     // perturbed set
     PropXArgs<T> px{};
@@ -451,7 +454,8 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pz.L = L;
     pz.density = 1;
     pz.order = (s->launch_order >> 1) & 1;
-    const bool split = prop_yz_split<T>(s->n);
+    pz.fused = fused ? 1 : 0;
+    const bool split = !fused && prop_yz_split<T>(s->n);
     auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
     auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
     const LaunchEvents e2{t2 ? t2->first : nullptr, t2 ? t2->second : nullptr};
@@ -1977,6 +1981,15 @@ bse_status bse_set_timing(bse_system* s, int32_t enable) {
   s->timer.on = enable != 0;
   s->timer.level = enable;
   s->timer.reset();
+  API_END
+}
+
+bse_status bse_set_yz_schedule(bse_system* s, int32_t schedule) {
+  API_BEGIN
+  if (!s) fail(BSE_ERR_ARG, "null system");
+  if (schedule != 0 && schedule != 1) fail(BSE_ERR_ARG, "bse_set_yz_schedule: schedule 0 or 1");
+  HIPC(hipStreamSynchronize(s->stream));
+  s->yz_schedule = schedule;
   API_END
 }
 

@@ -34,6 +34,7 @@ template <typename T> struct PropYZArgs {
   int density;
   int order;           // workgroup order of the y-line pass, as PropXArgs::order
   int nf;              // fields (or pairs) of the launch; set by the launcher
+  int fused;           // 1: the register-line plane pass where prop_yz_fused(n) (one pass for y and z)
 };
 
 template <typename T> struct PoisArgs {
@@ -99,6 +100,8 @@ template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, i
                                                 const LaunchEvents* ev = nullptr,
                                                 const LaunchEvents* ev2 = nullptr);
 template <typename T> bool prop_yz_split(int n);
+// grids where the y and z factors can run as one register-line plane pass
+template <typename T> bool prop_yz_fused(int n);
 template <typename T> hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_stoch_orbitals(const double* phi, const signed char* xi, int L, int n_occ,

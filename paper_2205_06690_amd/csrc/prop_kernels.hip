@@ -442,6 +442,199 @@ __global__ void __launch_bounds__(PY_NT) k_prop_y(PropYZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// prop_yz_reg: the y and z factors of exp(-iT dt) on a whole y-z plane in one
+// HBM pass where the plane fills most of the LDS (112^3 in FP32), plus the
+// induced density as in prop_yz.  A line of N = 16 R points lives in the
+// registers of 16 lanes of one row (lane j holds the points 16 j1 + j, j1 <
+// R).  Its transform is the four-step factorisation with the R-point DFTs
+// inside each lane and the 16-point DFTs across the 16 lanes as radix-2
+// butterflies on cross-lane moves (decimation in frequency forward, leaving
+// lane j with frequency k1 + R rev4(j); decimation in time back), the
+// kinetic phase applied in between.  The LDS holds the plane only to turn
+// z-lines into y-lines and back: three barriers per field, the next field's
+// loads in flight during the transforms.  One block per CU.
+// ---------------------------------------------------------------------------
+constexpr int YZR_NT = 896;   // 56 rows of 16 lanes: two lines of each plane per row at N = 112
+
+// the value of lane (l ^ H) of the same 16-lane row (H = 1, 2, 4, 8): DPP
+// quad permutations for 1 and 2, the row rotation by 8 for 8, and a
+// ds_swizzle in bit-mask mode (lane l reads lane l ^ 4) for 4
+template <int H> __device__ __forceinline__ float xlane(float v) {
+  const int iv = __builtin_bit_cast(int, v);
+  int r;
+  if constexpr (H == 1) {
+    r = __builtin_amdgcn_mov_dpp(iv, 0xB1, 0xF, 0xF, false);     // quad_perm(1, 0, 3, 2)
+  } else if constexpr (H == 2) {
+    r = __builtin_amdgcn_mov_dpp(iv, 0x4E, 0xF, 0xF, false);     // quad_perm(2, 3, 0, 1)
+  } else if constexpr (H == 8) {
+    r = __builtin_amdgcn_mov_dpp(iv, 0x128, 0xF, 0xF, false);    // row_ror:8
+  } else {
+    r = __builtin_amdgcn_ds_swizzle(iv, 0x1F | (4 << 10));      // and 0x1f, or 0, xor 4
+  }
+  return __builtin_bit_cast(float, r);
+}
+template <int H> __device__ __forceinline__ float2 xlane2(float2 v) {
+  return make_float2(xlane<H>(v.x), xlane<H>(v.y));
+}
+
+// One radix-2 stage of span H across the row, the same operations on every
+// lane.  Decimation in frequency: the lower lane of a pair keeps a + b, the
+// upper one (a - b) w, w = W_{2H}^(j mod H): t = other + sg mine, then t we
+// (sg = +1, we = 1 on the lower lane; sg = -1, we = w on the upper one).
+template <int H, int R>
+__device__ __forceinline__ void xstage_fwd(float2 (&v)[R], float sg, float2 we) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float2 o = xlane2<H>(v[k]);
+    v[k] = cmul(make_float2(fmaf(sg, v[k].x, o.x), fmaf(sg, v[k].y, o.y)), we);
+  }
+}
+// Its inverse without the factor 1/2, a = A + B conj(w), b = A - B conj(w):
+// each lane scales its own value by m (1 on the lower lane, conj(w) on the
+// upper one), then new = other + sg mine.
+template <int H, int R>
+__device__ __forceinline__ void xstage_inv(float2 (&v)[R], float sg, float2 m) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float2 u = cmul(v[k], m);
+    const float2 o = xlane2<H>(u);
+    v[k] = make_float2(fmaf(sg, u.x, o.x), fmaf(sg, u.y, o.y));
+  }
+}
+
+// per-lane constants of the four cross-lane stages
+struct XConst {
+  float s8, s4, s2, s1;            // +1 on the lower lane of the stage's pairs, -1 on the upper
+  float2 w8, w4, w2;               // the forward twiddle on upper lanes, 1 on lower ones
+};
+
+// exp(-i k^2 dt/2) along one line held by a row (1/N of the inverse in kp)
+template <int N>
+__device__ __forceinline__ void kin_line_reg(float2 (&v)[N / 16], int j, int rj, const float2* tw,
+                                             const float2* kp, const XConst& xc) {
+  constexpr int R = N / 16;
+  Dft<R, -1, float2>::run(v);
+#pragma unroll
+  for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], tw[j * k1]);
+  const float2 one = make_float2(1.f, 0.f);
+  xstage_fwd<8>(v, xc.s8, xc.w8);
+  xstage_fwd<4>(v, xc.s4, xc.w4);
+  xstage_fwd<2>(v, xc.s2, xc.w2);
+  xstage_fwd<1>(v, xc.s1, one);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) v[k1] = cmul(v[k1], kp[k1 + R * rj]);
+  xstage_inv<1>(v, xc.s1, one);
+  xstage_inv<2>(v, xc.s2, make_float2(xc.w2.x, -xc.w2.y));
+  xstage_inv<4>(v, xc.s4, make_float2(xc.w4.x, -xc.w4.y));
+  xstage_inv<8>(v, xc.s8, make_float2(xc.w8.x, -xc.w8.y));
+#pragma unroll
+  for (int k1 = 1; k1 < R; ++k1) v[k1] = cmulc(v[k1], tw[j * k1]);
+  Dft<R, +1, float2>::run(v);
+}
+
+template <int N, bool DENS>
+__global__ void __launch_bounds__(YZR_NT) k_prop_yz_reg(PropYZArgs<float> a) {
+  using C = float2;
+  constexpr int R = N / 16, G = YZR_NT / 16, LPG = N / G, S = N + 1;
+  static_assert(N % 16 == 0 && N % G == 0, "rows of 16 lanes must tile the plane");
+  extern __shared__ unsigned char smem_raw[];
+  C* pl = reinterpret_cast<C*>(smem_raw);          // plane [N][S]
+  C* tws = pl + N * S;                              // tw[N], then kph[N]
+  // the density sums of the pair variant, each thread's own slots (no
+  // sharing, no barriers): [LPG R][YZR_NT]
+  float* accl = reinterpret_cast<float*>(tws + 2 * N);
+  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  const int x = blockIdx.x, b = blockIdx.y;
+  const size_t ng = (size_t)N * N * N;
+  const size_t off = (size_t)x * N * N;
+  stage_tables<N>(tws, a.tw, a.kph, tid, YZR_NT);
+  const int rj = ((j & 1) << 3) | ((j & 2) << 1) | ((j & 4) >> 1) | ((j & 8) >> 3);
+  // z-layout element (q, j1) of the plane: y = g + G q, z = 16 j1 + j
+  const int zb = g * N + j;
+  auto zo = [&](int q, int j1) { return zb + G * N * q + 16 * j1; };
+  const int nf = DENS ? a.L : 1;
+  const size_t f0 = DENS ? (size_t)b * a.L : (size_t)b;
+  C dr[LPG][R];
+  {
+    const C* src = a.d + f0 * ng + off;
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) dr[q][j1] = src[zo(q, j1)];
+  }
+  if (DENS) {
+#pragma unroll
+    for (int e = 0; e < LPG * R; ++e) accl[e * YZR_NT + tid] = 0.f;
+  }
+  __syncthreads();   // tables staged
+  const C* tw = tws;
+  const C* kp = tws + N;
+  XConst xc;
+  {
+    const C one = make_float2(1.f, 0.f);
+    xc.s8 = (j & 8) ? -1.f : 1.f;
+    xc.s4 = (j & 4) ? -1.f : 1.f;
+    xc.s2 = (j & 2) ? -1.f : 1.f;
+    xc.s1 = (j & 1) ? -1.f : 1.f;
+    xc.w8 = (j & 8) ? tw[(j & 7) * R] : one;
+    xc.w4 = (j & 4) ? tw[(j & 3) * 2 * R] : one;
+    xc.w2 = (j & 2) ? tw[(j & 1) * 4 * R] : one;
+  }
+  for (int l = 0; l < nf; ++l) {
+    C* d = a.d + (f0 + l) * ng + off;
+    const C* h = DENS ? a.H + (size_t)l * ng + off : nullptr;
+    __syncthreads();   // the previous field's z lines have left the LDS
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) pl[(g + G * q) * S + 16 * j1 + j] = dr[q][j1];
+    __syncthreads();
+    // y lines: column z = g + G q, lane j holds y = 16 j1 + j
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+      C v[R];
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) v[j1] = pl[(16 * j1 + j) * S + g + G * q];
+      kin_line_reg<N>(v, j, rj, tw, kp, xc);
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) pl[(16 * j1 + j) * S + g + G * q] = v[j1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+      C v[R];
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) v[j1] = pl[(g + G * q) * S + 16 * j1 + j];
+      // this line's unperturbed values and the next field's loads of this
+      // line slot in flight during its transform
+      C hr[R];
+      if (DENS) {
+#pragma unroll
+        for (int j1 = 0; j1 < R; ++j1) hr[j1] = h[zo(q, j1)];
+      }
+      if (l + 1 < nf) {
+        const C* nx = d + ng;
+#pragma unroll
+        for (int j1 = 0; j1 < R; ++j1) dr[q][j1] = nx[zo(q, j1)];
+      }
+      kin_line_reg<N>(v, j, rj, tw, kp, xc);
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) {
+        d[zo(q, j1)] = v[j1];
+        if (DENS) accl[(q * R + j1) * YZR_NT + tid] += hr[j1].x * v[j1].x + hr[j1].y * v[j1].y;
+      }
+    }
+  }
+  if (DENS) {
+    float* dn = a.dens + (size_t)b * ng + off;
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) dn[zo(q, j1)] = 4.f * accl[(q * R + j1) * YZR_NT + tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Coulomb potential v[rho] of real densities, two packed per complex field
 // (the 4 pi/k^2 kernel is real and even, so re and im stay independent).
 // ---------------------------------------------------------------------------
@@ -1109,6 +1302,23 @@ struct Launch {
     return hipGetLastError();
   }
   static constexpr bool yz_split() { return yz_lds<N, T>() > 80 * 1024; }
+  // the register-line plane pass (prop_yz_reg) replaces the two line passes
+  static constexpr bool yz_reg() { return std::is_same<T, float>::value && N == 112; }
+  // the plane, the twiddle and phase tables, the density sums
+  static constexpr size_t yz_reg_lds() {
+    return sizeof(float2) * ((size_t)N * (N + 1) + 2 * N) + sizeof(float) * (size_t)N * N;
+  }
+  static hipError_t prop_yz_reg(const PropYZArgs<T>& a, int nb, hipStream_t st, const LaunchEvents* ev) {
+    if constexpr (yz_reg()) {
+      if (a.density)
+        go(k_prop_yz_reg<N, true>, dim3(N, nb), dim3(YZR_NT), yz_reg_lds(), st, ev, a);
+      else
+        go(k_prop_yz_reg<N, false>, dim3(N, nb), dim3(YZR_NT), yz_reg_lds(), st, ev, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   // the two line passes: ev times the z pass, ev2 the y pass
   static hipError_t prop_zy(const PropYZArgs<T>& a, int nb, hipStream_t st, const LaunchEvents* ev,
                             const LaunchEvents* ev2) {
@@ -1131,6 +1341,7 @@ struct Launch {
   }
   static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt, const LaunchEvents* ev,
                             const LaunchEvents* ev2) {
+    if (a.fused && yz_reg()) return prop_yz_reg(a, nb, st, ev);
     if constexpr (yz_split()) return prop_zy(a, nb, st, ev, ev2);
     if (nt == 0) nt = yz_threads<N>();
     switch (nt) {
@@ -1192,6 +1403,12 @@ struct Launch {
       (void)hipFuncSetAttribute((const void*)k_poisson_yz_inv<N, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, smp);
     }
     (void)hipFuncSetAttribute((const void*)k_poisson_x<N, TC, T>, hipFuncAttributeMaxDynamicSharedMemorySize, smx);
+    if constexpr (yz_reg()) {
+      (void)hipFuncSetAttribute((const void*)k_prop_yz_reg<N, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)yz_reg_lds());
+      (void)hipFuncSetAttribute((const void*)k_prop_yz_reg<N, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)yz_reg_lds());
+    }
   }
 };
 
@@ -1244,6 +1461,10 @@ bool prop_yz_split(int n) {
     case 112: return Launch<112, T>::yz_split();
     default: return false;
   }
+}
+template <typename T>
+bool prop_yz_fused(int n) {
+  return n == 112 && Launch<112, T>::yz_reg();
 }
 template <typename T>
 hipError_t launch_poisson(int n, const PoisArgs<T>& a, hipStream_t st) {
@@ -1397,6 +1618,7 @@ hipError_t launch_to_real(const double* in, size_t n, T* out, hipStream_t st) {
   template hipError_t launch_prop_yz<T>(int, const PropYZArgs<T>&, int, hipStream_t, int,      \
                                         const LaunchEvents*, const LaunchEvents*);               \
   template bool prop_yz_split<T>(int);                                                         \
+  template bool prop_yz_fused<T>(int);                                                         \
   template hipError_t launch_poisson<T>(int, const PoisArgs<T>&, hipStream_t);                 \
   template void configure_kernels<T>(int);                                                     \
   template bool grid_supported<T>(int);                                                        \

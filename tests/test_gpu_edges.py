@@ -124,3 +124,25 @@ def test_launch_order_does_not_change_results():
             s.close()
         say(f"launch order {spec.n}^3 precision {prec}: max|dW| {np.abs(res[0] - res[1]).max():.1e}")
         assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.timeout(300)
+def test_fused_yz_pass_equals_line_passes():
+    """At 112^3 in mixed precision the y and z factors run as one pass over
+    whole planes with the lines in registers; the schedule of two line
+    passes computes the same propagation in another order of rounding: W of
+    a 21-pair slice over 60 steps agrees to FP32 rounding."""
+    import dataclasses
+    from paper_2205_06690_amd import bse, inputs
+    spec = dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=60)
+    sysd = inputs.make_system(spec)
+    pairs = inputs.ij_pairs(spec)[-21:]
+    res = []
+    for sched in (0, 1):
+        s = gpu_system(spec, sysd, bse.BSE_MIXED, max_batch=len(pairs))
+        s.set_yz_schedule(sched)
+        res.append(s.apply_w(pairs))
+        s.close()
+    e = rel(res[0], res[1]).max()
+    say(f"fused y-z pass vs line passes, 21 pairs x 60 steps: max rel W {e:.2e}")
+    assert e < 2e-5
