@@ -369,7 +369,7 @@ def main():
     ap.add_argument("--slice", type=int, default=21, help="pairs per slice step")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--launch-order", type=int, default=-1,
-                    help="workgroup order of the x and y-line passes (bse_set_launch_order); -1 library default")
+                    help="workgroup order of the x, y-line and fused y-z passes (bse_set_launch_order); -1 library default")
     ap.add_argument("--n-steps", type=int, default=0,
                     help="propagation steps per solve (0: the workload's); only for counter runs, "
                          "whose per-launch figures do not depend on it")

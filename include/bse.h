@@ -375,16 +375,17 @@ bse_status bse_set_timing(bse_system* sys, int32_t enable);
  * rounding.  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_yz_schedule(bse_system* sys, int32_t schedule);
 
-/* Workgroup order of the propagation's x pass (bit 0 of order) and y-line
- * pass (bit 1); results do not depend on it.  Bit clear: the fields of a
- * tile consecutive on a 2-D grid, so that they run close together; bit set:
- * a 1-D grid renumbered so that each of the eight XCDs (each with its own
- * L2) walks a contiguous range of (tile, field), so that the fields of a
- * tile share one L2 for its unperturbed orbitals and phase tables.
- * Default 1 (measured at 112^3, 21 pairs: the grouped x pass fetches 1.02x
- * its algorithmic bytes instead of 1.52x and runs 1 % faster; the grouped
- * y-line pass, 7 % slower, stays in the default order).  Errors:
- * BSE_ERR_ARG outside 0..3. */
+/* Workgroup order of the propagation's x pass (bit 0 of order), y-line
+ * pass (bit 1) and fused y-z plane pass (bit 2, the 112^3 FP32 schedule);
+ * results do not depend on it.  Bit clear: a 2-D grid, the fields of a tile
+ * (plane) consecutive so that they run close together; bit set: a 1-D grid
+ * renumbered so that each of the eight XCDs (each with its own L2) walks a
+ * contiguous range of (tile, field), so that the fields of a tile share one
+ * L2 for its unperturbed orbitals and phase tables.  Default 5 (measured at
+ * 112^3, 21 pairs: the grouped x pass fetches 1.02x its algorithmic bytes
+ * instead of 1.52x and runs 1 % faster, the grouped fused pass 1.02x
+ * instead of 1.20x and 1 % faster; the grouped y-line pass, 7 % slower,
+ * stays in the plain order).  Errors: BSE_ERR_ARG outside 0..7. */
 bse_status bse_set_launch_order(bse_system* sys, int32_t order);
 
 /* Kernel schedule of bse_spectrum's Lanczos iteration (the arithmetic and

@@ -431,7 +431,7 @@ class System:
         return v.value
 
     def set_launch_order(self, order: int):
-        """bse_set_launch_order: bit 0 XCD-grouped x pass, bit 1 XCD-grouped y-line pass."""
+        """bse_set_launch_order: bit 0 XCD-grouped x pass, bit 1 y-line pass, bit 2 fused y-z pass."""
         _check(LIB.bse_set_launch_order(self._h, int(order)))
 
     def set_yz_schedule(self, schedule: int):

@@ -196,7 +196,7 @@ struct bse_system {
   int lz_path = 0;   // 0 fused launches where A fits, 1 a launch per operation
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
-  int launch_order = 1;           // workgroup order bits of the x (1) and y-line (2) passes (bse_set_launch_order)
+  int launch_order = 5;           // workgroup order bits: x (1), y-line (2), fused y-z (4) passes (bse_set_launch_order)
   int yz_schedule = 0;            // 0 one register-line plane pass where available, 1 line passes
   hipStream_t own_stream = nullptr;
   // surrogate descriptors and buffers
@@ -424,8 +424,10 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pze.kph = tb.kph.as<C>();
     pze.L = L;
     pze.density = 0;
-    pze.order = (s->launch_order >> 1) & 1;
     const bool fused = s->yz_schedule == 0 && prop_yz_fused<T>(s->n);
+    // bit 1 orders the y-line pass, bit 2 the fused y-z pass
+    const int yz_order = (s->launch_order >> (fused ? 2 : 1)) & 1;
+    pze.order = yz_order;
     pze.fused = fused ? 1 : 0;
     HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
     // perturbed set
@@ -453,7 +455,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pz.dens = s->dens.as<T>();
     pz.L = L;
     pz.density = 1;
-    pz.order = (s->launch_order >> 1) & 1;
+    pz.order = yz_order;
     pz.fused = fused ? 1 : 0;
     const bool split = !fused && prop_yz_split<T>(s->n);
     auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
@@ -1996,7 +1998,7 @@ bse_status bse_set_yz_schedule(bse_system* s, int32_t schedule) {
 bse_status bse_set_launch_order(bse_system* s, int32_t order) {
   API_BEGIN
   if (!s) fail(BSE_ERR_ARG, "null system");
-  if (order < 0 || order > 3) fail(BSE_ERR_ARG, "bse_set_launch_order: order 0..3");
+  if (order < 0 || order > 7) fail(BSE_ERR_ARG, "bse_set_launch_order: order 0..7");
   HIPC(hipStreamSynchronize(s->stream));
   s->launch_order = order;
   API_END

@@ -544,7 +544,16 @@ __global__ void __launch_bounds__(YZR_NT) k_prop_yz_reg(PropYZArgs<float> a) {
   // sharing, no barriers): [LPG R][YZR_NT]
   float* accl = reinterpret_cast<float*>(tws + 2 * N);
   const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
-  const int x = blockIdx.x, b = blockIdx.y;
+  // (plane x, field b): a 2-D grid (planes, fields), or the XCD-grouped
+  // 1-D order with the fields of a plane consecutive on one XCD, so that
+  // they share its L2 for the plane's unperturbed orbitals (field_tile)
+  int x, b;
+  if (a.order == 0) {
+    x = blockIdx.x;
+    b = blockIdx.y;
+  } else if (!field_tile(1, a.nf, N, b, x)) {
+    return;
+  }
   const size_t ng = (size_t)N * N * N;
   const size_t off = (size_t)x * N * N;
   stage_tables<N>(tws, a.tw, a.kph, tid, YZR_NT);
@@ -1310,10 +1319,13 @@ struct Launch {
   }
   static hipError_t prop_yz_reg(const PropYZArgs<T>& a, int nb, hipStream_t st, const LaunchEvents* ev) {
     if constexpr (yz_reg()) {
+      PropYZArgs<T> ar = a;
+      ar.nf = nb;
+      const dim3 gr = a.order ? field_tile_grid(1, nb, N) : dim3(N, nb);
       if (a.density)
-        go(k_prop_yz_reg<N, true>, dim3(N, nb), dim3(YZR_NT), yz_reg_lds(), st, ev, a);
+        go(k_prop_yz_reg<N, true>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
       else
-        go(k_prop_yz_reg<N, false>, dim3(N, nb), dim3(YZR_NT), yz_reg_lds(), st, ev, a);
+        go(k_prop_yz_reg<N, false>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;

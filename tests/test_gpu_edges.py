@@ -105,9 +105,10 @@ def test_lanczos_at_the_single_workgroup_limit(n_o, n_c):
 
 @pytest.mark.timeout(300)
 def test_launch_order_does_not_change_results():
-    """The XCD-grouped workgroup order of the x and y-line passes (order 3)
-    gives W bit for bit equal to the plain order (0), on a 64^3 grid (plane pass) and
-    on the 112^3 grid (z and y line passes), both precisions at 112^3."""
+    """The XCD-grouped workgroup order of the x, y-line and fused y-z passes
+    (order 7) gives W bit for bit equal to the plain order (0), on a 64^3
+    grid (plane pass) and on the 112^3 grid (fused y-z pass in mixed
+    precision, z and y line passes in FP64)."""
     import dataclasses
     from paper_2205_06690_amd import bse, inputs
     cases = [(dataclasses.replace(inputs.CONFIGS["mid64"], n_steps=30), bse.BSE_MIXED),
@@ -117,7 +118,7 @@ def test_launch_order_does_not_change_results():
         sysd = inputs.make_system(spec)
         pairs = inputs.ij_pairs(spec)[-5:]
         res = []
-        for order in (0, 3):
+        for order in (0, 7):
             s = gpu_system(spec, sysd, prec, max_batch=len(pairs))
             s.set_launch_order(order)
             res.append(s.apply_w(pairs))
