@@ -502,10 +502,33 @@ __device__ __forceinline__ void xstage_inv(float2 (&v)[R], float sg, float2 m) {
   }
 }
 
+// The span-2 stage, whose twiddle W_4^(j mod 2) is 1 or -i (forward) and its
+// conjugate 1 or +i (inverse): the product by -i or +i as two selects with a
+// negation instead of a complex multiply (rot: upper lane with j odd).
+template <int R>
+__device__ __forceinline__ void xstage_fwd_q(float2 (&v)[R], float sg, bool rot) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float2 o = xlane2<2>(v[k]);
+    const float2 t = make_float2(fmaf(sg, v[k].x, o.x), fmaf(sg, v[k].y, o.y));
+    v[k] = rot ? make_float2(t.y, -t.x) : t;
+  }
+}
+template <int R>
+__device__ __forceinline__ void xstage_inv_q(float2 (&v)[R], float sg, bool rot) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float2 u = rot ? make_float2(-v[k].y, v[k].x) : v[k];
+    const float2 o = xlane2<2>(u);
+    v[k] = make_float2(fmaf(sg, u.x, o.x), fmaf(sg, u.y, o.y));
+  }
+}
+
 // per-lane constants of the four cross-lane stages
 struct XConst {
   float s8, s4, s2, s1;            // +1 on the lower lane of the stage's pairs, -1 on the upper
-  float2 w8, w4, w2;               // the forward twiddle on upper lanes, 1 on lower ones
+  float2 w8, w4;                   // the forward twiddle on upper lanes, 1 on lower ones
+  bool q2;                         // upper lane of the span-2 stage with j odd: twiddle -i
 };
 
 // exp(-i k^2 dt/2) along one line held by a row (1/N of the inverse in kp)
@@ -519,12 +542,12 @@ __device__ __forceinline__ void kin_line_reg(float2 (&v)[N / 16], int j, int rj,
   const float2 one = make_float2(1.f, 0.f);
   xstage_fwd<8>(v, xc.s8, xc.w8);
   xstage_fwd<4>(v, xc.s4, xc.w4);
-  xstage_fwd<2>(v, xc.s2, xc.w2);
+  xstage_fwd_q(v, xc.s2, xc.q2);
   xstage_fwd<1>(v, xc.s1, one);
 #pragma unroll
   for (int k1 = 0; k1 < R; ++k1) v[k1] = cmul(v[k1], kp[k1 + R * rj]);
   xstage_inv<1>(v, xc.s1, one);
-  xstage_inv<2>(v, xc.s2, make_float2(xc.w2.x, -xc.w2.y));
+  xstage_inv_q(v, xc.s2, xc.q2);
   xstage_inv<4>(v, xc.s4, make_float2(xc.w4.x, -xc.w4.y));
   xstage_inv<8>(v, xc.s8, make_float2(xc.w8.x, -xc.w8.y));
 #pragma unroll
@@ -587,7 +610,7 @@ __global__ void __launch_bounds__(YZR_NT) k_prop_yz_reg(PropYZArgs<float> a) {
     xc.s1 = (j & 1) ? -1.f : 1.f;
     xc.w8 = (j & 8) ? tw[(j & 7) * R] : one;
     xc.w4 = (j & 4) ? tw[(j & 3) * 2 * R] : one;
-    xc.w2 = (j & 2) ? tw[(j & 1) * 4 * R] : one;
+    xc.q2 = (j & 3) == 3;
   }
   for (int l = 0; l < nf; ++l) {
     C* d = a.d + (f0 + l) * ng + off;
