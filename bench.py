@@ -194,17 +194,26 @@ def cpu_parallel_baseline(config: str, spec, pairs, steps: int, procs: int):
 def bench_uneven(args):
     """The uneven batch: 32 synthetic molecules on {32,48,64}^3 grids with
     10-80 wells, N_occ 10-100 and 16-200 pair densities each, L = 10,
-    400 steps, FP32 propagation.  Timed three ways: one system after the
-    other, all systems on their own streams, and all systems captured into
-    one HIP graph launched once.  Prints one JSON line."""
+    400 steps, FP32 propagation.  Timed four ways: one system after the
+    other, all systems on their own streams, all systems captured into one
+    HIP graph inside the call, and the replay of a plan captured once
+    beforehand (the reported value).  The CPU baseline runs the oracle on
+    one pair of the smallest member, and the plan's W of that pair is
+    compared with it.  Prints one JSON line."""
     import torch
     from paper_2205_06690_amd import inputs
     from paper_2205_06690_amd import bse
     specs = inputs.uneven_batch_specs(args.n_systems)
     systems, pairs, pairs_dev, outs = [], [], [], []
+    # the member whose pair the CPU baseline runs: the smallest grid and
+    # occupied space (the oracle finishes its full propagation in seconds)
+    k_cpu = min(range(len(specs)), key=lambda k: (specs[k][0].n, specs[k][0].n_occ))
+    sd_cpu = None
     t_in = time.perf_counter()
     for k, (sp, npair) in enumerate(specs):
         sd = inputs.make_system(sp)
+        if k == k_cpu:
+            sd_cpu = sd
         p = inputs.ia_pairs(sp)[:npair]
         S = bse.System(sp.n, sp.h, sd["v_ext"], n_occ=sp.n_occ, n_stoch=sp.n_stoch, seed=sp.seed,
                        dt=sp.dt, n_steps=sp.n_steps, gamma=sp.gamma_eff,
@@ -267,7 +276,32 @@ def bench_uneven(args):
         "plan_capture_s": round(t_plan_make, 2),
     }
     plan.close()
+    parity_bad = False
+    if not args.no_cpu_baseline:
+        # the oracle on one pair of the smallest member for its whole
+        # propagation; the plan's last replay computed the same pair
+        sp = specs[k_cpu][0]
+        pair = tuple(int(x) for x in pairs[k_cpu][-1])
+        w_o, _, per_solve, t_cpu = cpu_baseline(sp, sd_cpu, pair, sp.n_steps)
+        out["cpu_baseline"] = {
+            "value": round(1.0 / per_solve, 6), "unit": "pair solves/s", "cores": os.cpu_count(),
+            "cpu": _cpu_model(), "kind": "oracle",
+            "sample": f"1 pair of member {k_cpu} ({sp.n}^3, N_occ {sp.n_occ}, the smallest) x all "
+                      f"{sp.n_steps} steps ({t_cpu:.1f}s); the batch's larger members cost more per pair"}
+        w_g = outs[k_cpu][len(pairs[k_cpu]) - 1].cpu().numpy()
+        w_o = w_o.reshape(-1)
+        rel_w = float(np.linalg.norm(w_g - w_o) / np.linalg.norm(w_o))
+        mx = float(np.abs(w_g - w_o).max() / np.abs(w_o).max())
+        out["parity_sample"] = {"system": k_cpu, "pair": list(pair), "steps": sp.n_steps,
+                                "rel_err_W": rel_w, "max_err_W": mx,
+                                "reference": "oracle, full propagation, W from the plan's replay"}
+        parity_bad = not (rel_w <= 1e-3 and mx <= 1e-3)
+    if parity_bad:
+        out["valid"] = False
+        out["invalid_reason"] = "parity sample above the 1e-3 bar"
     print(json.dumps(out), flush=True)
+    if parity_bad:
+        sys.exit(3)
 
 
 def bench_surrogate(args):
@@ -397,6 +431,8 @@ def main():
     ap.add_argument("--loose-tol", type=float, default=0.5,
                     help="a second acceptance bar, loose enough for the network's errors")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--yz-schedule", type=int, default=-1,
+                    help="kernel schedule of the y and z kinetic factors (bse_set_yz_schedule); -1 library default")
     ap.add_argument("--skip", default="", help="comma list of extras to skip (chebyshev, mixed, box)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -456,6 +492,8 @@ def main():
     S.set_orbitals(sysd["phi"], sysd["eps"])
     if args.launch_order >= 0:
         S.set_launch_order(args.launch_order)
+    if args.yz_schedule >= 0:
+        S.set_yz_schedule(args.yz_schedule)
     n_exc = 20
 
     if step_kind == "slice":
