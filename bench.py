@@ -494,6 +494,13 @@ def main():
         S.set_launch_order(args.launch_order)
     if args.yz_schedule >= 0:
         S.set_yz_schedule(args.yz_schedule)
+    if args.autotune:
+        # tile shapes of the propagation passes timed on this system's own
+        # buffers for the batch of the step
+        n_tune = min(args.slice, n_ij) if (args.step or ("slice" if args.config == "paper112" else "")) == "slice" \
+            else n_ij
+        shape = S.autotune(n_tune, os.path.join(os.environ.get("TMPDIR", "/tmp"), "bse_tune.txt"))
+        log(f"[bench] autotuned tile shapes (x tile, plane block) for {n_tune} pairs: {shape}")
     n_exc = 20
 
     if step_kind == "slice":
