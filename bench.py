@@ -400,7 +400,8 @@ def main():
     ap.add_argument("--step", default="", choices=["", "slice", "build_a"],
                     help="slice: W-actions of one pair slice per step (paper112 default); "
                          "build_a: bse_build_A + bse_spectrum per step")
-    ap.add_argument("--slice", type=int, default=21, help="pairs per slice step")
+    ap.add_argument("--slice", type=int, default=42,
+                    help="pairs per slice step (42: five equal slices of the 210 pairs)")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--launch-order", type=int, default=-1,
                     help="workgroup order of the x, y-line and fused y-z passes (bse_set_launch_order); -1 library default")
@@ -413,7 +414,7 @@ def main():
                     help="steps per process of the one-process-per-core oracle sample "
                          "(0 = skip; default 10, 2 at 112^3)")
     ap.add_argument("--cpu-steps", type=int, default=0,
-                    help="oracle steps of the CPU sample (0: 200 at 64^3, 10 at 112^3)")
+                    help="oracle steps of the CPU sample (0: 200 at 64^3, 30 at 112^3)")
     ap.add_argument("--n-systems", type=int, default=32)
     ap.add_argument("--n-train", type=int, default=4096)
     ap.add_argument("--n-mol-train", type=int, default=20,
@@ -474,7 +475,7 @@ def main():
         args.no_parity = True
     step_kind = args.step or ("slice" if args.config == "paper112" else "build_a")
     if args.cpu_steps <= 0:
-        args.cpu_steps = 10 if spec.n >= 112 else min(200, spec.n_steps)
+        args.cpu_steps = 30 if spec.n >= 112 else min(200, spec.n_steps)
     if args.cpu_par_steps < 0:
         args.cpu_par_steps = 2 if spec.n >= 112 else 10
     t_in = time.perf_counter()

@@ -369,10 +369,13 @@ int32_t bse_kernel_times(bse_system* sys, int32_t cap, const char** names, doubl
 bse_status bse_set_timing(bse_system* sys, int32_t enable);
 
 /* Kernel schedule of the y and z factors of the kinetic step on grids whose
- * y-z plane fills most of the LDS (112^3 in mixed precision): 0 (default)
- * one pass over whole planes with the lines held in registers; 1 a z-line
- * pass and a y-line pass (one more HBM pass).  Results agree to FP32
- * rounding.  Errors: BSE_ERR_ARG for other values. */
+ * y-z plane fills most of the LDS (112^3 in mixed precision): 2 (default)
+ * one pass over whole planes, the lines in registers for the 7-point DFTs
+ * and each 16-point DFT (with the kinetic phase and its inverse) in one
+ * lane's registers after a transpose through the wave's own LDS; 0 the
+ * same pass with the 16-point DFTs as butterflies across the 16 lanes of a
+ * row; 1 a z-line pass and a y-line pass (one more HBM pass).  Results
+ * agree to FP32 rounding.  Errors: BSE_ERR_ARG for other values. */
 bse_status bse_set_yz_schedule(bse_system* sys, int32_t schedule);
 
 /* Workgroup order of the propagation's x pass (bit 0 of order), y-line

@@ -435,7 +435,7 @@ class System:
         _check(LIB.bse_set_launch_order(self._h, int(order)))
 
     def set_yz_schedule(self, schedule: int):
-        """bse_set_yz_schedule: 0 register-line plane pass, 1 two line passes, 2 LDS plane pass."""
+        """bse_set_yz_schedule: 2 (default) plane pass, DFT16 per lane; 0 cross-lane DFT16; 1 two line passes."""
         _check(LIB.bse_set_yz_schedule(self._h, int(schedule)))
 
     def set_lanczos_path(self, path):

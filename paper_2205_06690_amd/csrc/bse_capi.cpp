@@ -197,7 +197,7 @@ struct bse_system {
   std::vector<double> wts;
   int tune_tc = 0, tune_nt = 0;   // autotuned x-tile width / plane block size (0 = default)
   int launch_order = 5;           // workgroup order bits: x (1), y-line (2), fused y-z (4) passes (bse_set_launch_order)
-  int yz_schedule = 0;            // 0 one register-line plane pass where available, 1 line passes
+  int yz_schedule = 2;            // where available: 2 plane pass, 16-point DFTs per lane; 0 cross-lane; 1 line passes
   hipStream_t own_stream = nullptr;
   // surrogate descriptors and buffers
   DBuf n0dens, vdev, fx, fy, fscale, fdots, fwpol;
@@ -424,11 +424,11 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pze.kph = tb.kph.as<C>();
     pze.L = L;
     pze.density = 0;
-    const bool fused = s->yz_schedule == 0 && prop_yz_fused<T>(s->n);
+    const bool fused = s->yz_schedule != 1 && prop_yz_fused<T>(s->n);
     // bit 1 orders the y-line pass, bit 2 the fused y-z pass
     const int yz_order = (s->launch_order >> (fused ? 2 : 1)) & 1;
     pze.order = yz_order;
-    pze.fused = fused ? 1 : 0;
+    pze.fused = fused ? (s->yz_schedule == 2 ? 2 : 1) : 0;
     HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
     // perturbed set
     PropXArgs<T> px{};
@@ -456,7 +456,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
     pz.L = L;
     pz.density = 1;
     pz.order = yz_order;
-    pz.fused = fused ? 1 : 0;
+    pz.fused = pze.fused;
     const bool split = !fused && prop_yz_split<T>(s->n);
     auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
     auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
@@ -1989,7 +1989,7 @@ bse_status bse_set_timing(bse_system* s, int32_t enable) {
 bse_status bse_set_yz_schedule(bse_system* s, int32_t schedule) {
   API_BEGIN
   if (!s) fail(BSE_ERR_ARG, "null system");
-  if (schedule != 0 && schedule != 1) fail(BSE_ERR_ARG, "bse_set_yz_schedule: schedule 0 or 1");
+  if (schedule < 0 || schedule > 2) fail(BSE_ERR_ARG, "bse_set_yz_schedule: schedule 0, 1 or 2");
   HIPC(hipStreamSynchronize(s->stream));
   s->yz_schedule = schedule;
   API_END

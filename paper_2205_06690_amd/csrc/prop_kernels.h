@@ -34,7 +34,7 @@ template <typename T> struct PropYZArgs {
   int density;
   int order;           // workgroup order of the y-line pass, as PropXArgs::order
   int nf;              // fields (or pairs) of the launch; set by the launcher
-  int fused;           // 1: the register-line plane pass where prop_yz_fused(n) (one pass for y and z)
+  int fused;           // where prop_yz_fused(n), one pass for y and z: 1 cross-lane DFT16, 2 DFT16 per lane
 };
 
 template <typename T> struct PoisArgs {

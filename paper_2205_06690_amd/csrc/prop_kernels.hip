@@ -667,6 +667,213 @@ __global__ void __launch_bounds__(YZR_NT) k_prop_yz_reg(PropYZArgs<float> a) {
 }
 
 // ---------------------------------------------------------------------------
+// prop_yz_rt: the same plane pass with the 16-point DFTs taken out of the
+// lanes' cross-lane butterflies.  Lines, loads, stores and the 7-point DFTs
+// stay as in prop_yz_reg (16 lanes of a row hold a line, 7 points each);
+// after the 7-point DFTs and their twiddles, the 8 lines a wave holds (4
+// rows x 2 slots) are 56 vectors of 16 points (one per (line, k1)), which
+// go through a scratch area of the wave's own, one vector to a lane: the
+// 16-point DFT, the kinetic phase and the inverse DFT in registers, then
+// back to the lines.  The plane is kept transposed, [z][y], so that a
+// wave's y-lines are the rows it alone reads and writes: its scratch is
+// those rows, and the y half-step needs no block barrier.  Scratch element
+// jj of vector vi sits at slot jj ^ f(vi), f(vi) = (vi ^ (vi >> 4)) mod 16,
+// which keeps the lanes of a wave on distinct banks.  A wave's LDS
+// operations run in program order, so its scratch needs no wait between the
+// writes of one lane and the reads of another, only that the compiler keeps
+// their order (a wave barrier).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rt_swz(int vi) { return (vi ^ (vi >> 4)) & 15; }
+
+template <int N, bool DENS>
+__global__ void __launch_bounds__(YZR_NT) k_prop_yz_rt(PropYZArgs<float> a) {
+  using C = float2;
+  constexpr int R = N / 16, G = YZR_NT / 16, LPG = N / G, S = N + 1;
+  constexpr int NVQ = 4 * R;                        // vectors per wave and slot
+  static_assert(N % 16 == 0 && N % G == 0 && LPG == 2, "two line slots of 16 lanes per row");
+  static_assert(LPG * NVQ <= 64, "one vector per lane");
+  static_assert(NVQ * 16 <= 4 * S, "a slot's vectors fit in the wave's four rows");
+  extern __shared__ unsigned char smem_raw[];
+  C* pl = reinterpret_cast<C*>(smem_raw);           // plane, transposed: [z][y], rows of S
+  C* tws = pl + N * S;                              // tw[N], then kph[N]
+  float* accl = reinterpret_cast<float*>(tws + 2 * N);
+  const int tid = threadIdx.x, g = tid >> 4, j = tid & 15;
+  const int lane = tid & 63, wv = tid >> 6, rr = (tid >> 4) & 3;
+  // this wave's scratch: slot q's vectors in rows 4 wv .. 4 wv + 3 + G q
+  C* scr0 = pl + (4 * wv) * S;
+  C* scr1 = pl + (4 * wv + G) * S;
+  int x, b;
+  if (a.order == 0) {
+    x = blockIdx.x;
+    b = blockIdx.y;
+  } else if (!field_tile(1, a.nf, N, b, x)) {
+    return;
+  }
+  const size_t ng = (size_t)N * N * N;
+  const size_t off = (size_t)x * N * N;
+  stage_tables<N>(tws, a.tw, a.kph, tid, YZR_NT);
+  const int zb = g * N + j;
+  auto zo = [&](int q, int j1) { return zb + G * N * q + 16 * j1; };
+  const int nf = DENS ? a.L : 1;
+  const size_t f0 = DENS ? (size_t)b * a.L : (size_t)b;
+  C dr[LPG][R];
+  {
+    const C* src = a.d + f0 * ng + off;
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) dr[q][j1] = src[zo(q, j1)];
+  }
+  if (DENS) {
+#pragma unroll
+    for (int e = 0; e < LPG * R; ++e) accl[e * YZR_NT + tid] = 0.f;
+  }
+  __syncthreads();   // tables staged
+  const C* tw = tws;
+  const C* kp = tws + N;
+  // the vector a lane transforms: slot vq, frequency vk1 (of row lane & 3)
+  const int vq = lane / NVQ, vloc = lane % NVQ, vk1 = vloc >> 2;
+  const bool vlive = lane < LPG * NVQ;
+  C* vscr = (vq ? scr1 : scr0) + vloc * 16;
+  const int vsw = rt_swz(lane);
+  auto order = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  auto fwd7 = [&](C (&v)[R]) {
+    Dft<R, -1, float2>::run(v);
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], tw[j * k1]);
+  };
+  auto inv7 = [&](C (&v)[R]) {
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) v[k1] = cmulc(v[k1], tw[j * k1]);
+    Dft<R, +1, float2>::run(v);
+  };
+  // vector (q, k1, row rr) is lane (q NVQ + 4 k1 + rr) of the 16-point stage
+  auto xfer_out = [&](C (&v)[LPG][R]) {
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int k1 = 0; k1 < R; ++k1) {
+        const int vl = 4 * k1 + rr;
+        (q ? scr1 : scr0)[vl * 16 + (j ^ rt_swz(q * NVQ + vl))] = v[q][k1];
+      }
+  };
+  auto xfer_in_q = [&](C (&vq_)[R], int q) {
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      const int vl = 4 * k1 + rr;
+      vq_[k1] = (q ? scr1 : scr0)[vl * 16 + (j ^ rt_swz(q * NVQ + vl))];
+    }
+  };
+  auto xfer_in = [&](C (&v)[LPG][R]) {
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int k1 = 0; k1 < R; ++k1) {
+        const int vl = 4 * k1 + rr;
+        v[q][k1] = (q ? scr1 : scr0)[vl * 16 + (j ^ rt_swz(q * NVQ + vl))];
+      }
+  };
+  auto dft16_kin = [&]() {
+    if (vlive) {
+      C y[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) y[jj] = vscr[jj ^ vsw];
+      Dft<16, -1, float2>::run(y);
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) y[k2] = cmul(y[k2], kp[vk1 + R * k2]);
+      Dft<16, +1, float2>::run(y);
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) vscr[jj ^ vsw] = y[jj];
+    }
+  };
+  auto stage16 = [&](C (&v)[LPG][R]) {
+    xfer_out(v);
+    order();
+    dft16_kin();
+    order();
+    xfer_in(v);
+  };
+  for (int l = 0; l < nf; ++l) {
+    C* d = a.d + (f0 + l) * ng + off;
+    const C* h = DENS ? a.H + (size_t)l * ng + off : nullptr;
+    __syncthreads();   // the previous field's scratch is done with the plane
+    // point (y = g + G q, z = 16 j1 + j) to row z, column y
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) pl[(16 * j1 + j) * S + g + G * q] = dr[q][j1];
+    __syncthreads();
+    // y lines: row z = g + G q (this wave's), lane j holds y = 16 j1 + j
+    C v[LPG][R];
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) v[q][j1] = pl[(g + G * q) * S + 16 * j1 + j];
+      fwd7(v[q]);
+    }
+    order();           // the rows are read before they turn into scratch
+    stage16(v);
+    order();
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+      inv7(v[q]);
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) pl[(g + G * q) * S + 16 * j1 + j] = v[q][j1];
+    }
+    __syncthreads();
+    // z lines: column y = g + G q, lane j holds z = 16 j1 + j
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) v[q][j1] = pl[(16 * j1 + j) * S + g + G * q];
+    }
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) fwd7(v[q]);
+    __syncthreads();   // every wave has read its columns: rows turn into scratch
+    xfer_out(v);
+    order();
+    dft16_kin();
+    order();
+    // one slot at a time back from the scratch (fewer live registers); the
+    // next field's loads go out between the slots, in flight during the
+    // second slot's transform and stores
+#pragma unroll
+    for (int q = 0; q < LPG; ++q) {
+      xfer_in_q(v[q], q);
+      C hr[R];
+      if (DENS) {
+#pragma unroll
+        for (int j1 = 0; j1 < R; ++j1) hr[j1] = h[zo(q, j1)];
+      }
+      inv7(v[q]);
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) {
+        d[zo(q, j1)] = v[q][j1];
+        if (DENS) accl[(q * R + j1) * YZR_NT + tid] += hr[j1].x * v[q][j1].x + hr[j1].y * v[q][j1].y;
+      }
+      if (q == 0 && l + 1 < nf) {
+        const C* nx = d + ng;
+#pragma unroll
+        for (int qq = 0; qq < LPG; ++qq)
+#pragma unroll
+          for (int j1 = 0; j1 < R; ++j1) dr[qq][j1] = nx[zo(qq, j1)];
+      }
+    }
+  }
+  if (DENS) {
+    float* dn = a.dens + (size_t)b * ng + off;
+#pragma unroll
+    for (int q = 0; q < LPG; ++q)
+#pragma unroll
+      for (int j1 = 0; j1 < R; ++j1) dn[zo(q, j1)] = 4.f * accl[(q * R + j1) * YZR_NT + tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Coulomb potential v[rho] of real densities, two packed per complex field
 // (the 4 pi/k^2 kernel is real and even, so re and im stay independent).
 // ---------------------------------------------------------------------------
@@ -1345,7 +1552,12 @@ struct Launch {
       PropYZArgs<T> ar = a;
       ar.nf = nb;
       const dim3 gr = a.order ? field_tile_grid(1, nb, N) : dim3(N, nb);
-      if (a.density)
+      if (a.fused == 2) {
+        if (a.density)
+          go(k_prop_yz_rt<N, true>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
+        else
+          go(k_prop_yz_rt<N, false>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
+      } else if (a.density)
         go(k_prop_yz_reg<N, true>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
       else
         go(k_prop_yz_reg<N, false>, gr, dim3(YZR_NT), yz_reg_lds(), st, ev, ar);
@@ -1376,7 +1588,7 @@ struct Launch {
   }
   static hipError_t prop_yz(const PropYZArgs<T>& a, int nb, hipStream_t st, int nt, const LaunchEvents* ev,
                             const LaunchEvents* ev2) {
-    if (a.fused && yz_reg()) return prop_yz_reg(a, nb, st, ev);
+    if (a.fused && yz_reg()) return prop_yz_reg(a, nb, st, ev);   // 1 cross-lane, 2 transposed
     if constexpr (yz_split()) return prop_zy(a, nb, st, ev, ev2);
     if (nt == 0) nt = yz_threads<N>();
     switch (nt) {
@@ -1442,6 +1654,10 @@ struct Launch {
       (void)hipFuncSetAttribute((const void*)k_prop_yz_reg<N, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)yz_reg_lds());
       (void)hipFuncSetAttribute((const void*)k_prop_yz_reg<N, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)yz_reg_lds());
+      (void)hipFuncSetAttribute((const void*)k_prop_yz_rt<N, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)yz_reg_lds());
+      (void)hipFuncSetAttribute((const void*)k_prop_yz_rt<N, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)yz_reg_lds());
     }
   }
