@@ -39,12 +39,43 @@ __global__ void k_products_split(const double* __restrict__ phi, const int* __re
              l[(size_t)k * ng + r]);
 }
 
+// One 32-point step of a wave's 64 x 64 outputs: the A fragments of its four
+// row blocks stay in registers while the B fragments stream, one column block
+// at a time, so that fewer registers are live than with all of B loaded (two
+// blocks per SIMD).  Each accumulator sees the same three products in the same
+// order as in mma_stage.
+template <int P>
+__device__ __forceinline__ void mma_step_bstream(const __bf16 (*Ah)[P], const __bf16 (*Al)[P],
+                                                 const __bf16 (*Bh)[P], const __bf16 (*Bl)[P],
+                                                 int lane, int wm, int wn, f4 (&acc)[4][4], int ko) {
+  const int kk = ko + 8 * (lane >> 4);
+  bf8 fah[4], fal[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = wm * 64 + i * 16 + (lane & 15);
+    fah[i] = *reinterpret_cast<const bf8*>(&Ah[row][kk]);
+    fal[i] = *reinterpret_cast<const bf8*>(&Al[row][kk]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = wn * 64 + j * 16 + (lane & 15);
+    const bf8 fbh = *reinterpret_cast<const bf8*>(&Bh[col][kk]);
+    const bf8 fbl = *reinterpret_cast<const bf8*>(&Bl[col][kk]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh, acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl, acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh, acc[i][j], 0, 0, 0);
+    }
+  }
+}
+
 // part[kc][m][n] = sum over chunk kc of A[m][r] B[n][r], staged KS grid
 // points at a time.  Tile order (with remap): column tile fastest, then row
 // tile, then chunk, renumbered so that each XCD works through a contiguous
 // range and the tiles of one chunk share their row and column panels in L2.
 template <int KS>
-__global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __restrict__ ah,
+__global__ void __launch_bounds__(256, 2) k_contract_x3(const unsigned short* __restrict__ ah,
                                                      const unsigned short* __restrict__ al, int M,
                                                      const unsigned short* __restrict__ bh,
                                                      const unsigned short* __restrict__ bl, int N,
@@ -52,7 +83,6 @@ __global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __res
                                                      unsigned ntile, int remap,
                                                      float* __restrict__ part) {
   constexpr int P = KS + 8;            // padded LDS row (bf16), a multiple of 8
-  constexpr int NV = KS / 16;          // uint4 per thread and array
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_c[];
   __bf16 (*Ah)[P] = reinterpret_cast<__bf16 (*)[P]>(smem_c);
   __bf16 (*Al)[P] = Ah + XT;
@@ -65,48 +95,54 @@ __global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __res
   const size_t k0 = (size_t)kc * chunk, k1 = min(K, k0 + chunk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int sb = tid >> 1, hb = (tid & 1) * (KS / 2);   // row sb, K values hb .. hb + KS/2 - 1
+  // loader: QR lanes per row, each one 16-byte piece of the row's KS
+  // values, so that a load instruction covers whole 128-byte lines of
+  // RPP rows; pass c takes rows r0 + RPP c of the 2 XT staged rows (A's,
+  // then B's).  Rows past M (columns past N) load the last row: their
+  // outputs are never stored.
+  constexpr int QR = KS / 8, RPP = 256 / QR, NC = 2 * XT / RPP;
+  static_assert(2 * XT % RPP == 0 && XT % RPP == 0, "passes fill A's rows, then B's");
+  const int qp = tid % QR, r0 = tid / QR;
+  const unsigned short* gh[NC];
+  const unsigned short* gl[NC];
+  __bf16* lh[NC];
+  __bf16* ll[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int r = r0 + RPP * c;
+    if (r < XT) {
+      const size_t m = (size_t)min(M - 1, m0 + r);
+      gh[c] = ah + m * K + 8 * qp;
+      gl[c] = al + m * K + 8 * qp;
+      lh[c] = &Ah[r][8 * qp];
+      ll[c] = &Al[r][8 * qp];
+    } else {
+      const size_t n = (size_t)min(N - 1, n0 + r - XT);
+      gh[c] = bh + n * K + 8 * qp;
+      gl[c] = bl + n * K + 8 * qp;
+      lh[c] = &Bh[r - XT][8 * qp];
+      ll[c] = &Bl[r - XT][8 * qp];
+    }
+  }
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  uint4 rah[NV], ral[NV], rbh[NV], rbl[NV];
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  auto load = [&](size_t kb) {
-    const int m = m0 + sb, n = n0 + sb;
-    if (m < M) {
-      const uint4* qh = reinterpret_cast<const uint4*>(ah + (size_t)m * K + kb + hb);
-      const uint4* ql = reinterpret_cast<const uint4*>(al + (size_t)m * K + kb + hb);
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  u4v rh[NC], rl[NC];
+  auto load = [&](size_t kb) __attribute__((always_inline)) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        rah[q] = qh[q];
-        ral[q] = ql[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) rah[q] = ral[q] = z4;
-    }
-    if (n < N) {
-      const uint4* qh = reinterpret_cast<const uint4*>(bh + (size_t)n * K + kb + hb);
-      const uint4* ql = reinterpret_cast<const uint4*>(bl + (size_t)n * K + kb + hb);
-#pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        rbh[q] = qh[q];
-        rbl[q] = ql[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) rbh[q] = rbl[q] = z4;
+    for (int c = 0; c < NC; ++c) {
+      rh[c] = *reinterpret_cast<const u4v*>(gh[c] + kb);
+      rl[c] = *reinterpret_cast<const u4v*>(gl[c] + kb);
     }
   };
-  auto store = [&]() {
+  auto store = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      *reinterpret_cast<uint4*>(&Ah[sb][hb + 8 * q]) = rah[q];
-      *reinterpret_cast<uint4*>(&Al[sb][hb + 8 * q]) = ral[q];
-      *reinterpret_cast<uint4*>(&Bh[sb][hb + 8 * q]) = rbh[q];
-      *reinterpret_cast<uint4*>(&Bl[sb][hb + 8 * q]) = rbl[q];
+    for (int c = 0; c < NC; ++c) {
+      *reinterpret_cast<u4v*>(lh[c]) = rh[c];
+      *reinterpret_cast<u4v*>(ll[c]) = rl[c];
     }
   };
   load(k0);
@@ -116,7 +152,7 @@ __global__ void __launch_bounds__(256) k_contract_x3(const unsigned short* __res
     __syncthreads();
     if (kb + KS < k1) load(kb + KS);
 #pragma unroll
-    for (int ko = 0; ko < KS; ko += XK) mma_stage<P>(Ah, Al, Bh, Bl, lane, wm, wn, acc, ko);
+    for (int ko = 0; ko < KS; ko += XK) mma_step_bstream<P>(Ah, Al, Bh, Bl, lane, wm, wn, acc, ko);
   }
   float* out = part + (size_t)kc * M * N;
 #pragma unroll
