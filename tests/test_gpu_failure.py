@@ -60,6 +60,39 @@ def test_nan_in_one_orbital_fails_only_its_pairs(setup, precision):
     s.close()
 
 
+
+@pytest.mark.timeout(300)
+def test_nan_at_the_paper_grid_fails_only_its_pairs():
+    """The same at 112^3 in mixed precision, where the y and z factors of the
+    propagation run as one pass over whole planes with the lines in
+    registers: three pairs, so that one packed Poisson field holds a failed
+    density with a good one and the other a failed density alone; the NaN
+    sits at the centre of the box, where the orbital is large, so that the
+    failed pair's sanitised source differs from the clean one."""
+    import dataclasses
+    from paper_2205_06690_amd import bse, inputs
+    spec = dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=20)
+    sysd = inputs.make_system(spec)
+    bad_orb = spec.n_occ + 1
+    pairs = np.array([(spec.n_occ - 2, bad_orb), (spec.n_occ - 1, bad_orb + 1), (spec.n_occ - 1, bad_orb)],
+                     dtype=np.int32)
+    s = gpu_system(spec, sysd, bse.BSE_MIXED, max_batch=len(pairs))
+    w_clean, st0 = s.apply_w(pairs, return_status=True)
+    assert np.all(st0 == 0) and np.all(np.isfinite(w_clean))
+    c = spec.n // 2
+    s.inject_fault(bad_orb, (c * spec.n + c) * spec.n + c, float("nan"))
+    w, st = s.apply_w(pairs, return_status=True)
+    bad = np.array([bad_orb in p for p in pairs])
+    say(f"112^3: statuses {st.tolist()}, bad pairs {np.flatnonzero(bad).tolist()}")
+    assert np.all(st[bad] == bse.BSE_ERR_NUMERIC)
+    assert np.all(st[~bad] == 0)
+    assert np.all(np.isnan(w[bad]))
+    e = rel(w[~bad], w_clean[~bad]).max()
+    say(f"112^3: good pair vs clean run {e:.2e}")
+    assert e < 1e-5
+    s.close()
+
+
 def test_unperturbed_norm_drift_fails_every_pair(setup):
     from paper_2205_06690_amd import bse
     spec, sysd, pairs = setup
