@@ -286,7 +286,7 @@ __global__ void k_coef_split(const double2* __restrict__ coef, int F, int S, int
 // in stages of 32; row tile fastest so that the row tiles of one point tile
 // (sharing its phi^T tile) run together on one XCD.
 template <bool MID>
-__global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F, PhiSplit ps,
+__global__ void __launch_bounds__(256, 3) k_update_x3(float2* __restrict__ d, int F, PhiSplit ps,
                                                    const float2* __restrict__ E, int L, size_t ng,
                                                    const unsigned short* __restrict__ cth,
                                                    const unsigned short* __restrict__ ctl,
@@ -310,47 +310,46 @@ __global__ void __launch_bounds__(256) k_update_x3(float2* __restrict__ d, int F
   const int R = 2 * F, S = ps.S, Sp = ps.Sp;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int sb = tid >> 1, hb = (tid & 1) * 16;   // row / point sb, states hb..hb+15
+  // loader: 4 lanes per row, 16 bytes each, 64 rows a pass; passes 0 and 1
+  // take coefficient rows, 2 and 3 points of phi^T.  Rows past R (points
+  // past ng) load the last one: their results are never stored.  go, lo:
+  // element offsets in the global operand and in LDS (hi arrays; lo arrays
+  // one operand tile further)
+  const int qp = tid & 3, rw = tid >> 2;
+  unsigned go[4], lo[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int r = rw + 64 * (c & 1);
+    if (c < 2) {
+      go[c] = (unsigned)min(R - 1, r0 + r) * (unsigned)Sp + 8 * qp;
+      lo[c] = r * XKP + 8 * qp;
+    } else {
+      go[c] = (unsigned)min(ng - 1, p0 + r) * (unsigned)Sp + 8 * qp;
+      lo[c] = 2 * XT * XKP + r * XKP + 8 * qp;
+    }
+  }
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  uint4 rah[2], ral[2], rbh[2], rbl[2];
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  auto load = [&](int kb) {
-    const int row = r0 + sb;
-    if (row < R) {
-      const uint4* qh = reinterpret_cast<const uint4*>(cth + (size_t)row * Sp + kb + hb);
-      const uint4* ql = reinterpret_cast<const uint4*>(ctl + (size_t)row * Sp + kb + hb);
-      rah[0] = qh[0];
-      rah[1] = qh[1];
-      ral[0] = ql[0];
-      ral[1] = ql[1];
-    } else {
-      rah[0] = rah[1] = ral[0] = ral[1] = z4;
-    }
-    const size_t pt = p0 + sb;
-    if (pt < ng) {
-      const uint4* qh = reinterpret_cast<const uint4*>(ps.th + pt * Sp + kb + hb);
-      const uint4* ql = reinterpret_cast<const uint4*>(ps.tl + pt * Sp + kb + hb);
-      rbh[0] = qh[0];
-      rbh[1] = qh[1];
-      rbl[0] = ql[0];
-      rbl[1] = ql[1];
-    } else {
-      rbh[0] = rbh[1] = rbl[0] = rbl[1] = z4;
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  u4v rh[4], rl[4];
+  auto load = [&](int kb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const unsigned short* gh = c < 2 ? cth : ps.th;
+      const unsigned short* gl = c < 2 ? ctl : ps.tl;
+      rh[c] = *reinterpret_cast<const u4v*>(gh + go[c] + kb);
+      rl[c] = *reinterpret_cast<const u4v*>(gl + go[c] + kb);
     }
   };
-  auto store = [&]() {
-    *reinterpret_cast<uint4*>(&Ah[sb][hb]) = rah[0];
-    *reinterpret_cast<uint4*>(&Ah[sb][hb + 8]) = rah[1];
-    *reinterpret_cast<uint4*>(&Al[sb][hb]) = ral[0];
-    *reinterpret_cast<uint4*>(&Al[sb][hb + 8]) = ral[1];
-    *reinterpret_cast<uint4*>(&Bh[sb][hb]) = rbh[0];
-    *reinterpret_cast<uint4*>(&Bh[sb][hb + 8]) = rbh[1];
-    *reinterpret_cast<uint4*>(&Bl[sb][hb]) = rbl[0];
-    *reinterpret_cast<uint4*>(&Bl[sb][hb + 8]) = rbl[1];
+  auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      *reinterpret_cast<u4v*>(lds_u + lo[c]) = rh[c];
+      *reinterpret_cast<u4v*>(lds_u + lo[c] + XT * XKP) = rl[c];
+    }
   };
   load(0);
   for (int kb = 0; kb < Sp; kb += XK) {
@@ -477,6 +476,8 @@ hipError_t launch_coef_x3(const float2* d, int F, const PhiSplit& ps, size_t ng,
 hipError_t launch_update_x3(float2* d, int F, const PhiSplit& ps, const float2* E, int L, size_t ng,
                             const double2* coef, float* scratch, hipStream_t st, const MidArgs& mid) {
   if (F <= 0 || ps.S <= 0 || ps.Sp != clean_sp(ps.S)) return hipErrorInvalidValue;
+  // the loader's 32-bit element offsets into phi^T and the coefficient rows
+  if (ng * (size_t)ps.Sp > 0xFFFFFFFFull || (size_t)2 * F * ps.Sp > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const int Sp = ps.Sp;
   unsigned short* cth = reinterpret_cast<unsigned short*>(scratch);
   unsigned short* ctl = cth + (size_t)2 * F * Sp;
