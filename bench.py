@@ -194,10 +194,12 @@ def cpu_parallel_baseline(config: str, spec, pairs, steps: int, procs: int):
 def bench_uneven(args):
     """The uneven batch: 32 synthetic molecules on {32,48,64}^3 grids with
     10-80 wells, N_occ 10-100 and 16-200 pair densities each, L = 10,
-    400 steps, FP32 propagation.  Timed four ways: one system after the
+    400 steps, FP32 propagation.  Timed six ways: one system after the
     other, all systems on their own streams, all systems captured into one
-    HIP graph inside the call, and the replay of a plan captured once
-    beforehand (the reported value).  The CPU baseline runs the oracle on
+    HIP graph inside the call, the lockstep work-list schedule (the
+    propagation passes of every system in one persistent launch each per
+    time step) plain and captured inside the call, and the replay of a plan
+    captured once beforehand (the reported value).  The CPU baseline runs the oracle on
     one pair of the smallest member, and the plan's W of that pair is
     compared with it.  Prints one JSON line."""
     import torch
@@ -220,13 +222,15 @@ def bench_uneven(args):
                        clean_every=sp.clean_every, precision=bse.BSE_MIXED, max_batch=len(p))
         S.set_signs(sd["xi"])
         S.set_orbitals(sd["phi"], sd["eps"])
+        shape = ""
         if args.autotune:
-            S.autotune(len(p), os.path.join(os.environ.get("TMPDIR", "/tmp"), "bse_tune.txt"))
+            tc, nt = S.autotune(len(p), os.path.join(os.environ.get("TMPDIR", "/tmp"), "bse_tune.txt"))
+            shape = f", tuned x tile {tc}, plane block {nt}"
         systems.append(S)
         pairs.append(p)
         pairs_dev.append(torch.from_numpy(np.ascontiguousarray(p, dtype=np.int32)).cuda())
         outs.append(torch.empty((len(p), sp.ng), dtype=torch.float64, device="cuda"))
-        print(f"[bench] system {k}: {sp.n}^3, N_occ {sp.n_occ}, {len(p)} pairs", file=sys.stderr,
+        print(f"[bench] system {k}: {sp.n}^3, N_occ {sp.n_occ}, {len(p)} pairs{shape}", file=sys.stderr,
               flush=True)
     print(f"[bench] inputs ready in {time.perf_counter() - t_in:.1f}s", file=sys.stderr, flush=True)
     total = sum(len(p) for p in pairs)
@@ -246,10 +250,11 @@ def bench_uneven(args):
             plan.run()
         else:
             bse.apply_w_batch(systems, pairs, [o.data_ptr() for o in outs],
-                              use_graph=(mode == "graph"))
+                              use_graph=mode in ("graph", "worklist_graph"),
+                              work_list=mode.startswith("worklist"))
         torch.cuda.synchronize()
 
-    for mode in ("sequential", "streams", "graph", "plan"):
+    for mode in ("sequential", "streams", "graph", "worklist", "worklist_graph", "plan"):
         for _ in range(args.warmup):
             run(mode)
         t0 = time.perf_counter()
@@ -273,6 +278,8 @@ def bench_uneven(args):
         "sequential_solves_per_s": round(total / res["sequential"], 3),
         "streams_solves_per_s": round(total / res["streams"], 3),
         "graph_captured_per_call_solves_per_s": round(total / res["graph"], 3),
+        "worklist_solves_per_s": round(total / res["worklist"], 3),
+        "worklist_graph_per_call_solves_per_s": round(total / res["worklist_graph"], 3),
         "plan_capture_s": round(t_plan_make, 2),
     }
     plan.close()

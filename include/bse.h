@@ -312,13 +312,22 @@ bse_status bse_fit_box_correction(int32_t n_box, int32_t n_exc, const double* om
 /* Uneven batch: the W-action for several systems at once (different grids,
  * orbital counts and pair counts, same device).  System k propagates
  * n_pairs[k] (<= its max_batch) pairs pq[k][n_pairs[k]][2] (host) and
- * writes W to w_dev[k] (device, FP64, [n_pairs[k]][ng_k]).  With
- * use_graph != 0 the whole propagation of every system is captured into one
- * HIP graph (one branch per system) and launched once; otherwise the systems
- * run on their own streams.  Returns after the work has finished.  Results
- * equal those of bse_apply_W_device per system. */
+ * writes W to w_dev[k] (device, FP64, [n_pairs[k]][ng_k]).  mode bit 0:
+ * the whole propagation of every system is captured into one HIP graph and
+ * launched once.  mode bit 1: the lockstep work-list schedule, every system
+ * taking each time step in turn on one stream, with the perturbed sets' x
+ * and plane passes of all systems as one persistent launch each per step,
+ * walking the (system, pair, tile or plane) items of the whole batch;
+ * mixed-precision systems on grids of 16, 24, 32, 48 or 64 points per axis
+ * with the same number of steps and cleaning interval (else BSE_ERR_ARG).
+ * Without bit 1 the systems run on their own streams (one graph branch each
+ * with bit 0).  Returns after the work has finished.  Results equal those
+ * of bse_apply_W_device per system bit for bit in every mode.  Errors:
+ * BSE_ERR_ARG for a null argument, a mode outside 0..3, a system twice,
+ * systems on different devices, n_pairs outside 1..max_batch or a pair
+ * index out of range. */
 bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
-                             const int32_t* const* pq, void* const* w_dev, int32_t use_graph);
+                             const int32_t* const* pq, void* const* w_dev, int32_t mode);
 
 /* Uneven batch as a plan (the batched form of the W-action for many
  * independent systems; the paper treats pairs as independent units, and

@@ -157,16 +157,19 @@ def _iptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
-def apply_w_batch(systems, pair_lists, w_dev_ptrs, use_graph: bool = True):
+def apply_w_batch(systems, pair_lists, w_dev_ptrs, use_graph: bool = True, work_list: bool = False):
     """W-action for several systems at once (bse_apply_W_batch); outputs go to
-    the device buffers whose pointers are given."""
+    the device buffers whose pointers are given.  use_graph: captured into
+    one HIP graph; work_list: the lockstep schedule whose propagation passes
+    walk the items of every system in one launch each per time step."""
     n = len(systems)
     hs = (C.c_void_p * n)(*[s._h for s in systems])
     pqs = [np.ascontiguousarray(np.asarray(p, dtype=np.int32).reshape(-1, 2)) for p in pair_lists]
     npairs = np.array([p.shape[0] for p in pqs], dtype=np.int32)
     pq_ptrs = (C.POINTER(C.c_int32) * n)(*[_iptr(p) for p in pqs])
     w_ptrs = (C.c_void_p * n)(*[C.c_void_p(p) for p in w_dev_ptrs])
-    _check(LIB.bse_apply_W_batch(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, 1 if use_graph else 0))
+    mode = (1 if use_graph else 0) | (2 if work_list else 0)
+    _check(LIB.bse_apply_W_batch(n, hs, _iptr(npairs), pq_ptrs, w_ptrs, mode))
 
 
 class BatchPlan:

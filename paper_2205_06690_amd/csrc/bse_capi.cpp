@@ -366,18 +366,34 @@ void poissonT(bse_system* s, int B, double* acc, double wn) {
   s->timer.end(t);
 }
 
-// one batch of B pairs (pair list pq_dev[B][2] on the device);
+// One propagation of B pairs (pair list pq_dev[B][2] on the device) in
+// phases, so that the time steps of several systems can be interleaved:
 // results W^pol (FP64) in s->wpol, q in s->q.  Only kernel launches and
 // device-to-device work are issued, so the sequence can be captured into a
-// HIP graph.  The unperturbed set is propagated alongside, double-buffered.
+// HIP graph.  The unperturbed set is propagated alongside, double-buffered:
+// H_0 in s->h0, H_n in hbuf[n & 1] for n >= 1.
 template <typename T>
-void propagate_batch(bse_system* s, int B, const int* pq_dev) {
+struct PropRun {
+  bse_system* s;
+  int B;
+  const int* pq_dev;
+  const cplx<T>* hcur;   // H_n
+  bool half;             // the state is an end-of-step state (t = 0 or just cleaned)
+};
+
+template <typename T>
+cplx<T>* prop_hbuf(bse_system* s, int n) {
+  return s->hbuf.as<cplx<T>>() + (size_t)(n & 1) * (size_t)s->L * s->ng;
+}
+
+template <typename T>
+void prop_begin(PropRun<T>& r) {
   using C = cplx<T>;
-  Tables& tb = tabs<T>(s);
+  bse_system* s = r.s;
+  const int B = r.B;
   const size_t ng = s->ng;
   const int L = s->L;
   const int F = B * L;
-  const int N = s->cfg.n_steps;
   const int M = s->cfg.clean_every;
   hipStream_t st = s->stream;
   // per-pair failure flags, sticky over the whole propagation: bit 0 a
@@ -385,7 +401,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
   // unperturbed set at a cleaning step (every pair), and the final check
   // of W sets bit 0 too
   HIPC(launch_fill_zero(s->flags.p, sizeof(int) * B, st));
-  HIPC(launch_pair_density(s->phi64.as<double>(), pq_dev, B, ng, s->rho64.as<double>(), st));
+  HIPC(launch_pair_density(s->phi64.as<double>(), r.pq_dev, B, ng, s->rho64.as<double>(), st));
   poisson64(s, s->rho64.as<double>(), B, s->q.as<double>(), nullptr, 0.0, s->flags.as<int>());
   // per-pair scales for the packed Poisson solves of the induced densities:
   // the RMS of q_b (the response is linear in it), so that a pair whose
@@ -396,89 +412,148 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
   HIPC(launch_fill_zero(s->wpol.p, sizeof(double) * ng * B, st));
   HIPC(launch_fill_zero(s->u.p, sizeof(T) * ng * B, st));
   HIPC(launch_kick<T>(s->q.as<double>(), s->eta0.as<double>(), L, F, ng, s->d.as<C>(), st));
-  const size_t hstride = (size_t)L * ng;
-  const C* hcur = s->h0.as<C>();
-  C* hbuf = s->hbuf.as<C>();
-  if (M > 0) clean<T>(s, B, 2, hcur);
+  r.hcur = s->h0.as<C>();
+  if (M > 0) clean<T>(s, B, 2, r.hcur);
   // u_0 = 0: a phase kick does not change the density, so the t = 0 term
   // of the time integral vanishes.
-  bool half = true;
-  for (int n = 0; n < N; ++n) {
-    C* hnext = hbuf + (size_t)((n + 1) & 1) * hstride;
-    // unperturbed set: one step, H_n -> H_{n+1}
-    PropXArgs<T> pe{};
-    pe.din = hcur;
-    pe.dout = hnext;
-    pe.pf = tb.pf.as<C>();
-    pe.ph = tb.ph.as<C>();
-    pe.tw = tb.tw.as<C>();
-    pe.kph = tb.kph.as<C>();
-    pe.dt = (T)s->cfg.dt;
-    pe.L = L;
-    pe.mode = PX_ETA0;
-    pe.order = s->launch_order & 1;
-    HIPC(launch_prop_x<T>(s->n, pe, L, st, s->tune_tc));
-    PropYZArgs<T> pze{};
-    pze.d = hnext;
-    pze.tw = tb.tw.as<C>();
-    pze.kph = tb.kph.as<C>();
-    pze.L = L;
-    pze.density = 0;
-    const bool fused = s->yz_schedule != 1 && prop_yz_fused<T>(s->n);
-    // bit 1 orders the y-line pass, bit 2 the fused y-z pass
-    const int yz_order = (s->launch_order >> (fused ? 2 : 1)) & 1;
-    pze.order = yz_order;
-    pze.fused = fused ? (s->yz_schedule == 2 ? 2 : 1) : 0;
-    HIPC(launch_prop_yz<T>(s->n, pze, L, st, s->tune_nt));
-    // perturbed set
-    PropXArgs<T> px{};
-    px.din = s->d.as<C>();
-    px.dout = s->d.as<C>();
-    px.pf = tb.pf.as<C>();
-    px.ph = tb.ph.as<C>();
-    px.u = s->u.as<T>();
-    px.H = hcur;
-    px.tw = tb.tw.as<C>();
-    px.kph = tb.kph.as<C>();
-    px.dt = (T)s->cfg.dt;
-    px.L = L;
-    px.mode = half ? PX_HALF : PX_FULL;
-    px.order = s->launch_order & 1;
-    auto* t1 = s->timer.slot("prop_x", 1);
-    const LaunchEvents e1{t1 ? t1->first : nullptr, t1 ? t1->second : nullptr};
-    HIPC(launch_prop_x<T>(s->n, px, B, st, s->tune_tc, t1 ? &e1 : nullptr));
-    PropYZArgs<T> pz{};
-    pz.d = s->d.as<C>();
-    pz.H = hnext;
-    pz.tw = tb.tw.as<C>();
-    pz.kph = tb.kph.as<C>();
-    pz.dens = s->dens.as<T>();
-    pz.L = L;
-    pz.density = 1;
-    pz.order = yz_order;
-    pz.fused = pze.fused;
-    const bool split = !fused && prop_yz_split<T>(s->n);
-    auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
-    auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
-    const LaunchEvents e2{t2 ? t2->first : nullptr, t2 ? t2->second : nullptr};
-    const LaunchEvents e3{t3 ? t3->first : nullptr, t3 ? t3->second : nullptr};
-    HIPC(launch_prop_yz<T>(s->n, pz, B, st, s->tune_nt, t2 ? &e2 : nullptr, t3 ? &e3 : nullptr));
-    const bool do_clean = M > 0 && ((n + 1) % M == 0);
-    const double wn = s->wts[n + 1];
-    if (!do_clean) {
-      poissonT<T>(s, B, s->wpol.as<double>(), wn);
-      half = false;
-    } else {
-      poissonT<T>(s, B, nullptr, 0.0);
-      clean<T>(s, B, 1, hnext);
-      // the check point of Eq. 15: the unperturbed set must keep the norms
-      // of eta_l(0) under the unitary propagation
-      HIPC(launch_norm_drift<T>(hnext, L, ng, s->dv, s->n0.as<double>(), sizeof(T) == 4 ? 1e-3 : 1e-8,
-                                s->flags.as<int>(), B, s->normpart.as<double>(), st));
-      poissonT<T>(s, B, s->wpol.as<double>(), wn);
-      half = true;
-    }
-    hcur = hnext;
+  r.half = true;
+}
+
+// the y-z schedule of this system's plane passes
+struct YZSched {
+  bool fused;
+  int order;
+  int fused_kind;
+};
+template <typename T>
+YZSched yz_sched(const bse_system* s) {
+  YZSched y;
+  y.fused = s->yz_schedule != 1 && prop_yz_fused<T>(s->n);
+  // bit 1 orders the y-line pass, bit 2 the fused y-z pass
+  y.order = (s->launch_order >> (y.fused ? 2 : 1)) & 1;
+  y.fused_kind = y.fused ? (s->yz_schedule == 2 ? 2 : 1) : 0;
+  return y;
+}
+
+// unperturbed set: one step, H_n -> H_{n+1}
+template <typename T>
+void prop_unperturbed_step(PropRun<T>& r, int n) {
+  using C = cplx<T>;
+  bse_system* s = r.s;
+  Tables& tb = tabs<T>(s);
+  C* hnext = prop_hbuf<T>(s, n + 1);
+  PropXArgs<T> pe{};
+  pe.din = r.hcur;
+  pe.dout = hnext;
+  pe.pf = tb.pf.as<C>();
+  pe.ph = tb.ph.as<C>();
+  pe.tw = tb.tw.as<C>();
+  pe.kph = tb.kph.as<C>();
+  pe.dt = (T)s->cfg.dt;
+  pe.L = s->L;
+  pe.mode = PX_ETA0;
+  pe.order = s->launch_order & 1;
+  HIPC(launch_prop_x<T>(s->n, pe, s->L, s->stream, s->tune_tc));
+  const YZSched y = yz_sched<T>(s);
+  PropYZArgs<T> pze{};
+  pze.d = hnext;
+  pze.tw = tb.tw.as<C>();
+  pze.kph = tb.kph.as<C>();
+  pze.L = s->L;
+  pze.density = 0;
+  pze.order = y.order;
+  pze.fused = y.fused_kind;
+  HIPC(launch_prop_yz<T>(s->n, pze, s->L, s->stream, s->tune_nt));
+}
+
+// the perturbed set's two passes of step n (hcur = H_n, half as after step n - 1)
+template <typename T>
+PropXArgs<T> prop_pair_x_args(bse_system* s, const cplx<T>* hcur, bool half) {
+  using C = cplx<T>;
+  Tables& tb = tabs<T>(s);
+  PropXArgs<T> px{};
+  px.din = s->d.as<C>();
+  px.dout = s->d.as<C>();
+  px.pf = tb.pf.as<C>();
+  px.ph = tb.ph.as<C>();
+  px.u = s->u.as<T>();
+  px.H = hcur;
+  px.tw = tb.tw.as<C>();
+  px.kph = tb.kph.as<C>();
+  px.dt = (T)s->cfg.dt;
+  px.L = s->L;
+  px.mode = half ? PX_HALF : PX_FULL;
+  px.order = s->launch_order & 1;
+  return px;
+}
+template <typename T>
+PropYZArgs<T> prop_pair_yz_args(bse_system* s, const cplx<T>* hnext) {
+  using C = cplx<T>;
+  Tables& tb = tabs<T>(s);
+  const YZSched y = yz_sched<T>(s);
+  PropYZArgs<T> pz{};
+  pz.d = s->d.as<C>();
+  pz.H = hnext;
+  pz.tw = tb.tw.as<C>();
+  pz.kph = tb.kph.as<C>();
+  pz.dens = s->dens.as<T>();
+  pz.L = s->L;
+  pz.density = 1;
+  pz.order = y.order;
+  pz.fused = y.fused_kind;
+  return pz;
+}
+template <typename T>
+void prop_pair_passes(PropRun<T>& r, int n) {
+  bse_system* s = r.s;
+  const PropXArgs<T> px = prop_pair_x_args<T>(s, r.hcur, r.half);
+  auto* t1 = s->timer.slot("prop_x", 1);
+  const LaunchEvents e1{t1 ? t1->first : nullptr, t1 ? t1->second : nullptr};
+  HIPC(launch_prop_x<T>(s->n, px, r.B, s->stream, s->tune_tc, t1 ? &e1 : nullptr));
+  const PropYZArgs<T> pz = prop_pair_yz_args<T>(s, prop_hbuf<T>(s, n + 1));
+  const YZSched y = yz_sched<T>(s);
+  const bool split = !y.fused && prop_yz_split<T>(s->n);
+  auto* t2 = s->timer.slot(split ? "prop_z" : "prop_yz", 1);
+  auto* t3 = split ? s->timer.slot("prop_y", 1) : nullptr;
+  const LaunchEvents e2{t2 ? t2->first : nullptr, t2 ? t2->second : nullptr};
+  const LaunchEvents e3{t3 ? t3->first : nullptr, t3 ? t3->second : nullptr};
+  HIPC(launch_prop_yz<T>(s->n, pz, r.B, s->stream, s->tune_nt, t2 ? &e2 : nullptr, t3 ? &e3 : nullptr));
+}
+
+// the rest of step n after the passes: the potential of the new density
+// (and its time-integral term), the cleaning every M steps
+template <typename T>
+void prop_after_passes(PropRun<T>& r, int n) {
+  bse_system* s = r.s;
+  const int B = r.B;
+  const int M = s->cfg.clean_every;
+  cplx<T>* hnext = prop_hbuf<T>(s, n + 1);
+  const bool do_clean = M > 0 && ((n + 1) % M == 0);
+  const double wn = s->wts[n + 1];
+  if (!do_clean) {
+    poissonT<T>(s, B, s->wpol.as<double>(), wn);
+    r.half = false;
+  } else {
+    poissonT<T>(s, B, nullptr, 0.0);
+    clean<T>(s, B, 1, hnext);
+    // the check point of Eq. 15: the unperturbed set must keep the norms
+    // of eta_l(0) under the unitary propagation
+    HIPC(launch_norm_drift<T>(hnext, s->L, s->ng, s->dv, s->n0.as<double>(), sizeof(T) == 4 ? 1e-3 : 1e-8,
+                              s->flags.as<int>(), B, s->normpart.as<double>(), s->stream));
+    poissonT<T>(s, B, s->wpol.as<double>(), wn);
+    r.half = true;
+  }
+  r.hcur = hnext;
+}
+
+template <typename T>
+void propagate_batch(bse_system* s, int B, const int* pq_dev) {
+  PropRun<T> r{s, B, pq_dev, nullptr, true};
+  prop_begin<T>(r);
+  for (int n = 0; n < s->cfg.n_steps; ++n) {
+    prop_unperturbed_step<T>(r, n);
+    prop_pair_passes<T>(r, n);
+    prop_after_passes<T>(r, n);
   }
 }
 
@@ -1319,13 +1394,121 @@ void autotune_t(bse_system* s, int B, const char* cache_path) {
 }
 
 // ---------------------------------------------------------------------------
-// uneven batch: several systems (grids, pair counts) propagated together; the
-// whole propagation of every system is captured into one HIP graph with one
-// branch per system and launched once
+// lockstep work-list schedule of an uneven batch: every system takes time
+// step n in turn, and the perturbed sets' x and plane passes of all systems
+// of one grid size run as one persistent work-list launch each, over the
+// (system, pair, tile or plane) items of those systems.  The pass arguments of a step depend
+// only on which buffer holds H_n (h0 at n = 0, then hbuf[n & 1]), on whether
+// the state is an end-of-step one (t = 0 or just cleaned) and on which
+// buffer takes H_{n+1}, so every variant is on the device before the first
+// step and the schedule can be captured.
+// ---------------------------------------------------------------------------
+void batch_list_check(int n_sys, bse_system* const* sys) {
+  for (int i = 0; i < n_sys; ++i) {
+    const bse_system* s = sys[i];
+    if (s->cfg.precision != BSE_MIXED)
+      fail(BSE_ERR_ARG, "bse_apply_W_batch: the work-list schedule runs mixed-precision systems only");
+    if (!prop_list_grid(s->n) || prop_yz_split<float>(s->n) || prop_yz_fused<float>(s->n))
+      fail(BSE_ERR_ARG, "bse_apply_W_batch: the work-list schedule takes grids of 16, 24, 32, 48 or 64 points per axis");
+    if (s->cfg.n_steps != sys[0]->cfg.n_steps || s->cfg.clean_every != sys[0]->cfg.clean_every)
+      fail(BSE_ERR_ARG, "bse_apply_W_batch: the work-list schedule needs the same number of steps and cleaning "
+                        "interval in every system");
+  }
+}
+
+constexpr int LIST_XV = 5;   // x-pass variants: n = 0, then (n & 1, end-of-step state)
+
+// the systems grouped by grid size; in each group's entries, first counts
+// the group's items before the system
+struct BatchList {
+  struct Group {
+    int n;
+    int e0, ne;              // entries e0 .. e0 + ne - 1 of every variant
+    unsigned tot_x, tot_yz;
+  };
+  std::vector<Group> groups;
+  DBuf buf;                  // LIST_XV x n_sys XListSys, then 2 x n_sys YZListSys
+  int n_sys = 0;
+  const XListSys* x(int v, const Group& g) const { return buf.as<XListSys>() + (size_t)v * n_sys + g.e0; }
+  const YZListSys* yz(int p, const Group& g) const {
+    return reinterpret_cast<const YZListSys*>(buf.as<XListSys>() + (size_t)LIST_XV * n_sys) + (size_t)p * n_sys +
+           g.e0;
+  }
+};
+
+void batch_list_build(int n_sys, bse_system* const* sys, const int32_t* n_pairs, BatchList& bl) {
+  std::vector<XListSys> xl((size_t)LIST_XV * n_sys);
+  std::vector<YZListSys> yl((size_t)2 * n_sys);
+  bl.n_sys = n_sys;
+  std::vector<int> order(n_sys);
+  for (int i = 0; i < n_sys; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return sys[p]->n < sys[q]->n; });
+  for (int k = 0; k < n_sys; ++k) {
+    const int i = order[k];
+    bse_system* s = sys[i];
+    const int B = n_pairs[i];
+    if (bl.groups.empty() || bl.groups.back().n != s->n) bl.groups.push_back({s->n, k, 0, 0u, 0u});
+    BatchList::Group& g = bl.groups.back();
+    for (int v = 0; v < LIST_XV; ++v) {
+      const cplx<float>* hcur = v == 0 ? s->h0.as<cplx<float>>() : prop_hbuf<float>(s, (v - 1) >> 1);
+      const bool half = v == 0 || ((v - 1) & 1);
+      XListSys& e = xl[(size_t)v * n_sys + k];
+      e.a = prop_pair_x_args<float>(s, hcur, half);
+      e.a.nf = B;
+      e.first = g.tot_x;
+    }
+    for (int p = 0; p < 2; ++p) {
+      YZListSys& e = yl[(size_t)p * n_sys + k];
+      e.a = prop_pair_yz_args<float>(s, prop_hbuf<float>(s, p));
+      e.a.nf = B;
+      e.first = g.tot_yz;
+    }
+    g.ne += 1;
+    g.tot_x += prop_x_list_items(s->n, B);
+    g.tot_yz += prop_yz_list_items(s->n, B);
+  }
+  const size_t bx = sizeof(XListSys) * xl.size(), by = sizeof(YZListSys) * yl.size();
+  bl.buf.alloc(bx + by);
+  HIPC(hipMemcpy(bl.buf.p, xl.data(), bx, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(static_cast<char*>(bl.buf.p) + bx, yl.data(), by, hipMemcpyHostToDevice));
+}
+
+// the whole batch on one stream (every system's stream set to it)
+void batch_list_run(int n_sys, bse_system* const* sys, const int32_t* n_pairs, void* const* w_dev,
+                    const BatchList& bl, hipStream_t st) {
+  std::vector<PropRun<float>> runs(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    runs[i] = PropRun<float>{sys[i], n_pairs[i], sys[i]->pq_d.as<int>(), nullptr, true};
+    prop_begin<float>(runs[i]);
+  }
+  const int N = sys[0]->cfg.n_steps;
+  for (int n = 0; n < N; ++n) {
+    for (auto& r : runs) prop_unperturbed_step<float>(r, n);
+    const int v = n == 0 ? 0 : 1 + 2 * (n & 1) + (runs[0].half ? 1 : 0);
+    for (const auto& g : bl.groups) HIPC(launch_prop_x_list(g.n, bl.x(v, g), g.ne, g.tot_x, st));
+    for (const auto& g : bl.groups) HIPC(launch_prop_yz_list(g.n, bl.yz((n + 1) & 1, g), g.ne, g.tot_yz, st));
+    for (auto& r : runs) prop_after_passes<float>(r, n);
+  }
+  for (int i = 0; i < n_sys; ++i) {
+    bse_system* s = sys[i];
+    double* w = reinterpret_cast<double*>(w_dev[i]);
+    HIPC(launch_add(s->q.as<double>(), s->wpol.as<double>(), (size_t)n_pairs[i] * s->ng, w, st));
+    HIPC(launch_finite_check(w, n_pairs[i], s->ng, s->flags.as<int>(), st));
+    HIPC(launch_nan_flagged(w, n_pairs[i], s->ng, s->flags.as<int>(), st));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// uneven batch: several systems (grids, pair counts) propagated together.
+// mode bit 0: the whole propagation captured into one HIP graph and launched
+// once; bit 1: the lockstep work-list schedule on one stream, else every
+// system on its own stream (one graph branch each when captured)
 // ---------------------------------------------------------------------------
 void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
-                   const int32_t* const* pq, void* const* w_dev, int use_graph) {
+                   const int32_t* const* pq, void* const* w_dev, int mode) {
   if (n_sys < 1 || !sys || !n_pairs || !pq || !w_dev) fail(BSE_ERR_ARG, "bse_apply_W_batch: null argument");
+  if (mode < 0 || mode > 3) fail(BSE_ERR_ARG, "bse_apply_W_batch: mode must be 0..3");
+  const bool use_graph = (mode & 1) != 0, list = (mode & 2) != 0;
   int dev = -1;
   for (int i = 0; i < n_sys; ++i) {
     bse_system* s = sys[i];
@@ -1340,6 +1523,7 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
       if (pq[i][2 * k] < 0 || pq[i][2 * k] >= s->n_orb || pq[i][2 * k + 1] < 0 || pq[i][2 * k + 1] >= s->n_orb)
         fail(BSE_ERR_ARG, "pair index out of range");
   }
+  if (list) batch_list_check(n_sys, sys);
   HIPC(hipSetDevice(dev));
   std::vector<hipStream_t> saved(n_sys);
   std::vector<char> timer_was(n_sys, 0);
@@ -1379,14 +1563,17 @@ void apply_w_batch(int n_sys, bse_system* const* sys, const int32_t* n_pairs,
       if (s->cfg.precision == BSE_FP64) ensure_batch<double>(s, n_pairs[i]);
       else ensure_batch<float>(s, n_pairs[i]);
       HIPC(hipMemcpyAsync(s->pq_d.p, pq[i], sizeof(int) * 2 * n_pairs[i], hipMemcpyHostToDevice, s->own_stream));
-      s->stream = s->own_stream;
+      s->stream = list ? origin : s->own_stream;
       s->timer.on = false;
     }
     // the pair lists are on the device before the captured work reads them
     for (int i = 0; i < n_sys; ++i) HIPC(hipStreamSynchronize(sys[i]->own_stream));
+    BatchList bl;
+    if (list) batch_list_build(n_sys, sys, n_pairs, bl);
     if (use_graph) HIPC(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
     HIPC(hipEventRecord(ev[n_sys], origin));
-    for (int i = 0; i < n_sys; ++i) {
+    if (list) batch_list_run(n_sys, sys, n_pairs, w_dev, bl, origin);
+    for (int i = 0; i < n_sys && !list; ++i) {
       bse_system* s = sys[i];
       HIPC(hipStreamWaitEvent(s->stream, ev[n_sys], 0));
       const int B = n_pairs[i];
@@ -2139,9 +2326,9 @@ int32_t bse_tuned_shape(bse_system* s, int32_t* tc, int32_t* nt) {
 }
 
 bse_status bse_apply_W_batch(int32_t n_sys, bse_system* const* systems, const int32_t* n_pairs,
-                             const int32_t* const* pq, void* const* w_dev, int32_t use_graph) {
+                             const int32_t* const* pq, void* const* w_dev, int32_t mode) {
   API_BEGIN
-  apply_w_batch(n_sys, systems, n_pairs, pq, w_dev, use_graph);
+  apply_w_batch(n_sys, systems, n_pairs, pq, w_dev, mode);
   API_END
 }
 

@@ -99,6 +99,27 @@ template <typename T> hipError_t launch_prop_x(int n, const PropXArgs<T>& a, int
 template <typename T> hipError_t launch_prop_yz(int n, const PropYZArgs<T>& a, int nb, hipStream_t st, int nt = 0,
                                                 const LaunchEvents* ev = nullptr,
                                                 const LaunchEvents* ev2 = nullptr);
+// Work lists of uneven batches (FP32): one launch of a propagation pass walks
+// the items of every listed system of one grid size, (pair, x tile) for the
+// x pass and (x plane, pair) for the plane pass, systems in order with
+// first = the number of items before them in the list.  Grids whose plane
+// pass is the LDS plane kernel (prop_list_grid); each item is computed as by
+// the per-system pass.
+struct XListSys {
+  PropXArgs<float> a;   // the pair pass of this system (mode PX_FULL or PX_HALF, nf = pairs)
+  unsigned first;
+};
+struct YZListSys {
+  PropYZArgs<float> a;  // the pair pass with the density (nf = pairs)
+  unsigned first;
+};
+bool prop_list_grid(int n);
+// items of one system: pairs x tiles, planes x pairs
+unsigned prop_x_list_items(int n, int pairs);
+unsigned prop_yz_list_items(int n, int pairs);
+// list: device array of nsys entries of grid size n, total = all their items
+hipError_t launch_prop_x_list(int n, const XListSys* list, int nsys, unsigned total, hipStream_t st);
+hipError_t launch_prop_yz_list(int n, const YZListSys* list, int nsys, unsigned total, hipStream_t st);
 template <typename T> bool prop_yz_split(int n);
 // grids where the y and z factors can run as one register-line plane pass
 template <typename T> bool prop_yz_fused(int n);

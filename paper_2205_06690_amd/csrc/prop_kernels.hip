@@ -15,6 +15,7 @@
 #include "prop_kernels.h"
 #include "clean_mfma.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace bse {
@@ -86,20 +87,17 @@ inline dim3 field_tile_grid(int order, int nf, int ntile) {
   return dim3(8 * ((n + 7) / 8));
 }
 
+// One (field or pair fb, tile of TC columns) of the x pass, by a block of
+// 256 threads on LDS s (x_lds bytes); shared by the per-system kernel and the
+// work-list kernel of uneven batches.
 template <int N, int TC, typename T, bool ETA>
-__global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
+__device__ __forceinline__ void prop_x_item(const PropXArgs<T>& a, int fb, int tile, cplx<T>* s) {
   using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int NTH = 256;
   constexpr int N1 = Fac<N>::N1, N2 = Fac<N>::N2;
   constexpr int IT = TC * N2 / NTH;
   static_assert(TC * N2 % NTH == 0, "work items must fill the block");
   const size_t ng = (size_t)N * N * N;
-  // the blocks of one tile run close together and share its H and phase
-  // tiles in L2 (field_tile)
-  int fb, tile;
-  if (!field_tile(a.order, a.nf, N * N / TC, fb, tile)) return;
   const int c0 = tile * TC;
   const int tid = threadIdx.x;
   C* tws = s + N * TC;
@@ -211,6 +209,16 @@ __global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
   }
 }
 
+template <int N, int TC, typename T, bool ETA>
+__global__ void __launch_bounds__(256) k_prop_x(PropXArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  // the blocks of one tile run close together and share its H and phase
+  // tiles in L2 (field_tile)
+  int fb, tile;
+  if (!field_tile(a.order, a.nf, N * N / TC, fb, tile)) return;
+  prop_x_item<N, TC, T, ETA>(a, fb, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
 // ---------------------------------------------------------------------------
 // prop_yz: y and z factors of exp(-iT dt) on a whole y-z plane, plus the
 // induced density dn_b = 4 sum_l Re(conj(H_l) d_{b,l}) of the post-kinetic
@@ -246,32 +254,21 @@ __device__ __forceinline__ void kinetic_yz_plane(cplx<T>* s, const cplx<T>* __re
   __syncthreads();
 }
 
-template <int N, typename T, int NT, bool DENS>
-__global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
+// One (plane x, pair b) of the pair variant of the plane pass: the L
+// orbitals of the pair with the next one's loads in flight, and the induced
+// density of the pair; a block of NT threads on LDS s (yz_lds bytes).
+// Shared by the per-system kernel and the work-list kernel.
+template <int N, typename T, int NT>
+__device__ __forceinline__ void prop_yz_pair_item(const PropYZArgs<T>& a, int x, int b, cplx<T>* s) {
   using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C* s = reinterpret_cast<C*>(smem_raw);
   constexpr int P = N * N;
   constexpr int PER = (P + NT - 1) / NT;
   constexpr bool PREF_H = PER <= 8;
   const int ng = N * N * N;
-  // grid: (x planes, fields or pairs) with the plane fastest: blocks running
-  // together stream consecutive planes of one field (measured faster than
-  // sharing the H planes across pairs, which the x pass gains from)
-  const int x = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t poff = (size_t)x * P;
   C* tws = s + N * plane_stride<N>();
   stage_tables<N>(tws, a.tw, a.kph, tid, NT);
-  if (!DENS) {
-    C* d = a.d + (size_t)blockIdx.y * ng + poff;
-    for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = d[e];
-    __syncthreads();
-    kinetic_yz_plane<N, T, NT>(s, tws, tws + N, tid);
-    for (int e = tid; e < P; e += NT) d[e] = s[plane_idx<N>(e)];
-    return;
-  }
-  const int b = blockIdx.y;
   T acc[PER];
   C dn[PER];
 #pragma unroll
@@ -325,6 +322,32 @@ __global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
     const int e = tid + i * NT;
     if (e < P) dn_out[e] = (T)4 * acc[i];
   }
+}
+
+template <int N, typename T, int NT, bool DENS>
+__global__ void __launch_bounds__(NT) k_prop_yz(PropYZArgs<T> a) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  // grid: (x planes, fields or pairs) with the plane fastest: blocks running
+  // together stream consecutive planes of one field (measured faster than
+  // sharing the H planes across pairs, which the x pass gains from)
+  if (DENS) {
+    prop_yz_pair_item<N, T, NT>(a, blockIdx.x, blockIdx.y, s);
+    return;
+  }
+  constexpr int P = N * N;
+  const int ng = N * N * N;
+  const int x = blockIdx.x;
+  const int tid = threadIdx.x;
+  const size_t poff = (size_t)x * P;
+  C* tws = s + N * plane_stride<N>();
+  stage_tables<N>(tws, a.tw, a.kph, tid, NT);
+  C* d = a.d + (size_t)blockIdx.y * ng + poff;
+  for (int e = tid; e < P; e += NT) s[plane_idx<N>(e)] = d[e];
+  __syncthreads();
+  kinetic_yz_plane<N, T, NT>(s, tws, tws + N, tid);
+  for (int e = tid; e < P; e += NT) d[e] = s[plane_idx<N>(e)];
 }
 
 // ---------------------------------------------------------------------------
@@ -1493,6 +1516,130 @@ template <int N, int TC, typename T> constexpr size_t x_lds() {
 }
 template <int N, typename T> constexpr size_t yz_lds() {
   return sizeof(cplx<T>) * ((size_t)N * plane_stride<N>() + 2 * N);
+}
+
+// ---------------------------------------------------------------------------
+// Work-list passes of uneven batches: for one grid size, a persistent grid
+// (as many blocks as the CUs hold) walks the items of every listed system,
+// each with its own pairs and buffers.  An item computes exactly what the
+// per-system kernel computes for it (the tile shape changes only which
+// thread does what), so results equal the per-system passes bit for bit.
+// One instantiation per grid size keeps each one's registers those of its
+// per-system kernel.
+// ---------------------------------------------------------------------------
+// The items of a persistent list launch: workgroup ids are dealt
+// round-robin to the eight XCDs, so XCD c = id mod 8 takes the c-th eighth of
+// the items, walked by its own workgroups in order; consecutive items (the
+// fields of one tile, the planes of one pair) then share that XCD's L2.  The
+// grid is a multiple of 8.  Within a workgroup the items only grow, so its
+// entry index only moves forward.
+struct ListWalk {
+  unsigned it, hi, step;
+  __device__ ListWalk(unsigned total) {
+    const unsigned c = blockIdx.x & 7u, per = (total + 7u) / 8u;
+    step = gridDim.x >> 3;
+    it = c * per + (blockIdx.x >> 3);
+    hi = min(total, c * per + per);
+  }
+};
+template <typename E>
+__device__ __forceinline__ int list_advance(const E* __restrict__ list, int nsys, int k, unsigned it) {
+  while (k + 1 < nsys && list[k + 1].first <= it) ++k;
+  return k;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_prop_x_list(const XListSys* __restrict__ list, int nsys, unsigned total) {
+  extern __shared__ unsigned char smem_raw[];
+  float2* s = reinterpret_cast<float2*>(smem_raw);
+  int k = 0;
+  for (ListWalk w(total); w.it < w.hi; w.it += w.step) {
+    k = list_advance(list, nsys, k, w.it);
+    const XListSys e = list[k];
+    const unsigned loc = w.it - e.first;
+    prop_x_item<N, x_tc<N>(), float, false>(e.a, (int)(loc % (unsigned)e.a.nf), (int)(loc / (unsigned)e.a.nf), s);
+    __syncthreads();   // the next item restages the tables and the tile
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(yz_threads<N>()) k_prop_yz_list(const YZListSys* __restrict__ list, int nsys,
+                                                                 unsigned total) {
+  extern __shared__ unsigned char smem_raw[];
+  float2* s = reinterpret_cast<float2*>(smem_raw);
+  int k = 0;
+  for (ListWalk w(total); w.it < w.hi; w.it += w.step) {
+    k = list_advance(list, nsys, k, w.it);
+    const YZListSys e = list[k];
+    const unsigned loc = w.it - e.first;
+    prop_yz_pair_item<N, float, yz_threads<N>()>(e.a, (int)(loc % (unsigned)N), (int)(loc / (unsigned)N), s);
+    __syncthreads();
+  }
+}
+
+bool prop_list_grid(int n) { return n == 16 || n == 24 || n == 32 || n == 48 || n == 64; }
+unsigned prop_x_list_items(int n, int pairs) {
+  const int tc = n <= 16 ? 64 : 32;   // x_tc
+  return (unsigned)pairs * (unsigned)(n * n / tc);
+}
+unsigned prop_yz_list_items(int n, int pairs) { return (unsigned)n * (unsigned)pairs; }
+
+// blocks of a persistent list launch: what the CUs hold at once, a multiple
+// of the 8 XCDs
+static hipError_t list_grid(const void* k, int block, size_t lds, unsigned total, unsigned* grid) {
+  int dev = 0, ncu = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds);
+  if (e != hipSuccess) return e;
+  const unsigned g = std::min((total + 7u) / 8u * 8u, (unsigned)(std::max(1, per) * ncu));
+  *grid = std::max(8u, g / 8u * 8u);
+  return hipSuccess;
+}
+
+template <int N>
+static hipError_t prop_list_go(const XListSys* xl, const YZListSys* yl, int nsys, unsigned total, hipStream_t st) {
+  const void* k;
+  int block;
+  size_t lds;
+  if (xl) {
+    k = (const void*)k_prop_x_list<N>;
+    block = 256;
+    lds = x_lds<N, x_tc<N>(), float>();
+  } else {
+    k = (const void*)k_prop_yz_list<N>;
+    block = yz_threads<N>();
+    lds = yz_lds<N, float>();
+  }
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  unsigned g = 0;
+  if (e == hipSuccess) e = list_grid(k, block, lds, total, &g);
+  if (e != hipSuccess) return e;
+  if (xl)
+    hipLaunchKernelGGL(k_prop_x_list<N>, dim3(g), dim3(256), lds, st, xl, nsys, total);
+  else
+    hipLaunchKernelGGL(k_prop_yz_list<N>, dim3(g), dim3(yz_threads<N>()), lds, st, yl, nsys, total);
+  return hipGetLastError();
+}
+
+static hipError_t prop_list(int n, const XListSys* xl, const YZListSys* yl, int nsys, unsigned total,
+                            hipStream_t st) {
+  if (nsys < 1 || total == 0) return hipErrorInvalidValue;
+  switch (n) {
+    case 16: return prop_list_go<16>(xl, yl, nsys, total, st);
+    case 24: return prop_list_go<24>(xl, yl, nsys, total, st);
+    case 32: return prop_list_go<32>(xl, yl, nsys, total, st);
+    case 48: return prop_list_go<48>(xl, yl, nsys, total, st);
+    case 64: return prop_list_go<64>(xl, yl, nsys, total, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_prop_x_list(int n, const XListSys* list, int nsys, unsigned total, hipStream_t st) {
+  return prop_list(n, list, nullptr, nsys, total, st);
+}
+hipError_t launch_prop_yz_list(int n, const YZListSys* list, int nsys, unsigned total, hipStream_t st) {
+  return prop_list(n, nullptr, list, nsys, total, st);
 }
 
 template <int N, typename T>

@@ -21,8 +21,10 @@ def _systems():
     return specs, pair_lists
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_individual(use_graph):
+@pytest.mark.parametrize("use_graph,work_list", [(True, False), (False, False), (False, True), (True, True)])
+def test_batch_equals_individual(use_graph, work_list):
+    """Every schedule (own streams or the lockstep work list, captured or
+    not) equals the per-system calls bit for bit."""
     import torch
     from paper_2205_06690_amd import bse
     specs, pair_lists = _systems()
@@ -32,8 +34,9 @@ def test_batch_equals_individual(use_graph):
     ref = [s.apply_w(p) for s, p in zip(systems, pair_lists)]
     outs = [torch.zeros((len(p), sp.ng), dtype=torch.float64, device="cuda")
             for sp, p in zip(specs, pair_lists)]
-    say("batch of", len(systems), "systems, graph", use_graph)
-    bse.apply_w_batch(systems, pair_lists, [o.data_ptr() for o in outs], use_graph=use_graph)
+    say("batch of", len(systems), "systems, graph", use_graph, "work list", work_list)
+    bse.apply_w_batch(systems, pair_lists, [o.data_ptr() for o in outs], use_graph=use_graph,
+                      work_list=work_list)
     torch.cuda.synchronize()
     for k, (o, r) in enumerate(zip(outs, ref)):
         got = o.cpu().numpy()
@@ -70,6 +73,22 @@ def test_batch_argument_errors():
     s = gpu_system(specs[0], sd, bse.BSE_MIXED, max_batch=2)
     with pytest.raises(bse.BseError) as e:
         bse.apply_w_batch([s], [pair_lists[0]], [0])      # 3 pairs > max_batch 2
+    assert e.value.code == bse.BSE_ERR_ARG
+
+    # the work-list schedule: mixed precision, one number of steps
+    import dataclasses
+    import torch
+    out = torch.zeros((1, specs[0].ng), dtype=torch.float64, device="cuda")
+    s64 = gpu_system(specs[0], sd, bse.BSE_FP64, max_batch=1)
+    with pytest.raises(bse.BseError) as e:
+        bse.apply_w_batch([s64], [pair_lists[2]], [out.data_ptr()], work_list=True)
+    assert e.value.code == bse.BSE_ERR_ARG
+    sp2 = dataclasses.replace(specs[0], n_steps=30)
+    s2 = gpu_system(sp2, sd, bse.BSE_MIXED, max_batch=1)
+    out2 = torch.zeros((1, specs[0].ng), dtype=torch.float64, device="cuda")
+    with pytest.raises(bse.BseError) as e:
+        bse.apply_w_batch([s, s2], [pair_lists[2], pair_lists[2]], [out.data_ptr(), out2.data_ptr()],
+                          work_list=True)
     assert e.value.code == bse.BSE_ERR_ARG
 
 
