@@ -349,13 +349,21 @@ bse_status bse_batch_plan_create(int32_t n_sys, bse_system* const* systems, cons
 bse_status bse_batch_plan_run(bse_batch_plan* plan);
 void bse_batch_plan_destroy(bse_batch_plan* plan);
 
-/* Autotuner: times the tile-shape variants of the two propagation passes
- * for this system's grid, precision and a batch of n_pairs pairs and keeps
- * the fastest for later calls.  cache_path (nullable) is a text file of
- * "key tc nt ms_x ms_yz" lines: a matching key is used without timing, a new
- * result is appended.  Overwrites the system's pair workspace. */
+/* Autotuner: times the variants of the two propagation passes for this
+ * system's grid, precision and a batch of n_pairs pairs and keeps the
+ * fastest for later calls: the x pass's tile width (16, 32, 64) and
+ * workgroup order (bse_set_launch_order bit 0); the plane pass's block size
+ * (256, 512), or where the y and z factors run as one register-line pass
+ * (112^3 in mixed precision, unless bse_set_yz_schedule chose the line
+ * passes) its 16-point DFT schedule (2 or 0) and workgroup order (bit 2).
+ * The tile shapes and orders do not change results; the two DFT schedules
+ * agree to FP32 rounding.  cache_path (nullable) is a text
+ * file of "key tc nt ms_x ms_yz ox sched oz" lines (sched -1 where not
+ * tuned): a matching key is used without timing, a new result is appended.
+ * Overwrites the system's pair workspace. */
 bse_status bse_autotune(bse_system* sys, int32_t n_pairs, const char* cache_path);
-/* The tuned x-tile width and plane-pass block size (0 = built-in default). */
+/* The tuned x-tile width and plane-pass block size (0 = built-in default,
+ * or not used by the one-pass y-z kernel). */
 int32_t bse_tuned_shape(bse_system* sys, int32_t* tc, int32_t* nt);
 
 /* Stream for all later device work of this system (a hipStream_t). */

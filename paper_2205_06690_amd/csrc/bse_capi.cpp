@@ -1336,16 +1336,30 @@ void autotune_t(bse_system* s, int B, const char* cache_path) {
   using C = cplx<T>;
   char key[128];
   std::snprintf(key, sizeof(key), "n%d_%s_B%d_L%d", s->n, sizeof(T) == 4 ? "f32" : "f64", B, s->L);
+  // the choices a result sets: the x tile, the plane block size (0 where
+  // the y-z factors run as one register-line pass), the x pass's workgroup
+  // order, and for the one-pass y-z kernel its 16-point DFT schedule and order
+  auto apply = [&](int tc, int nt, int ox, int sched, int oz) {
+    s->tune_tc = tc;
+    s->tune_nt = nt;
+    s->launch_order = (s->launch_order & ~1) | (ox & 1);
+    if (sched >= 0) {
+      s->yz_schedule = sched;
+      s->launch_order = (s->launch_order & ~4) | ((oz & 1) << 2);
+    }
+  };
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       std::istringstream is(line);
       std::string k;
-      int tc = 0, nt = 0;
+      int tc = 0, nt = 0, ox = s->launch_order & 1, sched = -1, oz = 0;
+      float mx = 0, myz = 0;
       if (is >> k >> tc >> nt && k == key) {
-        s->tune_tc = tc;
-        s->tune_nt = nt;
+        // lines written before the orders were tuned end after the times
+        if (is >> mx >> myz >> ox) is >> sched >> oz;
+        apply(tc, nt, ox, sched, oz);
         return;
       }
     }
@@ -1354,42 +1368,38 @@ void autotune_t(bse_system* s, int B, const char* cache_path) {
   Tables& tb = tabs<T>(s);
   HIPC(launch_fill_zero(s->d.p, sizeof(C) * s->ng * (size_t)B * s->L, s->stream));
   HIPC(launch_fill_zero(s->u.p, sizeof(T) * s->ng * (size_t)B, s->stream));
-  PropXArgs<T> px{};
-  px.din = s->d.as<C>();
-  px.dout = s->d.as<C>();
-  px.pf = tb.pf.as<C>();
-  px.ph = tb.ph.as<C>();
-  px.u = s->u.as<T>();
-  px.H = s->h0.as<C>();
-  px.tw = tb.tw.as<C>();
-  px.kph = tb.kph.as<C>();
-  px.dt = (T)s->cfg.dt;
-  px.L = s->L;
-  px.mode = PX_FULL;
-  PropYZArgs<T> pz{};
-  pz.d = s->d.as<C>();
-  pz.H = s->h0.as<C>();
-  pz.tw = tb.tw.as<C>();
-  pz.kph = tb.kph.as<C>();
-  pz.dens = s->dens.as<T>();
-  pz.L = s->L;
-  pz.density = 1;
+  PropXArgs<T> px = prop_pair_x_args<T>(s, s->h0.as<C>(), false);
+  PropYZArgs<T> pz = prop_pair_yz_args<T>(s, s->h0.as<C>());
   float best_x = 1e30f, best_yz = 1e30f;
-  int tc_best = 0, nt_best = 0;
-  for (int tc : {16, 32, 64}) {
-    const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_x<T>(s->n, px, B, s->stream, tc); });
-    if (ms > 0 && ms < best_x) { best_x = ms; tc_best = tc; }
+  int tc_best = 0, nt_best = 0, ox_best = 0, sched_best = -1, oz_best = 0;
+  for (int ox : {0, 1})
+    for (int tc : {16, 32, 64}) {
+      px.order = ox;
+      const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_x<T>(s->n, px, B, s->stream, tc); });
+      if (ms > 0 && ms < best_x) { best_x = ms; tc_best = tc; ox_best = ox; }
+    }
+  if (s->yz_schedule != 1 && prop_yz_fused<T>(s->n)) {
+    for (int sched : {2, 0})
+      for (int oz : {0, 1}) {
+        pz.fused = sched == 2 ? 2 : 1;
+        pz.order = oz;
+        const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_yz<T>(s->n, pz, B, s->stream, 0); });
+        if (ms > 0 && ms < best_yz) { best_yz = ms; sched_best = sched; oz_best = oz; }
+      }
+    if (sched_best < 0) fail(BSE_ERR_DEVICE, "autotune: no valid variant");
+  } else {
+    for (int nt : {256, 512}) {
+      const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_yz<T>(s->n, pz, B, s->stream, nt); });
+      if (ms > 0 && ms < best_yz) { best_yz = ms; nt_best = nt; }
+    }
+    if (nt_best == 0) fail(BSE_ERR_DEVICE, "autotune: no valid variant");
   }
-  for (int nt : {256, 512}) {
-    const float ms = time_launches<T>(s, 5, [&]() { return launch_prop_yz<T>(s->n, pz, B, s->stream, nt); });
-    if (ms > 0 && ms < best_yz) { best_yz = ms; nt_best = nt; }
-  }
-  if (tc_best == 0 || nt_best == 0) fail(BSE_ERR_DEVICE, "autotune: no valid variant");
-  s->tune_tc = tc_best;
-  s->tune_nt = nt_best;
+  if (tc_best == 0) fail(BSE_ERR_DEVICE, "autotune: no valid variant");
+  apply(tc_best, nt_best, ox_best, sched_best, oz_best);
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key << " " << tc_best << " " << nt_best << " " << best_x << " " << best_yz << "\n";
+    out << key << " " << tc_best << " " << nt_best << " " << best_x << " " << best_yz << " " << ox_best << " "
+        << sched_best << " " << oz_best << "\n";
   }
 }
 

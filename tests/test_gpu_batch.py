@@ -64,6 +64,11 @@ def test_autotune_keeps_results(tmp_path):
     s2 = gpu_system(sp, sd, bse.BSE_MIXED, max_batch=len(p))
     assert s2.autotune(len(p), cache) == (tc, nt)
     assert open(cache).read().count("\n") == 1
+    # key, tile, block, two times, then the x order and (not tuned on this
+    # grid: the plane kernel) the y-z schedule and its order
+    fields = open(cache).read().split()
+    assert len(fields) == 8 and fields[5] in ("0", "1") and fields[6] == "-1"
+    assert np.array_equal(s2.apply_w(p), before)
 
 
 def test_batch_argument_errors():

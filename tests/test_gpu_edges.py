@@ -150,3 +150,26 @@ def test_fused_yz_pass_equals_line_passes():
         e = rel(res[sched], res[1]).max()
         say(f"one-pass schedule {sched} vs line passes, 21 pairs x 60 steps: max rel W {e:.2e}")
         assert e < 2e-5
+
+@pytest.mark.timeout(300)
+def test_autotune_at_the_paper_grid(tmp_path):
+    """At 112^3 in mixed precision the autotuner also picks the one-pass y-z
+    kernel's DFT schedule and workgroup order: W over 20 steps stays within
+    FP32 rounding of the untuned run (the schedules round differently)."""
+    import dataclasses
+    from paper_2205_06690_amd import bse, inputs
+    spec = dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=20)
+    sysd = inputs.make_system(spec)
+    pairs = inputs.ij_pairs(spec)[-3:]
+    s = gpu_system(spec, sysd, bse.BSE_MIXED, max_batch=len(pairs))
+    before = s.apply_w(pairs)
+    cache = str(tmp_path / "tune112.txt")
+    tc, nt = s.autotune(len(pairs), cache)
+    fields = open(cache).read().split()
+    say(f"112^3 autotune: x tile {tc}, x order {fields[5]}, y-z schedule {fields[6]}, y-z order {fields[7]}")
+    assert tc in (16, 32, 64) and nt == 0 and fields[6] in ("0", "2") and fields[7] in ("0", "1")
+    after = s.apply_w(pairs)
+    e = rel(after, before).max()
+    say(f"112^3 autotuned vs default: max rel W {e:.2e}")
+    assert e < 2e-5
+    s.close()
