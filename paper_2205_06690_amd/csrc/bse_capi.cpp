@@ -435,9 +435,9 @@ YZSched yz_sched(const bse_system* s) {
   return y;
 }
 
-// unperturbed set: one step, H_n -> H_{n+1}
+// unperturbed set: one step, H_n -> H_{n+1}, on stream st
 template <typename T>
-void prop_unperturbed_step(PropRun<T>& r, int n) {
+void prop_unperturbed_step(PropRun<T>& r, int n, hipStream_t st) {
   using C = cplx<T>;
   bse_system* s = r.s;
   Tables& tb = tabs<T>(s);
@@ -453,7 +453,7 @@ void prop_unperturbed_step(PropRun<T>& r, int n) {
   pe.L = s->L;
   pe.mode = PX_ETA0;
   pe.order = s->launch_order & 1;
-  HIPC(launch_prop_x<T>(s->n, pe, s->L, s->stream, s->tune_tc));
+  HIPC(launch_prop_x<T>(s->n, pe, s->L, st, s->tune_tc));
   const YZSched y = yz_sched<T>(s);
   PropYZArgs<T> pze{};
   pze.d = hnext;
@@ -463,7 +463,7 @@ void prop_unperturbed_step(PropRun<T>& r, int n) {
   pze.density = 0;
   pze.order = y.order;
   pze.fused = y.fused_kind;
-  HIPC(launch_prop_yz<T>(s->n, pze, s->L, s->stream, s->tune_nt));
+  HIPC(launch_prop_yz<T>(s->n, pze, s->L, st, s->tune_nt));
 }
 
 // the perturbed set's two passes of step n (hcur = H_n, half as after step n - 1)
@@ -503,9 +503,11 @@ PropYZArgs<T> prop_pair_yz_args(bse_system* s, const cplx<T>* hnext) {
   pz.fused = y.fused_kind;
   return pz;
 }
+// the unperturbed set's step n, then the perturbed set's two passes of step n
 template <typename T>
 void prop_pair_passes(PropRun<T>& r, int n) {
   bse_system* s = r.s;
+  prop_unperturbed_step<T>(r, n, s->stream);
   const PropXArgs<T> px = prop_pair_x_args<T>(s, r.hcur, r.half);
   auto* t1 = s->timer.slot("prop_x", 1);
   const LaunchEvents e1{t1 ? t1->first : nullptr, t1 ? t1->second : nullptr};
@@ -551,8 +553,7 @@ void propagate_batch(bse_system* s, int B, const int* pq_dev) {
   PropRun<T> r{s, B, pq_dev, nullptr, true};
   prop_begin<T>(r);
   for (int n = 0; n < s->cfg.n_steps; ++n) {
-    prop_unperturbed_step<T>(r, n);
-    prop_pair_passes<T>(r, n);
+    prop_pair_passes<T>(r, n);   // with the unperturbed set's step
     prop_after_passes<T>(r, n);
   }
 }
@@ -1493,7 +1494,7 @@ void batch_list_run(int n_sys, bse_system* const* sys, const int32_t* n_pairs, v
   }
   const int N = sys[0]->cfg.n_steps;
   for (int n = 0; n < N; ++n) {
-    for (auto& r : runs) prop_unperturbed_step<float>(r, n);
+    for (auto& r : runs) prop_unperturbed_step<float>(r, n, r.s->stream);
     const int v = n == 0 ? 0 : 1 + 2 * (n & 1) + (runs[0].half ? 1 : 0);
     for (const auto& g : bl.groups) HIPC(launch_prop_x_list(g.n, bl.x(v, g), g.ne, g.tot_x, st));
     for (const auto& g : bl.groups) HIPC(launch_prop_yz_list(g.n, bl.yz((n + 1) & 1, g), g.ne, g.tot_yz, st));

@@ -200,3 +200,32 @@ def test_plan_replays_equal_the_batch_call():
         plan.run()
     assert e.value.code == bse.BSE_ERR_STATE
     plan.close()
+
+
+@pytest.mark.skip(reason="creating this plan segfaulted on the host inside bse_batch_plan_create while "
+                         "capturing a 112^3 propagation that ran the unperturbed set's step on a second stream "
+                         "(fork and join events recorded again every step); that overlap was removed, the cause "
+                         "was not found, and the plan has not been captured at 112^3 since")
+@pytest.mark.timeout(300)
+def test_plan_at_the_paper_grid():
+    """A plan captured at 112^3 replays equal to the eager call bit for bit."""
+    import dataclasses
+    import torch
+    from paper_2205_06690_amd import bse
+    spec = dataclasses.replace(inputs.CONFIGS["paper112"], n_steps=20)
+    sysd = inputs.make_system(spec)
+    pairs = inputs.ij_pairs(spec)[-2:]
+    s = gpu_system(spec, sysd, bse.BSE_MIXED, max_batch=len(pairs))
+    ref = s.apply_w(pairs)
+    out = torch.zeros((len(pairs), spec.ng), dtype=torch.float64, device="cuda")
+    plan = bse.BatchPlan([s], [pairs], [out.data_ptr()])
+    for rep in range(2):
+        out.zero_()
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        say(f"112^3 plan replay {rep}: max|diff| {np.abs(got - ref).max():.1e}")
+        assert np.array_equal(got, ref)
+    plan.close()
+    s.close()
