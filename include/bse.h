@@ -477,6 +477,18 @@ bse_status bse_fno_loss_grad(bse_fno* fno, int32_t B, const void* x_dev, const v
 /* One training step: loss, gradient, Adam update with learning rate lr. */
 bse_status bse_fno_train_step(bse_fno* fno, int32_t B, const void* x_dev, const void* t_dev,
                               double lr, double* loss);
+/* Training batch under a symmetry of the cube (the Hamiltonian of a box and
+ * the Coulomb kernel commute with the cube's rotations and reflections, so
+ * a mapped sample has the mapped target): x_dst[b] = x_src[idx[b]] and
+ * t_dst[b] = t_src[idx[b]] (x [.][cin][n^3], t [.][n^3], FP32, device,
+ * points z fastest) with output axis k taken from input axis perm[k] and
+ * the output axes in flip_mask (bit k = axis k) reversed.  idx (host,
+ * B values in 0..n_src-1) and perm (host, a permutation of 0, 1, 2).
+ * Returns when done.  Errors: BSE_ERR_ARG for B outside 1..max_batch, a
+ * null pointer, an index out of range, a perm that is no permutation or a
+ * flip_mask outside 0..7. */
+bse_status bse_fno_gather(bse_fno* fno, int32_t B, const int32_t* idx, int32_t n_src, const void* x_src,
+                          const void* t_src, const int32_t* perm, int32_t flip_mask, void* x_dst, void* t_dst);
 const char* bse_fno_last_error(void);
 int32_t bse_fno_max_batch(const bse_fno* fno);
 void bse_fno_destroy(bse_fno* fno);

@@ -32,7 +32,7 @@ EXPORTS = (
     "bse_version", "bse_destroy_system", "bse_apply_W_batch", "bse_autotune",
     "bse_tuned_shape", "bse_fno_create", "bse_fno_num_params", "bse_fno_set_params",
     "bse_fno_get_params", "bse_fno_set_stream", "bse_fno_forward", "bse_fno_loss_grad",
-    "bse_fno_train_step", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
+    "bse_fno_train_step", "bse_fno_gather", "bse_fno_last_error", "bse_fno_destroy", "bse_fno_max_batch",
     "bse_fno_make_samples", "bse_apply_W_surrogate", "bse_chebyshev_spectrum",
     "bse_apply_A_mixed", "bse_chebyshev_mixed", "bse_exciton_states", "bse_exciton_states_mixed",
     "bse_boundary_potential", "bse_fit_box_correction", "bse_inject_fault", "bse_valence_W",
@@ -125,6 +125,7 @@ def _load():
     lib.bse_fno_forward.argtypes = [P, C.c_int32, P, P]
     lib.bse_fno_loss_grad.argtypes = [P, C.c_int32, P, P, dp, fp]
     lib.bse_fno_train_step.argtypes = [P, C.c_int32, P, P, C.c_double, dp]
+    lib.bse_fno_gather.argtypes = [P, C.c_int32, ip, C.c_int32, P, P, ip, C.c_int32, P, P]
     lib.bse_fno_last_error.restype = C.c_char_p
     lib.bse_fno_max_batch.argtypes = [P]
     lib.bse_fno_max_batch.restype = C.c_int32
@@ -509,6 +510,17 @@ class Fno:
         _fcheck(LIB.bse_fno_loss_grad(self._h, B, C.c_void_p(x_ptr), C.c_void_p(t_ptr), C.byref(loss),
                                       g.ctypes.data_as(C.POINTER(C.c_float)) if g is not None else None))
         return loss.value, g
+
+    def gather(self, idx, n_src: int, x_src_ptr: int, t_src_ptr: int, perm, flip_mask: int,
+               x_dst_ptr: int, t_dst_ptr: int):
+        """bse_fno_gather: samples idx of the source batch under a symmetry of
+        the cube (output axis k = input axis perm[k], axes in flip_mask
+        reversed) into the destination buffers."""
+        ix = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+        pm = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+        _fcheck(LIB.bse_fno_gather(self._h, int(ix.shape[0]), _iptr(ix), int(n_src), C.c_void_p(x_src_ptr),
+                                   C.c_void_p(t_src_ptr), _iptr(pm), int(flip_mask), C.c_void_p(x_dst_ptr),
+                                   C.c_void_p(t_dst_ptr)))
 
     def train_step(self, B: int, x_ptr: int, t_ptr: int, lr: float) -> float:
         loss = C.c_double()

@@ -68,6 +68,7 @@ struct bse_fno {
   int mix_path = 0;   // per-mode channel mix: 0 matrix cores, 1 vector FMA
   std::vector<Buf> h, z, V;
   Buf s, gh_a, gh_b, work, U, GU, GV, part, gy, y, loss_part, tn;
+  Buf gidx;   // sample indices of bse_fno_gather
 };
 
 namespace {
@@ -337,6 +338,31 @@ void bse_fno_destroy(bse_fno* f) {
   if (!f) return;
   (void)hipSetDevice(f->cfg.device);
   delete f;
+}
+
+bse_status bse_fno_gather(bse_fno* f, int32_t B, const int32_t* idx, int32_t n_src, const void* x_src,
+                          const void* t_src, const int32_t* perm, int32_t flip_mask, void* x_dst, void* t_dst) {
+  FAPI_BEGIN
+  check_batch(f, B);
+  if (!idx || !perm || !x_src || !t_src || !x_dst || !t_dst) ffail(BSE_ERR_ARG, "null argument");
+  for (int b = 0; b < B; ++b)
+    if (idx[b] < 0 || idx[b] >= n_src) ffail(BSE_ERR_ARG, "sample index outside 0..n_src-1");
+  bool seen[3] = {false, false, false};
+  for (int k = 0; k < 3; ++k) {
+    if (perm[k] < 0 || perm[k] > 2 || seen[perm[k]]) ffail(BSE_ERR_ARG, "perm is not a permutation of 0, 1, 2");
+    seen[perm[k]] = true;
+  }
+  if (flip_mask < 0 || flip_mask > 7) ffail(BSE_ERR_ARG, "flip_mask outside 0..7");
+  const int pm[3] = {perm[0], perm[1], perm[2]};
+  f->gidx.alloc(sizeof(int) * (size_t)f->cfg.max_batch);
+  FCK(hipMemcpyAsync(f->gidx.p, idx, sizeof(int) * B, hipMemcpyHostToDevice, f->stream));
+  const int n = f->cfg.n;
+  FCK(fno_gather_sym(reinterpret_cast<const float*>(x_src), reinterpret_cast<const int*>(f->gidx.p), B,
+                     f->cfg.cin, n, pm, flip_mask, reinterpret_cast<float*>(x_dst), f->stream));
+  FCK(fno_gather_sym(reinterpret_cast<const float*>(t_src), reinterpret_cast<const int*>(f->gidx.p), B, 1, n,
+                     pm, flip_mask, reinterpret_cast<float*>(t_dst), f->stream));
+  FCK(hipStreamSynchronize(f->stream));
+  FAPI_END
 }
 
 }  // extern "C"

@@ -36,4 +36,9 @@ hipError_t fno_loss_grad(const float* y, const float* t, const double* tn, int B
 hipError_t fno_adam(float* master, float* compute, const float* g, float* m, float* v, size_t n,
                     float lr, float b1, float b2, float eps, int step, int bf16, hipStream_t st);
 hipError_t fno_round_copy(const float* src, float* dst, size_t n, int bf16, hipStream_t st);
+// dst[b][c] = sample idx[b] of src[.][C][n^3] under a symmetry of the cube:
+// output axis k is input axis perm[k], and the output axes in flip_mask
+// (bit k) run backwards
+hipError_t fno_gather_sym(const float* src, const int* idx, int B, int C, int n, const int perm[3],
+                          int flip_mask, float* dst, hipStream_t st);
 }  // namespace bse

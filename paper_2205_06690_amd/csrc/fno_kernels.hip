@@ -808,4 +808,33 @@ hipError_t fno_round_copy(const float* src, float* dst, size_t n, int bf16, hipS
   return hipGetLastError();
 }
 
+// training batches under the symmetries of the cube: output point (o0, o1,
+// o2), after the flips o_k -> n - 1 - o_k, reads input point i with
+// i[perm[k]] = o_k
+__global__ void k_gather_sym(const float* __restrict__ src, const int* __restrict__ idx, int C, int n,
+                             int p0, int p1, int p2, int fmask, float* __restrict__ dst) {
+  const size_t ng = (size_t)n * n * n;
+  const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= ng) return;
+  const int c = blockIdx.y, b = blockIdx.z;
+  int oc[3] = {(int)(o / ((size_t)n * n)), (int)((o / n) % n), (int)(o % n)};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if ((fmask >> k) & 1) oc[k] = n - 1 - oc[k];
+  int ic[3];
+  ic[p0] = oc[0];
+  ic[p1] = oc[1];
+  ic[p2] = oc[2];
+  const size_t i = ((size_t)ic[0] * n + ic[1]) * n + ic[2];
+  dst[((size_t)b * C + c) * ng + o] = src[((size_t)idx[b] * C + c) * ng + i];
+}
+
+hipError_t fno_gather_sym(const float* src, const int* idx, int B, int C, int n, const int perm[3],
+                          int flip_mask, float* dst, hipStream_t st) {
+  const size_t ng = (size_t)n * n * n;
+  hipLaunchKernelGGL(k_gather_sym, dim3((unsigned)((ng + 255) / 256), C, B), dim3(256), 0, st, src, idx, C, n,
+                     perm[0], perm[1], perm[2], flip_mask, dst);
+  return hipGetLastError();
+}
+
 }  // namespace bse

@@ -89,28 +89,17 @@ def train(net: "bse.Fno", x, t, epochs: int, batch: int, lr: float, lr_end: floa
     hist = []
     k = 0
     t_start = time.perf_counter()
+    xb = torch.empty((batch,) + tuple(x.shape[1:]), dtype=x.dtype, device=x.device)
+    tb = torch.empty((batch,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
     for ep in range(epochs):
         perm = rng.permutation(n)
         losses = []
         for j in range(n // batch):
-            idx = torch.from_numpy(perm[j * batch:(j + 1) * batch]).cuda()
-            xb = x.index_select(0, idx)
-            tb = t.index_select(0, idx)
-            if augment:
-                # samples hold their grid flattened (z fastest): view it as n^3
-                perm_ax, flips = _cube_symmetry(rng)
-                xs, ts = xb.shape, tb.shape
-                ng = xs[-1]
-                m = int(round(ng ** (1.0 / 3.0)))
-                xb = xb.reshape(xs[0], xs[1], m, m, m).permute(0, 1, *(2 + a for a in perm_ax))
-                tb = tb.reshape(ts[0], m, m, m).permute(0, *(1 + a for a in perm_ax))
-                if flips:
-                    xb = xb.flip([2 + a for a in flips])
-                    tb = tb.flip([1 + a for a in flips])
-                xb = xb.reshape(xs)
-                tb = tb.reshape(ts)
-            xb = xb.contiguous()
-            tb = tb.contiguous()
+            # the batch's samples, under a random symmetry of the cube when
+            # augmenting, assembled by the library's gather kernel
+            sym_axes, flips = _cube_symmetry(rng) if augment else ((0, 1, 2), ())
+            net.gather(perm[j * batch:(j + 1) * batch], n, x.data_ptr(), t.data_ptr(), sym_axes,
+                       sum(1 << a for a in flips), xb.data_ptr(), tb.data_ptr())
             a = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * k / max(steps, 1)))
             losses.append(net.train_step(batch, xb.data_ptr(), tb.data_ptr(), a))
             k += 1

@@ -171,3 +171,36 @@ def test_matrix_core_mix_equals_vector_path(W, m, B):
     eg = np.linalg.norm(g0 - g1) / np.linalg.norm(g1)
     say(f"mix paths W={W} m={m} B={B}: rel|dy| {ey:.2e}, rel|dgrad| {eg:.2e}")
     assert ey < 1e-5 and eg < 1e-5 and abs(l0 - l1) < 1e-6 * abs(l1)
+
+
+def test_gather_under_cube_symmetries():
+    """The library's batch gather equals index_select, permute and flip of
+    the samples for symmetries of the cube (pure copies: bit for bit), and
+    rejects bad arguments."""
+    import torch
+    from paper_2205_06690_amd import bse
+    n, cin, B, n_src = 16, 3, 4, 7
+    net = bse.Fno(n, cin=cin, width=8, modes=4, layers=1, max_batch=B, seed=2)
+    g = torch.Generator().manual_seed(4)
+    x = torch.randn((n_src, cin, n ** 3), generator=g).cuda()
+    t = torch.randn((n_src, n ** 3), generator=g).cuda()
+    xd = torch.empty((B, cin, n ** 3), device="cuda")
+    td = torch.empty((B, n ** 3), device="cuda")
+    idx = [5, 0, 6, 2]
+    sel = torch.tensor(idx, device="cuda")
+    for perm, fm in [((0, 1, 2), 0), ((2, 0, 1), 5), ((1, 0, 2), 2), ((2, 1, 0), 7), ((0, 2, 1), 1)]:
+        net.gather(idx, n_src, x.data_ptr(), t.data_ptr(), perm, fm, xd.data_ptr(), td.data_ptr())
+        flips = [a for a in range(3) if (fm >> a) & 1]
+        xr = x.index_select(0, sel).reshape(B, cin, n, n, n).permute(0, 1, *(2 + a for a in perm))
+        tr = t.index_select(0, sel).reshape(B, n, n, n).permute(0, *(1 + a for a in perm))
+        if flips:
+            xr = xr.flip([2 + a for a in flips])
+            tr = tr.flip([1 + a for a in flips])
+        assert torch.equal(xd, xr.reshape(B, cin, -1)) and torch.equal(td, tr.reshape(B, -1)), (perm, fm)
+    say("gather: 5 symmetries equal to permute/flip")
+    for bad in [dict(idx=[0, 7, 1, 2]), dict(perm=(0, 0, 1)), dict(fm=8)]:
+        with pytest.raises(bse.BseError) as e:
+            net.gather(bad.get("idx", idx), n_src, x.data_ptr(), t.data_ptr(), bad.get("perm", (0, 1, 2)),
+                       bad.get("fm", 0), xd.data_ptr(), td.data_ptr())
+        assert e.value.code == bse.BSE_ERR_ARG
+    net.close()
