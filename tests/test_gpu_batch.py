@@ -47,6 +47,36 @@ def test_batch_equals_individual(use_graph, work_list):
     assert rel(outs[1].cpu().numpy(), w_o.reshape(len(pair_lists[1]), -1)).max() < 1e-3
 
 
+
+@pytest.mark.timeout(300)
+def test_work_list_on_the_uneven_grids():
+    """The lockstep work list on the grid sizes of the 32-molecule batch
+    (32^3, 48^3, 64^3; their own tile shapes and block sizes), two systems of
+    one size included, equals the per-system calls bit for bit."""
+    import torch
+    from paper_2205_06690_amd import bse
+    specs = [small_spec(n=32, h=0.4, wells=10, seed=1001, n_occ=8, n_steps=20),
+             small_spec(n=48, h=0.4, wells=12, seed=1002, n_occ=8, n_steps=20),
+             small_spec(n=64, h=0.4, wells=14, seed=1003, n_occ=8, n_steps=20),
+             small_spec(n=48, h=0.4, wells=9, seed=1004, n_occ=7, n_steps=20)]
+    pair_lists = [np.array([[6, 7], [7, 7], [5, 8]], dtype=np.int32),
+                  np.array([[7, 8], [6, 9]], dtype=np.int32),
+                  np.array([[7, 7], [6, 8], [5, 9], [7, 10]], dtype=np.int32),
+                  np.array([[6, 6]], dtype=np.int32)]
+    sysds = [inputs.make_system(sp) for sp in specs]
+    systems = [gpu_system(sp, sd, bse.BSE_MIXED, max_batch=len(p))
+               for sp, sd, p in zip(specs, sysds, pair_lists)]
+    ref = [s.apply_w(p) for s, p in zip(systems, pair_lists)]
+    outs = [torch.zeros((len(p), sp.ng), dtype=torch.float64, device="cuda")
+            for sp, p in zip(specs, pair_lists)]
+    bse.apply_w_batch(systems, pair_lists, [o.data_ptr() for o in outs], use_graph=False, work_list=True)
+    torch.cuda.synchronize()
+    for k, (o, r) in enumerate(zip(outs, ref)):
+        d = np.abs(o.cpu().numpy() - r).max()
+        say(f"work list, system {k} ({specs[k].n}^3): max|diff| {d:.1e}")
+        assert np.array_equal(o.cpu().numpy(), r)
+
+
 def test_autotune_keeps_results(tmp_path):
     from paper_2205_06690_amd import bse
     specs, pair_lists = _systems()
