@@ -1344,7 +1344,9 @@ void autotune_t(bse_system* s, int B, const char* cache_path) {
     s->tune_tc = tc;
     s->tune_nt = nt;
     s->launch_order = (s->launch_order & ~1) | (ox & 1);
-    if (sched >= 0) {
+    // a schedule is kept only where the one-pass y-z kernel runs (not after
+    // bse_set_yz_schedule chose the line passes)
+    if (sched >= 0 && s->yz_schedule != 1 && prop_yz_fused<T>(s->n)) {
       s->yz_schedule = sched;
       s->launch_order = (s->launch_order & ~4) | ((oz & 1) << 2);
     }
